@@ -1,0 +1,275 @@
+"""Pins of the CPU oracle against what the mathematics and the paper fix.
+
+Nothing here touches the GPU library.  Each test pins the oracle to
+something other than itself: closed forms, invariants, an independent
+pure-Python enumeration, the paper's printed expected solution count, or
+one oracle routine against a structurally different one (2^n walk vs
+counting DP vs heap Schroeppel-Shamir vs residue-class meet in the middle).
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2507_05045_amd.inputs import make_instance, random_small
+
+
+def py_enumerate(A, d):
+    """Independent tiny enumeration with itertools (n <= 14)."""
+    A = np.asarray(A, dtype=np.int64)
+    m, n = A.shape
+    S, hits = [], [0] * m
+    for bits in itertools.product((0, 1), repeat=n):
+        x = np.array(bits, dtype=np.int64)
+        s = A @ x
+        k = 0
+        while k < m and s[k] == d[k]:
+            k += 1
+        for i in range(k):
+            hits[i] += 1
+        if k == m:
+            S.append(bits)
+    return sorted(S), hits
+
+
+def sol_tuples(res):
+    return sorted(tuple(int(v) for v in r) for r in res.solutions)
+
+
+# --------------------------------------------------------------------------
+# Brute force (the definition) against an independent enumeration and
+# closed forms.
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(6))
+def test_brute_matches_itertools(seed):
+    rng = np.random.default_rng(100 + seed)
+    m, n = 3, 12
+    A = rng.integers(0, 6, size=(m, n)).astype(np.int32)
+    x = rng.integers(0, 2, size=n)
+    d = (A @ x).astype(np.int32)
+    S, hits = py_enumerate(A, d)
+    b = O.brute(A, d, key_rows=1)
+    assert sol_tuples(b) == S
+    assert [int(h) for h in b.hr] == hits
+    assert b.H == hits[0]
+
+
+def test_brute_equal_weights_binomial():
+    n, c, t = 20, 3, 7
+    A = np.full((1, n), c, dtype=np.int32)
+    b = O.brute(A, [c * t], key_rows=1)
+    assert b.H == math.comb(n, t) and b.nsol == math.comb(n, t)
+
+
+def test_brute_zero_row_and_zero_target():
+    n = 14
+    A = np.zeros((1, n), dtype=np.int32)
+    assert O.brute(A, [0]).H == 2 ** n
+    assert O.brute(A, [1]).H == 0
+    A2 = np.arange(1, n + 1, dtype=np.int32).reshape(1, n)
+    r = O.brute(A2, [0])
+    assert r.nsol == 1 and not r.solutions.any()
+
+
+def test_brute_target_above_row_sum_is_empty():
+    inst = make_instance(3, 16, 5)
+    d = inst.d.copy()
+    d[2] = int(inst.A[2].sum()) + 1
+    r = O.brute(inst.A, d, key_rows=1)
+    assert r.nsol == 0
+
+
+def test_paper_small_counterexample_all_six_pairs():
+    # n = 4, one variable per quarter, all weights 1, d = 2: S is every
+    # 2-subset.  Taking only the two heap tops on ties (Algorithm 1 read
+    # literally) loses cross pairs; the oracle must return all C(4,2) = 6.
+    A = np.ones((1, 4), dtype=np.int32)
+    for fn in (O.brute, O.ss_heap):
+        r = fn(A, [2], key_rows=1)
+        assert r.nsol == 6 and r.H == 6
+    assert O.mitm(A, [2], key_rows=1, log2_m=2).nsol == 6
+
+
+# --------------------------------------------------------------------------
+# Counting DPs.
+# --------------------------------------------------------------------------
+
+def test_dp_binomial_beyond_64_bits():
+    n = 90
+    assert O.dp_count(np.ones(n, dtype=np.int32), 45) == math.comb(90, 45)
+    assert math.comb(90, 45) > 2 ** 64
+    assert O.dp_count(np.full(n, 7, dtype=np.int32), 7 * 30) == math.comb(90, 30)
+
+
+def test_dp_zero_coefficients_double():
+    a = np.array([3, 0, 5, 0, 0, 2], dtype=np.int32)
+    assert O.dp_count(a, 5) == 2 * 2 ** 3   # {5}, {3,2}, times 2^3 zeros
+    assert O.dp_count(a, 0) == 2 ** 3
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_dp_matches_brute(seed):
+    inst = random_small(3, 18, seed)
+    b = O.brute(inst.A, inst.d, key_rows=1)
+    assert O.dp_count(inst.A[0], inst.d[0]) == b.hr[0]
+    assert O.dp_count2(inst.A[0], inst.A[1], inst.d[0], inst.d[1]) == b.hr[1]
+
+
+def test_dp_seed0_row1_counts():
+    # H for the (4,30) and (6,50) seed-0 instances with key row 1.
+    i4 = make_instance(4, 30, 0)
+    i6 = make_instance(6, 50, 0)
+    assert O.dp_count(i4.A[0], i4.d[0]) == 2_570_096
+    assert O.dp_count(i6.A[0], i6.d[0]) == 2_309_346_214_256
+
+
+# --------------------------------------------------------------------------
+# Heap Schroeppel-Shamir and residue meet-in-the-middle against brute force.
+# --------------------------------------------------------------------------
+
+CASES = [
+    dict(m=3, n=20, K=100, zero=0),
+    dict(m=4, n=21, K=100, zero=0),
+    dict(m=4, n=22, K=6, zero=0),     # heavy ties: many equal keys
+    dict(m=3, n=19, K=100, zero=3),   # zero columns must be enumerated
+    dict(m=5, n=17, K=3, zero=2),
+    dict(m=2, n=5, K=4, zero=0),      # tiny quarters
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("r", [1, 2, 3])
+def test_ss_and_mitm_match_brute(case, r):
+    r = min(r, case["m"])
+    for seed in range(2):
+        inst = random_small(case["m"], case["n"], 300 + seed, K=case["K"],
+                            zero_cols=case["zero"], planted=True)
+        b = O.brute(inst.A, inst.d, key_rows=r)
+        s = O.ss_heap(inst.A, inst.d, key_rows=r)
+        mm = O.mitm(inst.A, inst.d, key_rows=r, log2_m=6)
+        assert b.H == s.H == mm.H
+        assert b.H == b.hr[r - 1]
+        assert sol_tuples(b) == sol_tuples(s) == sol_tuples(mm)
+        assert tuple(int(v) for v in inst.planted) in set(sol_tuples(b))
+
+
+def test_single_column_and_empty_quarters():
+    for n in (1, 2, 3):
+        A = np.array([[2] * n, [1] * n], dtype=np.int32)
+        d = np.array([2, 1], dtype=np.int32)
+        b = O.brute(A, d, key_rows=1)
+        assert O.ss_heap(A, d, 1).nsol == b.nsol == n
+        assert O.mitm(A, d, 1, log2_m=3).nsol == n
+
+
+def test_complement_symmetry():
+    inst = random_small(4, 20, 9, planted=True)
+    rs = inst.A.astype(np.int64).sum(axis=1)
+    a = O.ss_heap(inst.A, inst.d, 2)
+    b = O.ss_heap(inst.A, (rs - inst.d).astype(np.int32), 2)
+    assert a.H == b.H
+    assert {tuple(1 - v for v in t) for t in sol_tuples(a)} == set(sol_tuples(b))
+
+
+def test_zero_columns_multiply():
+    base = random_small(3, 16, 4, planted=True)
+    z = 3
+    A = np.concatenate([base.A, np.zeros((3, z), dtype=np.int32)], axis=1)
+    a = O.ss_heap(base.A, base.d, 1)
+    b = O.ss_heap(A, base.d, 1)
+    assert b.H == a.H * 2 ** z and b.nsol == a.nsol * 2 ** z
+
+
+def test_infeasible_key_row_gives_no_hits():
+    inst = make_instance(3, 20, 2)
+    d = inst.d.copy()
+    d[1] = int(inst.A[1].sum()) + 5
+    for fn in (O.ss_heap, O.mitm):
+        r = fn(inst.A, d, 2)
+        assert r.H == 0 and r.nsol == 0
+    assert O.brute(inst.A, d, 2).H == 0
+
+
+def test_column_permutation_invariance():
+    inst = random_small(4, 20, 11, planted=True)
+    perm = np.random.default_rng(5).permutation(inst.A.shape[1])
+    a = O.ss_heap(inst.A, inst.d, 2)
+    b = O.ss_heap(inst.A[:, perm], inst.d, 2)
+    assert a.H == b.H
+    assert {t for t in sol_tuples(a)} == {tuple(t[np.argsort(perm)]) for t in
+                                           (np.array(u) for u in sol_tuples(b))}
+
+
+def test_slices_partition_the_solve():
+    inst = random_small(3, 18, 21, K=8, planted=True)
+    full = O.brute(inst.A, inst.d, key_rows=2)
+    tot_h, sols = 0, []
+    for s in range(4):
+        b = O.brute(inst.A, inst.d, key_rows=2, slice_mod=4, slice_res=s)
+        h = O.ss_heap(inst.A, inst.d, key_rows=2, slice_mod=4, slice_res=s)
+        mm = O.mitm(inst.A, inst.d, key_rows=2, log2_m=5, slice_mod=4, slice_res=s)
+        assert b.H == h.H == mm.H
+        assert sol_tuples(b) == sol_tuples(h) == sol_tuples(mm)
+        tot_h += b.H
+        sols += sol_tuples(b)
+    assert tot_h == full.H and sorted(sols) == sol_tuples(full)
+
+
+def test_mitm_modulus_and_range_invariance():
+    inst = random_small(4, 22, 31, planted=True)
+    ref = O.ss_heap(inst.A, inst.d, 2)
+    for lm in (0, 3, 9):
+        assert O.mitm(inst.A, inst.d, 2, log2_m=lm).H == ref.H
+    parts = [O.mitm(inst.A, inst.d, 2, log2_m=7, rho_lo=lo, rho_hi=lo + 32)
+             for lo in range(0, 128, 32)]
+    assert sum(p.H for p in parts) == ref.H
+    assert sorted(sum((sol_tuples(p) for p in parts), [])) == sol_tuples(ref)
+
+
+def test_4_30_seed0_and_planted():
+    inst = make_instance(4, 30, 0)
+    s = O.ss_heap(inst.A, inst.d, 1)
+    assert s.H == 2_570_096
+    assert O.mitm(inst.A, inst.d, 1, log2_m=11).H == s.H
+    p = make_instance(4, 30, 0, planted=True)
+    sp = O.ss_heap(p.A, p.d, 1)
+    mp = O.mitm(p.A, p.d, 1, log2_m=11)
+    assert sol_tuples(sp) == sol_tuples(mp)
+    assert tuple(int(v) for v in p.planted) in set(sol_tuples(sp))
+    assert sp.H == O.dp_count(p.A[0], p.d[0])
+
+
+def test_key_rows_bounds_chain():
+    # |S| <= H_m <= ... <= H_1 and H_r <= min DP(row i), i <= r.
+    inst = make_instance(4, 24, 3, planted=True)
+    hs = [O.ss_heap(inst.A, inst.d, r).H for r in range(1, 5)]
+    assert all(hs[i] >= hs[i + 1] for i in range(3))
+    dps = [O.dp_count(inst.A[i], inst.d[i]) for i in range(4)]
+    for r in range(1, 5):
+        assert hs[r - 1] <= min(dps[:r])
+    assert hs[0] == dps[0]
+    assert hs[1] == O.dp_count2(inst.A[0], inst.A[1], inst.d[0], inst.d[1])
+
+
+def test_paper_expected_solution_count_m4():
+    # Section 1: about 0.19 expected solutions for m = 4 (n = 30).  Mean over
+    # 400 fresh instances; the standard error is about 0.022.
+    tot = 0
+    N = 400
+    for s in range(N):
+        inst = make_instance(4, 30, 20_000 + s)
+        tot += O.ss_heap(inst.A, inst.d, 1).nsol
+    assert abs(tot / N - 0.19) < 0.09
+
+
+def test_errors():
+    A = np.ones((2, 3), dtype=np.int32)
+    with pytest.raises(O.OracleError):
+        O.brute(-A, [1, 1])
+    with pytest.raises(O.OracleError):
+        O.ss_heap(np.full((1, 3), 30000, dtype=np.int32), [1])     # row sum > 65534
+    with pytest.raises(O.OracleError):
+        O.ss_heap(np.full((9, 90), 99, dtype=np.int32), [1] * 9, key_rows=5)  # key overflow
