@@ -1,0 +1,126 @@
+/*
+ * msp.h -- C ABI of libmsp, an exact GPU solver (AMD Instinct MI355X,
+ * gfx950) for the feasibility market split problem.
+ *
+ * Problem (Section 1, eq. nSSP): given A in N0^{m x n} and d in N0^m, find
+ * EVERY x in {0,1}^n with sum_j a_ij x_j = d_i for all i = 1..m.
+ *
+ * Method (Sections 2-3): the first r rows are folded into one 1-D key by the
+ * surrogate constraint of Section 1 (eq. surrogate): with D = max(100,
+ * max a_ij + 1) and base B = n*D, key(x) = sum_{i<r} B^i (a_i . x) and
+ * K_d = sum_{i<r} B^i d_i; key(x) = K_d holds exactly when rows 1..r hold.
+ * Every solution of that 1-D subset-sum problem (a "1-D hit") is enumerated
+ * with a Schroeppel-Shamir style four-list meet in the middle (Algorithm 1,
+ * with the heaps replaced by residue classes of the key), and every hit is
+ * checked exactly against the remaining m - r rows (Algorithm 2).  All
+ * arithmetic is exact integer.
+ *
+ * Counting conventions:
+ *   H    = number of 1-D hits = #{x : rows 1..r hold}, a 128-bit count;
+ *   S    = the solution set; |S| is exact even when not all vectors are
+ *          stored (see max_solutions).
+ *   slice: with slice_mod = 2^s > 0, only x whose left-half key
+ *          k_L(x) = key of x restricted to columns 0..ceil(n/2)-1 satisfies
+ *          k_L(x) mod slice_mod == slice_res are counted and returned.
+ *
+ * Column partition (Algorithm 1 leaves it open): contiguous quarters,
+ * h_L = ceil(n/2), q_A = ceil(h_L/2), q_B = floor(h_L/2),
+ * q_C = ceil((n-h_L)/2), q_D = floor((n-h_L)/2).
+ *
+ * Threading: one context is used by one host thread at a time; distinct
+ * contexts may be used concurrently.  All calls return MSP_OK (0) or a
+ * negative MSP_E_* code; msp_strerror() names it.
+ */
+#ifndef MSP_H
+#define MSP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MSP_OK               0
+#define MSP_E_INVALID      (-1)  /* null pointer, m<1, n<1, a_ij<0, d_i<0, bad option */
+#define MSP_E_RANGE        (-2)  /* some row sum exceeds 65534 (uint16 row packing)    */
+#define MSP_E_KEY_OVERFLOW (-3)  /* sum_{i<r} B^i rowsum_i >= 2^63                      */
+#define MSP_E_UNSUPPORTED  (-4)  /* m > 10 or n > 92 or m - r > 10                      */
+#define MSP_E_NOMEM        (-5)  /* device workspace does not fit the budget            */
+#define MSP_E_DEVICE       (-6)  /* HIP runtime error; the context is poisoned          */
+#define MSP_E_CANCELLED    (-7)  /* solve cancelled                                     */
+#define MSP_E_TRUNCATED    (-8)  /* caller buffer smaller than the result               */
+#define MSP_E_STATE        (-9)  /* no result yet (msp_solve not run or failed)         */
+#define MSP_E_NOLIB        (-10) /* GPU not present or not usable                       */
+
+typedef struct msp_ctx msp_ctx;
+
+typedef struct {
+    int32_t  key_rows;        /* r >= 1 rows folded into the 1-D key; 0 = 1            */
+    int32_t  log2_m;          /* residue modulus M = 2^log2_m; 0 = planner's choice     */
+    int32_t  log2_cells;      /* residue cells T = 2^log2_cells; 0 = planner's choice   */
+    int32_t  parts;           /* work-groups per cell; 0 = planner's choice             */
+    int64_t  slice_mod;       /* 0 = full solve; else a power of two (see above)        */
+    int64_t  slice_res;       /* residue kept by the slice, 0 <= slice_res < slice_mod  */
+    uint64_t max_solutions;   /* solution vectors kept on the device; 0 = 1<<20         */
+    uint64_t window_records;  /* half records per side per window; 0 = planner's choice */
+    void    *workspace;       /* caller-owned device buffer, or NULL (library allocates)*/
+    uint64_t workspace_bytes; /* size of `workspace`; with NULL workspace: budget, 0=auto*/
+    void    *stream;          /* hipStream_t to run on, or NULL (library's own stream)  */
+} msp_opts;
+
+/* Per-solve statistics; phase times are measured with HIP events on the
+ * solve's stream and summed over windows. */
+typedef struct {
+    double   ms_total;        /* host wall time of msp_solve                        */
+    double   ms_quarters;     /* quarter-list generation + residue-cell sort         */
+    double   ms_count;        /* bucket counting pass                                */
+    double   ms_scan;         /* offset scans                                        */
+    double   ms_scatter;      /* bucket generation (scatter) pass                    */
+    double   ms_join;         /* per-bucket join (and in-join verify)                */
+    double   ms_verify;       /* tiled verify of large equal-key runs                */
+    uint64_t records_left;    /* half records generated, left side                   */
+    uint64_t records_right;   /* half records generated, right side                  */
+    uint64_t windows;         /* residue windows processed                           */
+    uint64_t verify_launches; /* launches of the tiled verify kernel                  */
+    uint64_t verify_pairs;    /* pairs covered by the tiled verify                   */
+    uint64_t record_bytes;    /* bytes of one half record                            */
+    int32_t  log2_m, log2_cells, parts, key_rows;
+    int32_t  exact_buckets;   /* 1: each bucket holds one key value                  */
+    int32_t  words;           /* 32-bit words of packed non-key rows                 */
+} msp_stats_t;
+
+/* Copies A (row-major m*n int32) and d (m int32); the caller may free both
+ * on return.  Validates the instance (see the error codes). */
+int  msp_create(const int32_t *A, const int32_t *d, int32_t m, int32_t n, msp_ctx **out);
+
+/* Fills *o with the defaults (all zero / NULL). */
+void msp_default_opts(msp_opts *o);
+
+/* Runs the whole solve on the GPU and keeps H, |S| and up to max_solutions
+ * vectors in the context.  Synchronous: returns when results are ready.
+ * opts may be NULL (defaults). */
+int  msp_solve(msp_ctx *ctx, const msp_opts *opts);
+
+/* Results of the last successful msp_solve. */
+int  msp_num_solutions(const msp_ctx *ctx, uint64_t *count);
+int  msp_hits(const msp_ctx *ctx, uint64_t *lo, uint64_t *hi);   /* 128-bit H */
+/* Writes up to `capacity` solutions as count*n bytes of 0/1 (x_1..x_n),
+ * in canonical lexicographic order.  Returns MSP_E_TRUNCATED (with
+ * *written = what fit) when capacity, or the stored set, is smaller than
+ * |S|. */
+int  msp_get_solutions(const msp_ctx *ctx, uint8_t *x, uint64_t capacity, uint64_t *written);
+int  msp_stats(const msp_ctx *ctx, msp_stats_t *out);
+
+void msp_destroy(msp_ctx *ctx);
+const char *msp_strerror(int code);
+
+/* Device workspace bytes msp_solve would use with these options, the
+ * plan shrunk to fit opts->workspace_bytes when that is non-zero (0 on
+ * error or when it cannot fit).  Size a caller-owned workspace with it. */
+uint64_t msp_workspace_bytes(const msp_ctx *ctx, const msp_opts *opts);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MSP_H */

@@ -1,0 +1,98 @@
+// Internal declarations shared by the engine and the kernels of libmsp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace msp {
+
+constexpr int kMaxWords = 5;        // packed uint16 non-key rows: up to 10 rows
+constexpr int kMaxFine = 4096;      // fine buckets per residue cell (LDS counters)
+constexpr int kJoinCap = 2048;      // left records per bucket held in LDS by the join
+constexpr int kJoinSlots = 4096;    // LDS hash slots of the join (power of two)
+constexpr int kTileR = 2048;        // right records per verify tile (256 lanes x 8)
+constexpr int kTileL = 4096;        // left records per verify tile
+constexpr int kThreads = 256;
+
+// Everything the kernels need to know about one solve.
+struct Plan {
+    int32_t m, n, r, nv, W;          // rows, columns, key rows, non-key rows, words
+    int32_t qa, qb, qc, qd, hL;      // quarter widths, left-half width
+    int32_t log2M, log2T, log2F;     // modulus M, cells T, fine buckets per cell F
+    int32_t parts;                   // work-groups per cell in count/scatter
+    int32_t exact;                   // 1: M > K_d, each bucket is one key value
+    int64_t Kd;                      // target key
+    int64_t slice_mod, slice_res;    // slice on the left key (0 = none)
+    int64_t kstep, kfirst;           // cell k = kfirst + idx * kstep
+    uint32_t dpk[kMaxWords];         // packed non-key right-hand sides
+    uint32_t Q[4];                   // quarter sizes
+};
+
+// A quarter subset: 1-D key (for quarter C: K_d - key), subset mask, packed
+// partial sums of the non-key rows.
+template <int W>
+struct alignas(8) QRec {
+    int64_t key;
+    uint32_t mask;
+    uint32_t vec[W > 0 ? W : 1];
+};
+
+// A half record in a bucket: left (k_a + k_b, packed row sums) or right
+// (K_d - k_c - k_d, packed d' - row sums with 0xFFFF for negatives).
+template <int W>
+struct alignas(8) Rec {
+    int64_t key;
+    uint64_t mask;                   // subset of the half (A|B<<qa, or C|D<<qc)
+    uint32_t vec[W > 0 ? W : 1];
+};
+
+struct RunPair {
+    uint32_t l0, nl, r0, nr;         // window-relative record ranges
+};
+
+// Device pointers of one solve.
+struct DevBufs {
+    void *qraw[4];                   // unsorted quarter records
+    void *qsrt[4];                   // quarter records sorted by residue cell
+    uint32_t *qcnt[4];               // per-cell counts, then exclusive offsets (T+1)
+    uint32_t *qcur[4];               // scatter cursors (T)
+    uint32_t *cnt[2];                // window counts per side (K*F*P + 1)
+    uint32_t *off[2];                // scanned offsets per side
+    void *rec[2];                    // window records per side
+    RunPair *runs;                   // run pairs for the tiled verify
+    uint32_t *tiles;                 // per run pair tile counts -> offsets (+1)
+    uint64_t *sol;                   // solutions: (maskL, maskR) pairs
+    uint64_t *scal;                  // scalars (see Scal)
+    void *scan_tmp;                  // scratch of the device-wide scan
+    size_t scan_tmp_bytes;
+    int64_t *colw;                   // per-column key weight (n)
+    uint16_t *rows;                  // non-key rows, nv x n
+};
+
+// Slots of DevBufs::scal.
+enum Scal {
+    S_H_LO = 0, S_H_HI, S_NSOL, S_NRUNS, S_TOT_L, S_TOT_R, S_TOT_TILES, S_STORED, S_COUNT
+};
+
+// Launchers (kernels.hip).  All asynchronous on `st`.
+hipError_t launch_quarters(const Plan &p, const DevBufs &b, int log2T_unused, hipStream_t st);
+hipError_t launch_count(const Plan &p, const DevBufs &b, int64_t idx0, int32_t K, hipStream_t st);
+hipError_t launch_scatter(const Plan &p, const DevBufs &b, int64_t idx0, int32_t K, hipStream_t st);
+hipError_t launch_exact_runs(const Plan &p, const DevBufs &b, int32_t K, hipStream_t st);
+hipError_t launch_hash_join(const Plan &p, const DevBufs &b, int32_t K, uint64_t sol_cap,
+                            hipStream_t st);
+hipError_t launch_verify(const Plan &p, const DevBufs &b, uint32_t nruns, uint32_t ntiles,
+                         uint64_t sol_cap, int check_key, hipStream_t st);
+hipError_t launch_tile_counts(const Plan &p, const DevBufs &b, uint32_t nruns, int check_key,
+                              hipStream_t st);
+// Exclusive scan of n uint32 values (out[n] = total; out may equal in);
+// the total is also stored to *total64 when non-null.
+hipError_t scan_u32(const uint32_t *in, uint32_t *out, size_t n, uint64_t *total64,
+                    void *tmp, size_t tmp_bytes, hipStream_t st);
+size_t scan_tmp_bytes(size_t n);
+
+size_t qrec_bytes(int W);
+size_t rec_bytes(int W);
+
+}  // namespace msp

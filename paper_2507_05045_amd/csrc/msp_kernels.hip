@@ -1,0 +1,747 @@
+// HIP kernels of libmsp for gfx950 (wave64).  Integer only; no MFMA: nothing
+// on this path is a dense contraction.
+//
+// Pipeline of one solve (Section 2, Algorithm 1, and Section 3, Algorithm 2):
+//   quarter lists  -> residue-cell sort of each quarter
+//   per window of residue cells:
+//     bucket count -> offset scan -> bucket scatter (half records grouped by
+//     residue bucket) -> per-bucket equal-key join (+ verify of small runs)
+//     -> tiled verify of large equal-key runs against the non-key rows.
+//
+// Residue structure.  Left key k_L = k_a + k_b, right target t_R = K_d - k_c
+// - k_d; a pair is a 1-D hit iff k_L == t_R.  A bucket is a residue class
+// rho = key mod M (M = 2^log2M).  A residue cell is rho mod T (T = 2^log2T,
+// low bits), the fine index f = (key mod M) >> log2T.  Because cells use the
+// low bits, cell(a + b) = cell(a) + cell(b) mod T exactly, so the left
+// records of output cell k are exactly the products A_i x B_{k-i}: every
+// enumerated pair lands in the cell being built.
+#include "msp_internal.h"
+
+namespace msp {
+
+// ---------------------------------------------------------------------------
+// Small device helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+
+// Sum over a 256-thread block; result valid in thread 0.
+__device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t *lds4) {
+    v = wave_sum_u64(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) lds4[wave] = v;
+    __syncthreads();
+    uint64_t t = 0;
+    if (threadIdx.x == 0) t = lds4[0] + lds4[1] + lds4[2] + lds4[3];
+    __syncthreads();
+    return t;
+}
+
+__device__ __forceinline__ void add_u128(uint64_t *lo, uint64_t *hi, uint64_t v) {
+    if (!v) return;
+    unsigned long long old = atomicAdd((unsigned long long *)lo, (unsigned long long)v);
+    if (old + v < old) atomicAdd((unsigned long long *)hi, 1ull);
+}
+
+// Inclusive scan across a wave of 64 lanes.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    const int lane = threadIdx.x & 63;
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// Exclusive scan of a[0 .. 256*E) held in LDS, by a 256-thread block.
+// Returns the total.  `w4` is 4 words of LDS scratch.
+template <int E>
+__device__ uint32_t block_excl_scan_lds(uint32_t *a, uint32_t *w4) {
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    uint32_t loc[E];
+    uint32_t s = 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) { loc[e] = a[t * E + e]; s += loc[e]; }
+    uint32_t inc = wave_incl_scan(s);
+    if (lane == 63) w4[wave] = inc;
+    __syncthreads();
+    uint32_t wbase = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        uint32_t x = w4[w];
+        if (w < wave) wbase += x;
+        total += x;
+    }
+    uint32_t run = wbase + inc - s;
+#pragma unroll
+    for (int e = 0; e < E; ++e) { a[t * E + e] = run; run += loc[e]; }
+    __syncthreads();
+    return total;
+}
+
+// Packed right residual: per 16-bit half, d'_i - c_i - e_i, or 0xFFFF when
+// negative (a left half-sum never equals 0xFFFF because row sums <= 65534).
+__device__ __forceinline__ uint32_t resid_word(uint32_t dp, uint32_t c, uint32_t e) {
+    int lo = (int)(dp & 0xFFFFu) - (int)(c & 0xFFFFu) - (int)(e & 0xFFFFu);
+    int hi = (int)(dp >> 16) - (int)(c >> 16) - (int)(e >> 16);
+    uint32_t l = lo < 0 ? 0xFFFFu : (uint32_t)lo;
+    uint32_t h = hi < 0 ? 0xFFFFu : (uint32_t)hi;
+    return l | (h << 16);
+}
+
+template <int W>
+struct QPtrs { QRec<W> *q[4]; };
+struct UPtrs { uint32_t *q[4]; };
+
+// ---------------------------------------------------------------------------
+// Quarter lists (Algorithm 1, the power sets 2^A .. 2^D with their sums)
+// ---------------------------------------------------------------------------
+
+// One thread per subset u of one quarter: its key weight, its packed partial
+// sums of the non-key rows, and its residue cell (counted).
+template <int W>
+__global__ __launch_bounds__(256) void k_quarter_gen(Plan p, const int64_t *__restrict__ colw,
+                                                     const uint16_t *__restrict__ rows,
+                                                     QPtrs<W> out, UPtrs cnt) {
+    __shared__ int64_t s_w[96];
+    __shared__ uint16_t s_rows[kMaxWords * 2 * 96];
+    for (int i = threadIdx.x; i < p.n; i += blockDim.x) s_w[i] = colw[i];
+    for (int i = threadIdx.x; i < p.nv * p.n; i += blockDim.x) s_rows[i] = rows[i];
+    __syncthreads();
+    uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int x = 0;
+    while (x < 4 && g >= p.Q[x]) { g -= p.Q[x]; ++x; }
+    if (x >= 4) return;
+    const int col0 = x == 0 ? 0 : x == 1 ? p.qa : x == 2 ? p.hL : p.hL + p.qc;
+    const int width = x == 0 ? p.qa : x == 1 ? p.qb : x == 2 ? p.qc : p.qd;
+    const uint32_t u = (uint32_t)g;
+    int64_t key = 0;
+    uint32_t s[kMaxWords * 2];
+#pragma unroll
+    for (int v = 0; v < kMaxWords * 2; ++v) s[v] = 0;
+    for (int b = 0; b < width; ++b) {
+        if (!((u >> b) & 1u)) continue;
+        const int j = col0 + b;
+        key += s_w[j];
+#pragma unroll
+        for (int v = 0; v < kMaxWords * 2; ++v)
+            if (v < p.nv) s[v] += s_rows[v * p.n + j];
+    }
+    if (x == 2) key = p.Kd - key;        // quarter C carries K_d - k_c
+    QRec<W> r;
+    r.key = key;
+    r.mask = u;
+#pragma unroll
+    for (int w = 0; w < (W > 0 ? W : 1); ++w) r.vec[w] = s[2 * w] | (s[2 * w + 1] << 16);
+    out.q[x][u] = r;
+    const uint32_t T = 1u << p.log2T;
+    atomicAdd(&cnt.q[x][(uint32_t)key & (T - 1)], 1u);
+}
+
+// Counting-sort scatter of each quarter by residue cell.
+template <int W>
+__global__ __launch_bounds__(256) void k_quarter_sort(Plan p, QPtrs<W> raw, QPtrs<W> srt,
+                                                      UPtrs cur) {
+    uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int x = 0;
+    while (x < 4 && g >= p.Q[x]) { g -= p.Q[x]; ++x; }
+    if (x >= 4) return;
+    const QRec<W> r = raw.q[x][g];
+    const uint32_t T = 1u << p.log2T;
+    const uint32_t pos = atomicAdd(&cur.q[x][(uint32_t)r.key & (T - 1)], 1u);
+    srt.q[x][pos] = r;
+}
+
+// ---------------------------------------------------------------------------
+// Bucket count / scatter (one enumeration, two modes)
+// ---------------------------------------------------------------------------
+//
+// Work-group (cell-in-window c, part p, side s).  Side 0 builds left records
+// of cell k from (a in A) x (b in B_{k - cell(a)}); side 1 builds right
+// records from (c in C) x (e in D_{cell(c) - k}).  Part p takes a contiguous
+// slice of the outer quarter.  Counts are laid out [c][f][p] so that one
+// exclusive scan makes every bucket (c, f) contiguous, parts in order.
+template <int W, bool SCATTER>
+__global__ __launch_bounds__(256) void k_bucket(Plan p, const QRec<W> *__restrict__ A,
+                                                const QRec<W> *__restrict__ B,
+                                                const uint32_t *__restrict__ offB,
+                                                const QRec<W> *__restrict__ Cq,
+                                                const QRec<W> *__restrict__ Dq,
+                                                const uint32_t *__restrict__ offD,
+                                                uint32_t *cntL, uint32_t *cntR,
+                                                const uint32_t *__restrict__ offL,
+                                                const uint32_t *__restrict__ offR,
+                                                Rec<W> *recL, Rec<W> *recR, int64_t idx0) {
+    __shared__ uint32_t s_f[kMaxFine];
+    const int side = blockIdx.y;
+    const int P = p.parts;
+    const int cw = blockIdx.x / P, part = blockIdx.x % P;
+    const uint32_t T = 1u << p.log2T;
+    const int F = 1 << p.log2F;
+    const int64_t M1 = ((int64_t)1 << p.log2M) - 1;
+    const uint32_t k = (uint32_t)(p.kfirst + (idx0 + cw) * p.kstep) & (T - 1);
+    const QRec<W> *outer = side ? Cq : A;
+    const QRec<W> *inner = side ? Dq : B;
+    const uint32_t *ioff = side ? offD : offB;
+    const uint64_t Qo = side ? p.Q[2] : p.Q[0];
+    const int sh = side ? p.qc : p.qa;
+    const uint32_t *offs = side ? offR : offL;
+    uint32_t *cnt = side ? cntR : cntL;
+    Rec<W> *rec = side ? recR : recL;
+    const uint64_t base = ((uint64_t)cw * F) * P + part;
+    for (int f = threadIdx.x; f < F; f += blockDim.x)
+        s_f[f] = SCATTER ? offs[base + (uint64_t)f * P] : 0u;
+    __syncthreads();
+    const uint64_t lo = Qo * part / P, hi = Qo * (part + 1) / P;
+    const int64_t smod1 = p.slice_mod - 1;
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+        const QRec<W> a = outer[i];
+        const uint32_t ca = (uint32_t)a.key & (T - 1);
+        const uint32_t j = side ? ((ca - k) & (T - 1)) : ((k - ca) & (T - 1));
+        const uint32_t b0 = ioff[j], b1 = ioff[j + 1];
+        for (uint32_t q = b0; q < b1; ++q) {
+            const QRec<W> b = inner[q];
+            const int64_t key = side ? a.key - b.key : a.key + b.key;
+            bool keep = side ? key >= 0 : key <= p.Kd;   // only these can meet
+            if (p.slice_mod) keep = keep && ((key & smod1) == p.slice_res);
+            if (!keep) continue;
+            const uint32_t f = (uint32_t)((key & M1) >> p.log2T);
+            if (!SCATTER) {
+                atomicAdd(&s_f[f], 1u);
+            } else {
+                const uint32_t slot = atomicAdd(&s_f[f], 1u);
+                Rec<W> r;
+                r.key = key;
+                r.mask = (uint64_t)a.mask | ((uint64_t)b.mask << sh);
+#pragma unroll
+                for (int w = 0; w < (W > 0 ? W : 1); ++w)
+                    r.vec[w] = side ? resid_word(p.dpk[w], a.vec[w], b.vec[w])
+                                    : a.vec[w] + b.vec[w];
+                rec[slot] = r;
+            }
+        }
+    }
+    if (!SCATTER) {
+        __syncthreads();
+        for (int f = threadIdx.x; f < F; f += blockDim.x) cnt[base + (uint64_t)f * P] = s_f[f];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Exact buckets (M > K_d): a bucket is one key value, so the whole bucket pair
+// is one equal-key run pair (the E_A x E_C groups of Algorithm 1).
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_exact_runs(Plan p, const uint32_t *__restrict__ offL,
+                                                    const uint32_t *__restrict__ offR,
+                                                    uint32_t nb, RunPair *runs,
+                                                    uint64_t *scal, int w_zero) {
+    __shared__ uint64_t s4[4];
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t h = 0;
+    if (b < nb) {
+        const uint64_t P = p.parts;
+        const uint32_t l0 = offL[b * P], l1 = offL[(b + 1) * P];
+        const uint32_t r0 = offR[b * P], r1 = offR[(b + 1) * P];
+        if (l1 > l0 && r1 > r0) {
+            h = (uint64_t)(l1 - l0) * (r1 - r0);
+            const uint64_t idx = atomicAdd((unsigned long long *)&scal[S_NRUNS], 1ull);
+            runs[idx] = RunPair{l0, l1 - l0, r0, r1 - r0};
+        }
+    }
+    const uint64_t t = block_sum_u64(h, s4);
+    if (threadIdx.x == 0) {
+        add_u128(&scal[S_H_LO], &scal[S_H_HI], t);
+        if (w_zero) atomicAdd((unsigned long long *)&scal[S_NSOL], (unsigned long long)t);
+    }
+}
+
+__global__ void k_tile_counts(const RunPair *__restrict__ runs, const uint64_t *__restrict__ scal,
+                              uint32_t *tiles) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t n = scal[S_NRUNS];
+    if (i >= n) return;
+    const RunPair r = runs[i];
+    tiles[i] = ((r.nl + kTileL - 1) / kTileL) * ((r.nr + kTileR - 1) / kTileR);
+}
+
+__device__ __forceinline__ void emit_solution(uint64_t *sol, uint64_t cap, uint64_t *ctr,
+                                              uint64_t ml, uint64_t mr) {
+    const uint64_t idx = atomicAdd((unsigned long long *)ctr, 1ull);
+    if (idx < cap) {
+        sol[2 * idx] = ml;
+        sol[2 * idx + 1] = mr;
+    }
+}
+
+// Full check of one 1-D hit against the non-key rows (the key rows hold by
+// key equality): every packed word of the left sums equals the right residual.
+template <int W>
+__device__ __forceinline__ bool rows_match(const Rec<W> &l, const Rec<W> &r) {
+    bool ok = true;
+#pragma unroll
+    for (int w = 0; w < W; ++w) ok = ok && (l.vec[w] == r.vec[w]);
+    return ok;
+}
+
+// ---------------------------------------------------------------------------
+// Hash join of one bucket (keys of several values): left keys grouped by a
+// hash table in LDS, right records probe it; small equal-key groups are
+// verified in place.  Buckets with more than kJoinCap left records are sent
+// to the key-checking tiled verify instead.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t key_hash(int64_t k) {
+    return (uint32_t)(((uint64_t)k * 0x9E3779B97F4A7C15ull) >> 40);
+}
+
+template <int W>
+__global__ __launch_bounds__(256) void k_hash_join(Plan p, const uint32_t *__restrict__ offL,
+                                                   const uint32_t *__restrict__ offR,
+                                                   const Rec<W> *__restrict__ L,
+                                                   const Rec<W> *__restrict__ R, RunPair *runs,
+                                                   uint64_t *scal, uint64_t *sol, uint64_t cap) {
+    __shared__ int64_t s_key[kJoinCap];
+    __shared__ uint32_t s_v0[kJoinCap];
+    __shared__ int32_t s_head[kJoinSlots];
+    __shared__ uint32_t s_start[kJoinSlots];
+    __shared__ uint16_t s_slot[kJoinCap];
+    __shared__ uint16_t s_grp[kJoinCap];
+    __shared__ uint32_t s_w4[4];
+    __shared__ uint64_t s_s4[4];
+    const uint32_t b = blockIdx.x;
+    const uint64_t P = p.parts;
+    const uint32_t l0 = offL[b * P], l1 = offL[(b + 1) * P];
+    const uint32_t r0 = offR[b * P], r1 = offR[(b + 1) * P];
+    const uint32_t nl = l1 - l0, nr = r1 - r0;
+    if (nl == 0 || nr == 0) return;                     // uniform across the block
+    if (nl > (uint32_t)kJoinCap) {
+        if (threadIdx.x == 0) {
+            const uint64_t idx = atomicAdd((unsigned long long *)&scal[S_NRUNS], 1ull);
+            runs[idx] = RunPair{l0, nl, r0, nr};
+        }
+        return;
+    }
+    const int t = threadIdx.x;
+    for (int i = t; i < kJoinSlots; i += 256) { s_head[i] = -1; s_start[i] = 0; }
+    for (uint32_t i = t; i < nl; i += 256) {
+        s_key[i] = L[l0 + i].key;
+        s_v0[i] = W > 0 ? L[l0 + i].vec[0] : 0u;
+    }
+    __syncthreads();
+    // Insert: one representative per distinct key, count per slot.
+    for (uint32_t i = t; i < nl; i += 256) {
+        const int64_t k = s_key[i];
+        uint32_t h = key_hash(k) & (kJoinSlots - 1);
+        for (;;) {
+            int cur = s_head[h];
+            if (cur < 0) {
+                const int old = atomicCAS(&s_head[h], -1, (int)i);
+                if (old < 0) break;
+                cur = old;
+            }
+            if (s_key[cur] == k) break;
+            h = (h + 1) & (kJoinSlots - 1);
+        }
+        s_slot[i] = (uint16_t)h;
+        atomicAdd(&s_start[h], 1u);
+    }
+    __syncthreads();
+    block_excl_scan_lds<kJoinSlots / 256>(s_start, s_w4);
+    // Group left records by slot; afterwards s_start[h] = end of group h.
+    for (uint32_t i = t; i < nl; i += 256) {
+        const uint32_t pos = atomicAdd(&s_start[s_slot[i]], 1u);
+        s_grp[pos] = (uint16_t)i;
+    }
+    __syncthreads();
+    uint64_t hits = 0;
+    for (uint32_t j = t; j < nr; j += 256) {
+        const Rec<W> rr = R[r0 + j];
+        uint32_t h = key_hash(rr.key) & (kJoinSlots - 1);
+        int found = -1;
+        for (;;) {
+            const int cur = s_head[h];
+            if (cur < 0) break;
+            if (s_key[cur] == rr.key) { found = (int)h; break; }
+            h = (h + 1) & (kJoinSlots - 1);
+        }
+        if (found < 0) continue;
+        const uint32_t ge = s_start[found], gs = found ? s_start[found - 1] : 0u;
+        hits += ge - gs;
+        if (W == 0) {
+            atomicAdd((unsigned long long *)&scal[S_NSOL], (unsigned long long)(ge - gs));
+            for (uint32_t q = gs; q < ge; ++q) {
+                if (scal[S_STORED] >= cap) break;
+                const uint32_t li = s_grp[q];
+                emit_solution(sol, cap, &scal[S_STORED], L[l0 + li].mask, rr.mask);
+            }
+        } else {
+            for (uint32_t q = gs; q < ge; ++q) {
+                const uint32_t li = s_grp[q];
+                if (s_v0[li] != rr.vec[0]) continue;
+                const Rec<W> ll = L[l0 + li];
+                if (rows_match<W>(ll, rr)) emit_solution(sol, cap, &scal[S_NSOL], ll.mask, rr.mask);
+            }
+        }
+    }
+    const uint64_t tot = block_sum_u64(hits, s_s4);
+    if (t == 0) add_u128(&scal[S_H_LO], &scal[S_H_HI], tot);
+}
+
+// ---------------------------------------------------------------------------
+// Tiled verify of equal-key run pairs (exact buckets), or of oversized hash
+// buckets with the key compared per pair (CK).  Tile = kTileL left x kTileR
+// right records.  Each lane holds 8 right words; left words are staged in
+// LDS and read as broadcasts; a wave-wide ballot OR flags candidate pairs,
+// which are then checked in full.
+// ---------------------------------------------------------------------------
+
+constexpr int kKR = kTileR / 256;     // right records per lane
+constexpr int kChunk = 1024;          // left records per LDS stage
+
+template <int W, bool CK>
+__global__ __launch_bounds__(256) void k_verify(Plan p, const Rec<W> *__restrict__ L,
+                                                const Rec<W> *__restrict__ R,
+                                                const RunPair *__restrict__ runs,
+                                                const uint32_t *__restrict__ toff,
+                                                uint32_t nruns, uint64_t *scal, uint64_t *sol,
+                                                uint64_t cap) {
+    __shared__ __attribute__((aligned(16))) uint32_t s_lw[kChunk];
+    __shared__ int64_t s_lk[CK ? kChunk : 1];
+    __shared__ uint64_t s_s4[4];
+    const uint32_t tile = blockIdx.x;
+    // Run pair of this tile: last ri with toff[ri] <= tile.
+    uint32_t lo = 0, hi = nruns;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (toff[mid] <= tile) lo = mid; else hi = mid;
+    }
+    const RunPair rp = runs[lo];
+    const uint32_t loc = tile - toff[lo];
+    const uint32_t tr_n = (rp.nr + kTileR - 1) / kTileR;
+    const uint32_t tl = loc / tr_n, tr = loc % tr_n;
+    const uint32_t lb = rp.l0 + tl * kTileL;
+    const uint32_t le = min(rp.l0 + rp.nl, lb + (uint32_t)kTileL);
+    const uint32_t rb = rp.r0 + tr * kTileR;
+    const uint32_t re = min(rp.r0 + rp.nr, rb + (uint32_t)kTileR);
+    const int t = threadIdx.x;
+
+    uint32_t rw[kKR];
+    int64_t rk[CK ? kKR : 1];
+#pragma unroll
+    for (int k = 0; k < kKR; ++k) {
+        const uint32_t ri = rb + k * 256 + t;
+        rw[k] = 0xFFFFFFFFu;                      // never equals a left word
+        if (CK) rk[k] = -1;                       // never equals a left key
+        if (ri < re) {
+            rw[k] = W > 0 ? R[ri].vec[0] : 0u;
+            if (CK) rk[k] = R[ri].key;
+        }
+    }
+    uint64_t hits = 0;
+    if (W == 0 && !CK) {
+        // Every pair is a solution: store while there is room.
+        for (uint32_t li = lb; li < le; ++li) {
+#pragma unroll
+            for (int k = 0; k < kKR; ++k) {
+                const uint32_t ri = rb + k * 256 + t;
+                if (ri < re && scal[S_STORED] < cap)
+                    emit_solution(sol, cap, &scal[S_STORED], L[li].mask, R[ri].mask);
+            }
+        }
+        return;
+    }
+    for (uint32_t c0 = lb; c0 < le; c0 += kChunk) {
+        const uint32_t cn = min((uint32_t)kChunk, le - c0);
+        __syncthreads();
+        for (uint32_t i = t; i < cn; i += 256) {
+            s_lw[i] = W > 0 ? L[c0 + i].vec[0] : 0u;
+            if (CK) s_lk[i] = L[c0 + i].key;
+        }
+        __syncthreads();
+        if (!CK) {
+            uint64_t acc = 0;
+            uint32_t j = 0;
+            for (; j + 4 <= cn; j += 4) {
+                const uint4 q = *reinterpret_cast<const uint4 *>(&s_lw[j]);
+#pragma unroll
+                for (int k = 0; k < kKR; ++k) acc |= __builtin_amdgcn_ballot_w64(rw[k] == q.x);
+#pragma unroll
+                for (int k = 0; k < kKR; ++k) acc |= __builtin_amdgcn_ballot_w64(rw[k] == q.y);
+#pragma unroll
+                for (int k = 0; k < kKR; ++k) acc |= __builtin_amdgcn_ballot_w64(rw[k] == q.z);
+#pragma unroll
+                for (int k = 0; k < kKR; ++k) acc |= __builtin_amdgcn_ballot_w64(rw[k] == q.w);
+            }
+            for (; j < cn; ++j) {
+                const uint32_t x = s_lw[j];
+#pragma unroll
+                for (int k = 0; k < kKR; ++k) acc |= __builtin_amdgcn_ballot_w64(rw[k] == x);
+            }
+            if (acc) {
+                // Rare: some lane saw equal first words.  Check those pairs fully.
+                for (uint32_t jj = 0; jj < cn; ++jj) {
+                    const uint32_t x = s_lw[jj];
+#pragma unroll
+                    for (int k = 0; k < kKR; ++k) {
+                        if (rw[k] == x) {
+                            const Rec<W> ll = L[c0 + jj];
+                            const Rec<W> rr = R[rb + k * 256 + t];
+                            if (rows_match<W>(ll, rr))
+                                emit_solution(sol, cap, &scal[S_NSOL], ll.mask, rr.mask);
+                        }
+                    }
+                }
+            }
+        } else {
+            for (uint32_t jj = 0; jj < cn; ++jj) {
+                const int64_t lk = s_lk[jj];
+                const uint32_t x = s_lw[jj];
+#pragma unroll
+                for (int k = 0; k < kKR; ++k) {
+                    if (rk[k] == lk) {
+                        ++hits;
+                        if (W == 0) {
+                            atomicAdd((unsigned long long *)&scal[S_NSOL], 1ull);
+                            if (scal[S_STORED] < cap)
+                                emit_solution(sol, cap, &scal[S_STORED], L[c0 + jj].mask,
+                                              R[rb + k * 256 + t].mask);
+                        } else if (rw[k] == x) {
+                            const Rec<W> ll = L[c0 + jj];
+                            const Rec<W> rr = R[rb + k * 256 + t];
+                            if (rows_match<W>(ll, rr))
+                                emit_solution(sol, cap, &scal[S_NSOL], ll.mask, rr.mask);
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (CK) {
+        const uint64_t tot = block_sum_u64(hits, s_s4);
+        if (t == 0) add_u128(&scal[S_H_LO], &scal[S_H_HI], tot);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Device-wide exclusive scan of uint32 (reduce -> scan of block sums -> apply)
+// ---------------------------------------------------------------------------
+
+constexpr int kScanE = 4;
+constexpr int kScanBlock = 256 * kScanE;
+
+__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t *__restrict__ in, size_t n,
+                                                     uint32_t *sums) {
+    __shared__ uint64_t s4[4];
+    const size_t base = (size_t)blockIdx.x * kScanBlock;
+    uint64_t s = 0;
+    for (int e = 0; e < kScanE; ++e) {
+        const size_t i = base + (size_t)e * 256 + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    s = block_sum_u64(s, s4);
+    if (threadIdx.x == 0) sums[blockIdx.x] = (uint32_t)s;
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *__restrict__ in, uint32_t *out,
+                                                    size_t n, const uint32_t *__restrict__ pref,
+                                                    uint64_t *total64, int write_total) {
+    __shared__ uint32_t s_a[kScanBlock];
+    __shared__ uint32_t s_w4[4];
+    const size_t base = (size_t)blockIdx.x * kScanBlock;
+    for (int e = 0; e < kScanE; ++e) {
+        const size_t i = base + (size_t)e * 256 + threadIdx.x;
+        s_a[e * 256 + threadIdx.x] = i < n ? in[i] : 0u;
+    }
+    __syncthreads();
+    const uint32_t tot = block_excl_scan_lds<kScanE>(s_a, s_w4);
+    const uint32_t add = pref ? pref[blockIdx.x] : 0u;
+    for (int e = 0; e < kScanE; ++e) {
+        const size_t i = base + (size_t)e * 256 + threadIdx.x;
+        if (i < n) out[i] = s_a[e * 256 + threadIdx.x] + add;
+    }
+    if (write_total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+        out[n] = add + tot;
+        if (total64) *total64 = (uint64_t)(add + tot);
+    }
+}
+
+size_t scan_tmp_bytes(size_t n) {
+    size_t bytes = 0;
+    while (n > (size_t)kScanBlock) {
+        n = (n + kScanBlock - 1) / kScanBlock;
+        bytes += (n + 1) * sizeof(uint32_t) * 2 + 256;
+    }
+    return bytes + 256;
+}
+
+hipError_t scan_u32(const uint32_t *in, uint32_t *out, size_t n, uint64_t *total64, void *tmp,
+                    size_t tmp_bytes, hipStream_t st) {
+    if (n == 0) {
+        hipError_t e = hipMemsetAsync(out, 0, sizeof(uint32_t), st);
+        if (e == hipSuccess && total64) e = hipMemsetAsync(total64, 0, sizeof(uint64_t), st);
+        return e;
+    }
+    const size_t nb = (n + kScanBlock - 1) / kScanBlock;
+    if (nb == 1) {
+        hipLaunchKernelGGL(k_scan_apply, dim3(1), dim3(256), 0, st, in, out, n, nullptr, total64, 1);
+        return hipGetLastError();
+    }
+    const size_t need = (nb + 1) * sizeof(uint32_t) * 2 + 256;
+    if (tmp_bytes < need) return hipErrorInvalidValue;
+    uint32_t *sums = (uint32_t *)tmp;
+    uint32_t *pref = sums + nb + 1;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((uint32_t)nb), dim3(256), 0, st, in, n, sums);
+    hipError_t e = scan_u32(sums, pref, nb, nullptr, (char *)tmp + need, tmp_bytes - need, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scan_apply, dim3((uint32_t)nb), dim3(256), 0, st, in, out, n, pref,
+                       total64, 1);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+size_t qrec_bytes(int W) {
+    switch (W) {
+        case 0: return sizeof(QRec<0>);
+        case 1: return sizeof(QRec<1>);
+        case 2: return sizeof(QRec<2>);
+        case 3: return sizeof(QRec<3>);
+        case 4: return sizeof(QRec<4>);
+        default: return sizeof(QRec<5>);
+    }
+}
+
+size_t rec_bytes(int W) {
+    switch (W) {
+        case 0: return sizeof(Rec<0>);
+        case 1: return sizeof(Rec<1>);
+        case 2: return sizeof(Rec<2>);
+        case 3: return sizeof(Rec<3>);
+        case 4: return sizeof(Rec<4>);
+        default: return sizeof(Rec<5>);
+    }
+}
+
+#define MSP_DISPATCH_W(W, CALL)                       \
+    switch (W) {                                      \
+        case 0: { constexpr int WW = 0; CALL; } break; \
+        case 1: { constexpr int WW = 1; CALL; } break; \
+        case 2: { constexpr int WW = 2; CALL; } break; \
+        case 3: { constexpr int WW = 3; CALL; } break; \
+        case 4: { constexpr int WW = 4; CALL; } break; \
+        case 5: { constexpr int WW = 5; CALL; } break; \
+        default: return hipErrorInvalidValue;         \
+    }
+
+template <int W>
+static hipError_t quarters_impl(const Plan &p, const DevBufs &b, hipStream_t st) {
+    const uint64_t tot = (uint64_t)p.Q[0] + p.Q[1] + p.Q[2] + p.Q[3];
+    const uint32_t grid = (uint32_t)((tot + 255) / 256);
+    QPtrs<W> raw, srt;
+    UPtrs cnt, cur;
+    for (int x = 0; x < 4; ++x) {
+        raw.q[x] = (QRec<W> *)b.qraw[x];
+        srt.q[x] = (QRec<W> *)b.qsrt[x];
+        cnt.q[x] = b.qcnt[x];
+        cur.q[x] = b.qcur[x];
+    }
+    hipLaunchKernelGGL(k_quarter_gen<W>, dim3(grid), dim3(256), 0, st, p, b.colw, b.rows, raw, cnt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t T = (size_t)1 << p.log2T;
+    for (int x = 0; x < 4; ++x) {
+        e = scan_u32(b.qcnt[x], b.qcnt[x], T, nullptr, b.scan_tmp, b.scan_tmp_bytes, st);
+        if (e != hipSuccess) return e;
+        e = hipMemcpyAsync(b.qcur[x], b.qcnt[x], T * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_quarter_sort<W>, dim3(grid), dim3(256), 0, st, p, raw, srt, cur);
+    return hipGetLastError();
+}
+
+hipError_t launch_quarters(const Plan &p, const DevBufs &b, int, hipStream_t st) {
+    MSP_DISPATCH_W(p.W, return quarters_impl<WW>(p, b, st));
+    return hipSuccess;
+}
+
+template <int W, bool SC>
+static hipError_t bucket_impl(const Plan &p, const DevBufs &b, int64_t idx0, int32_t K,
+                              hipStream_t st) {
+    dim3 grid((uint32_t)K * p.parts, 2);
+    hipLaunchKernelGGL((k_bucket<W, SC>), grid, dim3(256), 0, st, p,
+                       (const QRec<W> *)b.qsrt[0], (const QRec<W> *)b.qsrt[1], b.qcnt[1],
+                       (const QRec<W> *)b.qsrt[2], (const QRec<W> *)b.qsrt[3], b.qcnt[3],
+                       b.cnt[0], b.cnt[1], b.off[0], b.off[1], (Rec<W> *)b.rec[0],
+                       (Rec<W> *)b.rec[1], idx0);
+    return hipGetLastError();
+}
+
+hipError_t launch_count(const Plan &p, const DevBufs &b, int64_t idx0, int32_t K, hipStream_t st) {
+    MSP_DISPATCH_W(p.W, return (bucket_impl<WW, false>(p, b, idx0, K, st)));
+    return hipSuccess;
+}
+
+hipError_t launch_scatter(const Plan &p, const DevBufs &b, int64_t idx0, int32_t K,
+                          hipStream_t st) {
+    MSP_DISPATCH_W(p.W, return (bucket_impl<WW, true>(p, b, idx0, K, st)));
+    return hipSuccess;
+}
+
+hipError_t launch_exact_runs(const Plan &p, const DevBufs &b, int32_t K, hipStream_t st) {
+    const uint32_t nb = (uint32_t)K << p.log2F;
+    hipLaunchKernelGGL(k_exact_runs, dim3((nb + 255) / 256), dim3(256), 0, st, p, b.off[0],
+                       b.off[1], nb, b.runs, b.scal, p.W == 0 ? 1 : 0);
+    return hipGetLastError();
+}
+
+template <int W>
+static hipError_t join_impl(const Plan &p, const DevBufs &b, int32_t K, uint64_t cap,
+                            hipStream_t st) {
+    const uint32_t nb = (uint32_t)K << p.log2F;
+    hipLaunchKernelGGL(k_hash_join<W>, dim3(nb), dim3(256), 0, st, p, b.off[0], b.off[1],
+                       (const Rec<W> *)b.rec[0], (const Rec<W> *)b.rec[1], b.runs, b.scal,
+                       b.sol, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_hash_join(const Plan &p, const DevBufs &b, int32_t K, uint64_t cap,
+                            hipStream_t st) {
+    MSP_DISPATCH_W(p.W, return join_impl<WW>(p, b, K, cap, st));
+    return hipSuccess;
+}
+
+hipError_t launch_tile_counts(const Plan &, const DevBufs &b, uint32_t nruns, int, hipStream_t st) {
+    if (nruns == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tile_counts, dim3((nruns + 255) / 256), dim3(256), 0, st, b.runs, b.scal,
+                       b.tiles);
+    return hipGetLastError();
+}
+
+template <int W>
+static hipError_t verify_impl(const Plan &p, const DevBufs &b, uint32_t nruns, uint32_t ntiles,
+                              uint64_t cap, int ck, hipStream_t st) {
+    if (ck)
+        hipLaunchKernelGGL((k_verify<W, true>), dim3(ntiles), dim3(256), 0, st, p,
+                           (const Rec<W> *)b.rec[0], (const Rec<W> *)b.rec[1], b.runs, b.tiles,
+                           nruns, b.scal, b.sol, cap);
+    else
+        hipLaunchKernelGGL((k_verify<W, false>), dim3(ntiles), dim3(256), 0, st, p,
+                           (const Rec<W> *)b.rec[0], (const Rec<W> *)b.rec[1], b.runs, b.tiles,
+                           nruns, b.scal, b.sol, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_verify(const Plan &p, const DevBufs &b, uint32_t nruns, uint32_t ntiles,
+                         uint64_t cap, int check_key, hipStream_t st) {
+    if (ntiles == 0) return hipSuccess;
+    MSP_DISPATCH_W(p.W, return verify_impl<WW>(p, b, nruns, ntiles, cap, check_key, st));
+    return hipSuccess;
+}
+
+}  // namespace msp

@@ -1,0 +1,70 @@
+"""Writes tests/golden/oracle_configs.json: oracle results for the named
+workloads, computed only by the CPU oracle (oracle/).  Run from the repo
+root:  python tests/golden/make_golden.py
+
+Small workloads are solved whole with the heap Schroeppel-Shamir oracle;
+the large ones are sampled: the meet-in-the-middle oracle solves single
+residue classes of the left key modulo 2^k, which the GPU path reproduces
+with slice_mod = 2^k, slice_res = rho.  Planted twins sample the class that
+holds x*.
+"""
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle import oracle as O  # noqa: E402
+from paper_2507_05045_amd.inputs import make_instance  # noqa: E402
+
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_configs.json")
+
+
+def entry(inst, r, res, slice_mod=0, slice_res=0, routine=""):
+    return dict(name=inst.name, m=inst.m, n=inst.n, seed=inst.seed,
+                planted=inst.planted is not None, key_rows=r, slice_mod=slice_mod,
+                slice_res=slice_res, H=str(res.H), nsol=res.nsol,
+                solutions=["".join(str(int(v)) for v in s) for s in res.solutions],
+                routine=routine)
+
+
+def main():
+    out = []
+    t0 = time.time()
+    for (m, n) in [(4, 30), (6, 50)]:
+        for planted in (False, True):
+            inst = make_instance(m, n, 0, planted=planted)
+            out.append(entry(inst, 1, O.ss_heap(inst.A, inst.d, 1), routine="ss_heap"))
+            print(inst.name, out[-1]["H"], out[-1]["nsol"], f"{time.time() - t0:.1f}s", flush=True)
+    sampled = [((8, 70), 20, [0, 1, 2, 3, 4], [12345, 777777]),
+               ((9, 80), 24, [0], [12345]),
+               ((10, 90), 26, [0], [12345])]
+    for (m, n), lm, seeds, rhos in sampled:
+        mod = 1 << lm
+        for s in seeds:
+            inst = make_instance(m, n, s)
+            for rho in rhos:
+                res = O.mitm(inst.A, inst.d, 4, lm, rho, rho + 1)
+                out.append(entry(inst, 4, res, mod, rho, routine=f"mitm mod 2^{lm}"))
+                print(inst.name, rho, out[-1]["H"], out[-1]["nsol"], f"{time.time() - t0:.1f}s",
+                      flush=True)
+        # planted twin of seed 0; for (10,90) x* is drawn inside the 1/64
+        # slice k_L(x*) mod 64 == 0 of that workload.
+        acc = None
+        if (m, n) == (10, 90):
+            probe = make_instance(m, n, 0)
+            acc = lambda x: O.left_key(probe.A, probe.d, x, 4) % 64 == 0  # noqa: E731
+        inst = make_instance(m, n, 0, planted=True, accept=acc)
+        rho = O.left_key(inst.A, inst.d, inst.planted, 4) % mod
+        res = O.mitm(inst.A, inst.d, 4, lm, rho, rho + 1)
+        out.append(entry(inst, 4, res, mod, rho, routine=f"mitm mod 2^{lm}"))
+        print(inst.name, rho, out[-1]["H"], out[-1]["nsol"], f"{time.time() - t0:.1f}s", flush=True)
+    with open(OUT, "w") as f:
+        json.dump(out, f, indent=1)
+    print("wrote", OUT)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,74 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/msp.h declares, and validates instances before touching a GPU."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "msp.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(msp_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for want in ("msp_create", "msp_solve", "msp_hits", "msp_get_solutions", "msp_destroy"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2507_05045_amd import msp
+    for name in declared_functions():
+        assert hasattr(msp.lib, name), name
+    assert set(declared_functions()) == set(msp.EXPORTS)
+
+
+def test_create_validates():
+    from paper_2507_05045_amd import msp
+    with pytest.raises(msp.MspError) as e:
+        msp.Context(-np.ones((2, 3)), [1, 1])
+    assert e.value.code == -1
+    with pytest.raises(msp.MspError) as e:
+        msp.Context(np.full((1, 3), 30000), [1])
+    assert e.value.code == -2
+    with pytest.raises(msp.MspError) as e:
+        msp.Context(np.ones((2, 93)), [1, 1])
+    assert e.value.code == -4
+    ctx = msp.Context(np.ones((2, 5)), [2, 2])
+    with pytest.raises(msp.MspError) as e:
+        ctx.hits()                                   # nothing solved yet
+    assert e.value.code == -9
+    ctx.close()
+
+
+def test_workspace_query_and_key_overflow():
+    from paper_2507_05045_amd import msp
+    ctx = msp.Context(np.full((9, 90), 99), [4455] * 9)
+    assert ctx.workspace_bytes(msp.msp_default_opts(key_rows=4)) > 0
+    assert ctx.workspace_bytes(msp.msp_default_opts(key_rows=5)) == 0   # key overflows int64
+    # A budget too small to hold even the quarter lists cannot be met.
+    assert ctx.workspace_bytes(msp.msp_default_opts(key_rows=4, workspace_bytes=1 << 20)) == 0
+    ctx.close()
+
+
+def test_strerror_names_codes():
+    from paper_2507_05045_amd import msp
+    assert "row sum" in msp.strerror(-2)
+    assert msp.strerror(0) == "ok"
+
+
+@pytest.mark.skipif(os.path.exists("/dev/kfd"), reason="a GPU is present")
+def test_solve_without_gpu_fails_loudly():
+    from paper_2507_05045_amd import msp
+    ctx = msp.Context(np.ones((1, 4)), [2])
+    with pytest.raises(msp.MspError) as e:
+        ctx.solve(use_torch=False)
+    assert e.value.code == -10
+    ctx.close()
