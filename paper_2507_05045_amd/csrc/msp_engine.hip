@@ -169,8 +169,11 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
     z.ncells = T / (uint64_t)p.kstep;
 
     // Window: enough cells that one launch fills the chip, bounded by memory.
-    const uint64_t est_cell = std::max<uint64_t>(
-        1, std::max((uint64_t)p.Q[0] * p.Q[1], (uint64_t)p.Q[2] * p.Q[3]) / T);
+    // Records per cell: at most Q_A*Q_B over all T cells; a slice finer
+    // than the cells keeps only 1/(slice_mod/T) of a cell.
+    const uint64_t all_rec = std::max((uint64_t)p.Q[0] * p.Q[1], (uint64_t)p.Q[2] * p.Q[3]);
+    const uint64_t thin = (o.slice_mod > 0 && (uint64_t)o.slice_mod > T) ? (uint64_t)o.slice_mod / T : 1;
+    const uint64_t est_cell = std::max<uint64_t>(1, all_rec / T / thin);
     const uint64_t rb = rec_bytes(p.W), qb = qrec_bytes(p.W);
     const int F = 1 << p.log2F;
     z.sol_cap = o.max_solutions ? o.max_solutions : ((uint64_t)1 << 20);
@@ -178,12 +181,11 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
     // side (each pair lands in exactly one cell); smaller windows get a 25%
     // margin per cell, and the count pass checks the real totals anyway.
     const uint64_t hard_cap = ((uint64_t)1 << 31) - 1;
-    const uint64_t all_rec = std::max((uint64_t)p.Q[0] * p.Q[1], (uint64_t)p.Q[2] * p.Q[3]);
     const uint64_t per_cell = est_cell + est_cell / 4 + 1;
     uint64_t want = o.window_records ? o.window_records : ((uint64_t)1 << 30);
     want = std::min(std::max<uint64_t>(want, per_cell + 1024), hard_cap);
     uint64_t kwin;
-    if (all_rec <= want && !o.window_records) {
+    if (std::min(all_rec, z.ncells * per_cell) <= want && !o.window_records) {
         kwin = z.ncells;
     } else {
         kwin = std::max<uint64_t>(1, std::min<uint64_t>(z.ncells, want / per_cell));
@@ -218,8 +220,7 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
         return off;
     };
     auto cap_for = [&](uint64_t kw) {
-        if (kw == z.ncells) return std::min<uint64_t>(hard_cap, all_rec);
-        return std::min<uint64_t>(hard_cap, kw * per_cell + 1024);
+        return std::min<uint64_t>(hard_cap, std::min<uint64_t>(all_rec, kw * per_cell + 1024));
     };
     uint64_t cap_rec = cap_for(kwin);
     uint64_t total = layout(cap_rec, kwin);

@@ -11,7 +11,6 @@ constexpr int kMaxWords = 5;        // packed uint16 non-key rows: up to 10 rows
 constexpr int kMaxFine = 4096;      // fine buckets per residue cell (LDS counters)
 constexpr int kJoinCap = 2048;      // left records per bucket held in LDS by the join
 constexpr int kJoinSlots = 4096;    // LDS hash slots of the join (power of two)
-constexpr int kTileR = 2048;        // right records per verify tile (256 lanes x 8)
 constexpr int kTileL = 4096;        // left records per verify tile
 constexpr int kThreads = 256;
 

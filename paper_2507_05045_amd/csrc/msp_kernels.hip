@@ -17,6 +17,8 @@
 // enumerated pair lands in the cell being built.
 #include "msp_internal.h"
 
+#include <stdlib.h>
+
 namespace msp {
 
 // ---------------------------------------------------------------------------
@@ -260,12 +262,12 @@ __global__ __launch_bounds__(256) void k_exact_runs(Plan p, const uint32_t *__re
 }
 
 __global__ void k_tile_counts(const RunPair *__restrict__ runs, const uint64_t *__restrict__ scal,
-                              uint32_t *tiles) {
+                              uint32_t *tiles, uint32_t tile_r) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t n = scal[S_NRUNS];
     if (i >= n) return;
     const RunPair r = runs[i];
-    tiles[i] = ((r.nl + kTileL - 1) / kTileL) * ((r.nr + kTileR - 1) / kTileR);
+    tiles[i] = ((r.nl + kTileL - 1) / kTileL) * ((r.nr + tile_r - 1) / tile_r);
 }
 
 __device__ __forceinline__ void emit_solution(uint64_t *sol, uint64_t cap, uint64_t *ctr,
@@ -393,23 +395,40 @@ __global__ __launch_bounds__(256) void k_hash_join(Plan p, const uint32_t *__res
 
 // ---------------------------------------------------------------------------
 // Tiled verify of equal-key run pairs (exact buckets), or of oversized hash
-// buckets with the key compared per pair (CK).  Tile = kTileL left x kTileR
-// right records.  Each lane holds 8 right words; left words are staged in
-// LDS and read as broadcasts; a wave-wide ballot OR flags candidate pairs,
-// which are then checked in full.
+// buckets with the key compared per pair (CK).  Tile = kTileL left x 256*kKR
+// right records.  Each lane holds kKR right records as 32-bit fingerprints of
+// their packed non-key rows; left fingerprints are staged in LDS and read
+// as broadcasts, 4 at a time.  Equal vectors have equal fingerprints, so a
+// wave-wide ballot OR over 4 x 8 compares flags every candidate group; the
+// (rare) flagged groups are then checked in full, word by word.
 // ---------------------------------------------------------------------------
 
-constexpr int kKR = kTileR / 256;     // right records per lane
 constexpr int kChunk = 1024;          // left records per LDS stage
 
-template <int W, bool CK>
+// Fingerprint of a packed row vector: the word itself for one word, else a
+// multiplicative mix of all words.  Only equality of fingerprints is used,
+// as a filter in front of the exact word-by-word compare.
+template <int W>
+__device__ __forceinline__ uint32_t fingerprint(const uint32_t *v) {
+    if (W <= 1) return v[0];
+    uint32_t h = v[0] * 0x9E3779B1u;
+#pragma unroll
+    for (int w = 1; w < W; ++w) {
+        h ^= h >> 15;
+        h = (h + v[w]) * 0x85EBCA77u;
+    }
+    h ^= h >> 13;
+    return h;
+}
+
+template <int W, bool CK, int kKR>
 __global__ __launch_bounds__(256) void k_verify(Plan p, const Rec<W> *__restrict__ L,
                                                 const Rec<W> *__restrict__ R,
                                                 const RunPair *__restrict__ runs,
                                                 const uint32_t *__restrict__ toff,
                                                 uint32_t nruns, uint64_t *scal, uint64_t *sol,
                                                 uint64_t cap) {
-    __shared__ __attribute__((aligned(16))) uint32_t s_lw[kChunk];
+    __shared__ __attribute__((aligned(16))) uint32_t s_fp[kChunk];
     __shared__ int64_t s_lk[CK ? kChunk : 1];
     __shared__ uint64_t s_s4[4];
     const uint32_t tile = blockIdx.x;
@@ -421,27 +440,15 @@ __global__ __launch_bounds__(256) void k_verify(Plan p, const Rec<W> *__restrict
     }
     const RunPair rp = runs[lo];
     const uint32_t loc = tile - toff[lo];
-    const uint32_t tr_n = (rp.nr + kTileR - 1) / kTileR;
+    constexpr uint32_t kTR = 256u * kKR;       // right records per tile
+    const uint32_t tr_n = (rp.nr + kTR - 1) / kTR;
     const uint32_t tl = loc / tr_n, tr = loc % tr_n;
     const uint32_t lb = rp.l0 + tl * kTileL;
     const uint32_t le = min(rp.l0 + rp.nl, lb + (uint32_t)kTileL);
-    const uint32_t rb = rp.r0 + tr * kTileR;
-    const uint32_t re = min(rp.r0 + rp.nr, rb + (uint32_t)kTileR);
+    const uint32_t rb = rp.r0 + tr * kTR;
+    const uint32_t re = min(rp.r0 + rp.nr, rb + kTR);
     const int t = threadIdx.x;
 
-    uint32_t rw[kKR];
-    int64_t rk[CK ? kKR : 1];
-#pragma unroll
-    for (int k = 0; k < kKR; ++k) {
-        const uint32_t ri = rb + k * 256 + t;
-        rw[k] = 0xFFFFFFFFu;                      // never equals a left word
-        if (CK) rk[k] = -1;                       // never equals a left key
-        if (ri < re) {
-            rw[k] = W > 0 ? R[ri].vec[0] : 0u;
-            if (CK) rk[k] = R[ri].key;
-        }
-    }
-    uint64_t hits = 0;
     if (W == 0 && !CK) {
         // Every pair is a solution: store while there is room.
         for (uint32_t li = lb; li < le; ++li) {
@@ -454,52 +461,69 @@ __global__ __launch_bounds__(256) void k_verify(Plan p, const Rec<W> *__restrict
         }
         return;
     }
+
+    uint32_t rf[kKR];
+    int64_t rk[CK ? kKR : 1];
+#pragma unroll
+    for (int k = 0; k < kKR; ++k) {
+        const uint32_t ri = rb + k * 256 + t;
+        rf[k] = 0u;
+        if (CK) rk[k] = -1;                       // never equals a left key (>= 0)
+        if (ri < re) {
+            if (W > 0) rf[k] = fingerprint<W>(R[ri].vec);
+            if (CK) rk[k] = R[ri].key;
+        }
+    }
+    // Full check of a flagged (left j, right slot k) pair.
+    auto check = [&](uint32_t li, int k) {
+        const uint32_t ri = rb + k * 256 + t;
+        if (ri >= re) return;
+        const Rec<W> ll = L[li];
+        const Rec<W> rr = R[ri];
+        if (rows_match<W>(ll, rr)) emit_solution(sol, cap, &scal[S_NSOL], ll.mask, rr.mask);
+    };
+    uint64_t hits = 0;
     for (uint32_t c0 = lb; c0 < le; c0 += kChunk) {
         const uint32_t cn = min((uint32_t)kChunk, le - c0);
         __syncthreads();
         for (uint32_t i = t; i < cn; i += 256) {
-            s_lw[i] = W > 0 ? L[c0 + i].vec[0] : 0u;
+            s_fp[i] = W > 0 ? fingerprint<W>(L[c0 + i].vec) : 0u;
             if (CK) s_lk[i] = L[c0 + i].key;
         }
         __syncthreads();
         if (!CK) {
-            uint64_t acc = 0;
             uint32_t j = 0;
             for (; j + 4 <= cn; j += 4) {
-                const uint4 q = *reinterpret_cast<const uint4 *>(&s_lw[j]);
+                const uint4 q = *reinterpret_cast<const uint4 *>(&s_fp[j]);
+                uint64_t acc = 0;
 #pragma unroll
-                for (int k = 0; k < kKR; ++k) acc |= __builtin_amdgcn_ballot_w64(rw[k] == q.x);
+                for (int k = 0; k < kKR; ++k) acc |= __builtin_amdgcn_ballot_w64(rf[k] == q.x);
 #pragma unroll
-                for (int k = 0; k < kKR; ++k) acc |= __builtin_amdgcn_ballot_w64(rw[k] == q.y);
+                for (int k = 0; k < kKR; ++k) acc |= __builtin_amdgcn_ballot_w64(rf[k] == q.y);
 #pragma unroll
-                for (int k = 0; k < kKR; ++k) acc |= __builtin_amdgcn_ballot_w64(rw[k] == q.z);
+                for (int k = 0; k < kKR; ++k) acc |= __builtin_amdgcn_ballot_w64(rf[k] == q.z);
 #pragma unroll
-                for (int k = 0; k < kKR; ++k) acc |= __builtin_amdgcn_ballot_w64(rw[k] == q.w);
-            }
-            for (; j < cn; ++j) {
-                const uint32_t x = s_lw[j];
-#pragma unroll
-                for (int k = 0; k < kKR; ++k) acc |= __builtin_amdgcn_ballot_w64(rw[k] == x);
-            }
-            if (acc) {
-                // Rare: some lane saw equal first words.  Check those pairs fully.
-                for (uint32_t jj = 0; jj < cn; ++jj) {
-                    const uint32_t x = s_lw[jj];
+                for (int k = 0; k < kKR; ++k) acc |= __builtin_amdgcn_ballot_w64(rf[k] == q.w);
+                if (__builtin_expect(acc != 0, 0)) {
 #pragma unroll
                     for (int k = 0; k < kKR; ++k) {
-                        if (rw[k] == x) {
-                            const Rec<W> ll = L[c0 + jj];
-                            const Rec<W> rr = R[rb + k * 256 + t];
-                            if (rows_match<W>(ll, rr))
-                                emit_solution(sol, cap, &scal[S_NSOL], ll.mask, rr.mask);
-                        }
+                        if (rf[k] == q.x) check(c0 + j, k);
+                        if (rf[k] == q.y) check(c0 + j + 1, k);
+                        if (rf[k] == q.z) check(c0 + j + 2, k);
+                        if (rf[k] == q.w) check(c0 + j + 3, k);
                     }
                 }
+            }
+            for (; j < cn; ++j) {
+                const uint32_t x = s_fp[j];
+#pragma unroll
+                for (int k = 0; k < kKR; ++k)
+                    if (rf[k] == x) check(c0 + j, k);
             }
         } else {
             for (uint32_t jj = 0; jj < cn; ++jj) {
                 const int64_t lk = s_lk[jj];
-                const uint32_t x = s_lw[jj];
+                const uint32_t x = s_fp[jj];
 #pragma unroll
                 for (int k = 0; k < kKR; ++k) {
                     if (rk[k] == lk) {
@@ -509,11 +533,8 @@ __global__ __launch_bounds__(256) void k_verify(Plan p, const Rec<W> *__restrict
                             if (scal[S_STORED] < cap)
                                 emit_solution(sol, cap, &scal[S_STORED], L[c0 + jj].mask,
                                               R[rb + k * 256 + t].mask);
-                        } else if (rw[k] == x) {
-                            const Rec<W> ll = L[c0 + jj];
-                            const Rec<W> rr = R[rb + k * 256 + t];
-                            if (rows_match<W>(ll, rr))
-                                emit_solution(sol, cap, &scal[S_NSOL], ll.mask, rr.mask);
+                        } else if (rf[k] == x) {
+                            check(c0 + jj, k);
                         }
                     }
                 }
@@ -716,10 +737,22 @@ hipError_t launch_hash_join(const Plan &p, const DevBufs &b, int32_t K, uint64_t
     return hipSuccess;
 }
 
-hipError_t launch_tile_counts(const Plan &, const DevBufs &b, uint32_t nruns, int, hipStream_t st) {
+// Right records per lane of the tiled verify: 8 by default (tile 2048),
+// MSP_VERIFY_KR=16 selects tiles of 4096 right records.
+int verify_kr() {
+    static int kr = [] {
+        const char *e = getenv("MSP_VERIFY_KR");
+        return (e && atoi(e) == 16) ? 16 : 8;
+    }();
+    return kr;
+}
+
+hipError_t launch_tile_counts(const Plan &, const DevBufs &b, uint32_t nruns, int ck,
+                              hipStream_t st) {
     if (nruns == 0) return hipSuccess;
+    const uint32_t tile_r = 256u * (ck ? 8 : verify_kr());
     hipLaunchKernelGGL(k_tile_counts, dim3((nruns + 255) / 256), dim3(256), 0, st, b.runs, b.scal,
-                       b.tiles);
+                       b.tiles, tile_r);
     return hipGetLastError();
 }
 
@@ -727,11 +760,15 @@ template <int W>
 static hipError_t verify_impl(const Plan &p, const DevBufs &b, uint32_t nruns, uint32_t ntiles,
                               uint64_t cap, int ck, hipStream_t st) {
     if (ck)
-        hipLaunchKernelGGL((k_verify<W, true>), dim3(ntiles), dim3(256), 0, st, p,
+        hipLaunchKernelGGL((k_verify<W, true, 8>), dim3(ntiles), dim3(256), 0, st, p,
+                           (const Rec<W> *)b.rec[0], (const Rec<W> *)b.rec[1], b.runs, b.tiles,
+                           nruns, b.scal, b.sol, cap);
+    else if (verify_kr() == 16)
+        hipLaunchKernelGGL((k_verify<W, false, 16>), dim3(ntiles), dim3(256), 0, st, p,
                            (const Rec<W> *)b.rec[0], (const Rec<W> *)b.rec[1], b.runs, b.tiles,
                            nruns, b.scal, b.sol, cap);
     else
-        hipLaunchKernelGGL((k_verify<W, false>), dim3(ntiles), dim3(256), 0, st, p,
+        hipLaunchKernelGGL((k_verify<W, false, 8>), dim3(ntiles), dim3(256), 0, st, p,
                            (const Rec<W> *)b.rec[0], (const Rec<W> *)b.rec[1], b.runs, b.tiles,
                            nruns, b.scal, b.sol, cap);
     return hipGetLastError();
