@@ -148,8 +148,10 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
     if (o.log2_cells) {
         log2T = o.log2_cells;
     } else {
+        // |B_j| ~ 8 pairs per outer element, and at most 1024 fine buckets
+        // per cell (the staged scatter's LDS budget).
         log2T = std::max(p.qb - 3, 0);
-        log2T = std::max(log2T, log2M - 12);
+        log2T = std::max(log2T, log2M - 10);
     }
     log2T = std::min(log2T, log2M);
     if (log2M - log2T > 12) return MSP_E_INVALID;       // fine buckets per cell <= 4096

@@ -18,6 +18,10 @@
 #include "msp_internal.h"
 
 #include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cstring>
 
 namespace msp {
 
@@ -232,6 +236,167 @@ __global__ __launch_bounds__(256) void k_bucket(Plan p, const QRec<W> *__restric
     }
 }
 
+// Exclusive scan of a[0 .. n) in LDS (n a multiple of 256, at most 2048) by
+// a 256-thread block; returns the total.
+template <typename T>
+__device__ uint32_t block_excl_scan_rt(T *a, int n, uint32_t *w4) {
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int E = n >> 8;
+    uint32_t loc[16];
+    uint32_t s = 0;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        loc[e] = e < E ? (uint32_t)a[t * E + e] : 0u;
+        s += loc[e];
+    }
+    const uint32_t inc = wave_incl_scan(s);
+    if (lane == 63) w4[wave] = inc;
+    __syncthreads();
+    uint32_t wbase = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const uint32_t x = w4[w];
+        if (w < wave) wbase += x;
+        total += x;
+    }
+    uint32_t run = wbase + inc - s;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        if (e < E) { a[t * E + e] = (T)run; run += loc[e]; }
+    }
+    __syncthreads();
+    return total;
+}
+
+// Bucket scatter staged through LDS.  The work-group enumerates its pairs in
+// batches; each batch is counting-sorted by fine bucket in LDS and written
+// out so that consecutive lanes store consecutive records of one bucket
+// (full cache lines instead of one partial line per record).
+constexpr int kStageAC = 1024;            // outer elements per chunk (max)
+constexpr int kStageMaxF = 1024;          // fine buckets handled by the staged path
+
+template <int W>
+constexpr int stage_batch() { return (int)(49152 / sizeof(Rec<W>)) & ~255; }   // ~48 KB of records
+
+template <int W>
+__global__ __launch_bounds__(256) void k_scatter_staged(Plan p, const QRec<W> *__restrict__ A,
+                                                        const QRec<W> *__restrict__ B,
+                                                        const uint32_t *__restrict__ offB,
+                                                        const QRec<W> *__restrict__ Cq,
+                                                        const QRec<W> *__restrict__ Dq,
+                                                        const uint32_t *__restrict__ offD,
+                                                        const uint32_t *__restrict__ offL,
+                                                        const uint32_t *__restrict__ offR,
+                                                        Rec<W> *recL, Rec<W> *recR, int64_t idx0,
+                                                        int ac) {
+    constexpr int BATCH = stage_batch<W>();
+    __shared__ uint32_t s_cur[kStageMaxF];
+    __shared__ uint32_t s_cnt[kStageMaxF];
+    __shared__ Rec<W> s_rec[BATCH];
+    __shared__ uint16_t s_f[BATCH];
+    __shared__ uint16_t s_perm[BATCH];
+    __shared__ uint32_t s_pre[kStageAC + 1];
+    __shared__ uint32_t s_b0[kStageAC];
+    __shared__ uint32_t s_w4[4];
+    const int side = blockIdx.y;
+    const int P = p.parts;
+    const int cw = blockIdx.x / P, part = blockIdx.x % P;
+    const int t = threadIdx.x;
+    const uint32_t T = 1u << p.log2T;
+    const int F = 1 << p.log2F;
+    const int Fs = F < 256 ? 256 : F;            // scan length (multiple of 256)
+    const int64_t M1 = ((int64_t)1 << p.log2M) - 1;
+    const uint32_t k = (uint32_t)(p.kfirst + (idx0 + cw) * p.kstep) & (T - 1);
+    const QRec<W> *outer = side ? Cq : A;
+    const QRec<W> *inner = side ? Dq : B;
+    const uint32_t *ioff = side ? offD : offB;
+    const uint64_t Qo = side ? p.Q[2] : p.Q[0];
+    const int sh = side ? p.qc : p.qa;
+    const uint32_t *offs = side ? offR : offL;
+    Rec<W> *rec = side ? recR : recL;
+    const uint64_t base = ((uint64_t)cw * F) * P + part;
+    for (int f = t; f < F; f += 256) s_cur[f] = offs[base + (uint64_t)f * P];
+    const uint64_t lo = Qo * part / P, hi = Qo * (part + 1) / P;
+    const int64_t smod1 = p.slice_mod - 1;
+    const int per = ac >> 8;                     // outer elements per thread per chunk
+    for (uint64_t c0 = lo; c0 < hi; c0 += ac) {
+        // Pair counts of this chunk's outer elements, scanned into s_pre.
+        __syncthreads();
+        uint32_t nloc[4];
+        uint32_t mysum = 0;
+        for (int e = 0; e < per; ++e) {
+            const uint64_t i = c0 + (uint64_t)t * per + e;
+            uint32_t n = 0, b0 = 0;
+            if (i < hi) {
+                const uint32_t ca = (uint32_t)outer[i].key & (T - 1);
+                const uint32_t j = side ? ((ca - k) & (T - 1)) : ((k - ca) & (T - 1));
+                b0 = ioff[j];
+                n = ioff[j + 1] - b0;
+            }
+            s_b0[t * per + e] = b0;
+            nloc[e] = n;
+            mysum += n;
+        }
+        const uint32_t inc = wave_incl_scan(mysum);
+        if ((t & 63) == 63) s_w4[t >> 6] = inc;
+        __syncthreads();
+        uint32_t run = inc - mysum, total = 0;
+        for (int w = 0; w < 4; ++w) {
+            if (w < (t >> 6)) run += s_w4[w];
+            total += s_w4[w];
+        }
+        for (int e = 0; e < per; ++e) { s_pre[t * per + e] = run; run += nloc[e]; }
+        if (t == 0) s_pre[ac] = total;
+        __syncthreads();
+        for (uint32_t P0 = 0; P0 < total; P0 += BATCH) {
+            const uint32_t nb = min((uint32_t)BATCH, total - P0);
+            // Generate the batch (pair index -> outer element by binary search).
+            for (uint32_t o = t; o < nb; o += 256) {
+                const uint32_t pi = P0 + o;
+                int lo2 = 0, hi2 = ac;                     // last slot with s_pre <= pi
+                while (hi2 - lo2 > 1) {
+                    const int mid = (lo2 + hi2) >> 1;
+                    if (s_pre[mid] <= pi) lo2 = mid; else hi2 = mid;
+                }
+                const QRec<W> a = outer[c0 + lo2];
+                const QRec<W> b = inner[s_b0[lo2] + (pi - s_pre[lo2])];
+                const int64_t key = side ? a.key - b.key : a.key + b.key;
+                bool keep = side ? key >= 0 : key <= p.Kd;
+                if (p.slice_mod) keep = keep && ((key & smod1) == p.slice_res);
+                Rec<W> r;
+                r.key = key;
+                r.mask = (uint64_t)a.mask | ((uint64_t)b.mask << sh);
+#pragma unroll
+                for (int w = 0; w < (W > 0 ? W : 1); ++w)
+                    r.vec[w] = side ? resid_word(p.dpk[w], a.vec[w], b.vec[w]) : a.vec[w] + b.vec[w];
+                s_rec[o] = r;
+                s_f[o] = keep ? (uint16_t)((key & M1) >> p.log2T) : (uint16_t)0xFFFF;
+            }
+            for (int f = t; f < Fs; f += 256) s_cnt[f] = 0;
+            __syncthreads();
+            for (uint32_t o = t; o < nb; o += 256)
+                if (s_f[o] != 0xFFFF) atomicAdd(&s_cnt[s_f[o]], 1u);
+            __syncthreads();
+            const uint32_t nvalid = block_excl_scan_rt<uint32_t>(s_cnt, Fs, s_w4);
+            // Rank within the batch; afterwards s_cnt[f] = end of group f.
+            for (uint32_t o = t; o < nb; o += 256) {
+                const uint32_t f = s_f[o];
+                if (f != 0xFFFF) s_perm[atomicAdd(&s_cnt[f], 1u)] = (uint16_t)o;
+            }
+            __syncthreads();
+            for (uint32_t o = t; o < nvalid; o += 256) {
+                const uint32_t slot = s_perm[o];
+                const uint32_t f = s_f[slot];
+                const uint32_t start = f ? s_cnt[f - 1] : 0u;
+                rec[s_cur[f] + (o - start)] = s_rec[slot];
+            }
+            __syncthreads();
+            for (int f = t; f < F; f += 256) s_cur[f] += s_cnt[f] - (f ? s_cnt[f - 1] : 0u);
+            __syncthreads();
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Exact buckets (M > K_d): a bucket is one key value, so the whole bucket pair
 // is one equal-key run pair (the E_A x E_C groups of Algorithm 1).
@@ -306,10 +471,11 @@ __global__ __launch_bounds__(256) void k_hash_join(Plan p, const uint32_t *__res
                                                    const Rec<W> *__restrict__ L,
                                                    const Rec<W> *__restrict__ R, RunPair *runs,
                                                    uint64_t *scal, uint64_t *sol, uint64_t cap) {
+    // s_tab[h] = (representative left index << 16) | count, then | group end.
+    constexpr uint32_t kEmpty = 0xFFFF0000u;
+    constexpr int kPre = 4;                              // right records preloaded per lane
     __shared__ int64_t s_key[kJoinCap];
-    __shared__ uint32_t s_v0[kJoinCap];
-    __shared__ int32_t s_head[kJoinSlots];
-    __shared__ uint32_t s_start[kJoinSlots];
+    __shared__ uint32_t s_tab[kJoinSlots];
     __shared__ uint16_t s_slot[kJoinCap];
     __shared__ uint16_t s_grp[kJoinCap];
     __shared__ uint32_t s_w4[4];
@@ -328,67 +494,91 @@ __global__ __launch_bounds__(256) void k_hash_join(Plan p, const uint32_t *__res
         return;
     }
     const int t = threadIdx.x;
-    for (int i = t; i < kJoinSlots; i += 256) { s_head[i] = -1; s_start[i] = 0; }
-    for (uint32_t i = t; i < nl; i += 256) {
-        s_key[i] = L[l0 + i].key;
-        s_v0[i] = W > 0 ? L[l0 + i].vec[0] : 0u;
-    }
+    // Issue the right-side loads first; they are consumed after the build.
+    Rec<W> rr[kPre];
+#pragma unroll
+    for (int e = 0; e < kPre; ++e)
+        if ((uint32_t)(t + 256 * e) < nr) rr[e] = R[r0 + t + 256 * e];
+    uint32_t slots = 256;
+    while (slots < 2 * nl) slots <<= 1;
+    const uint32_t smask = slots - 1;
+    for (uint32_t i = t; i < slots; i += 256) s_tab[i] = kEmpty;
+    for (uint32_t i = t; i < nl; i += 256) s_key[i] = L[l0 + i].key;
     __syncthreads();
-    // Insert: one representative per distinct key, count per slot.
+    // Build: one representative per distinct key, count per slot.
     for (uint32_t i = t; i < nl; i += 256) {
         const int64_t k = s_key[i];
-        uint32_t h = key_hash(k) & (kJoinSlots - 1);
+        uint32_t h = key_hash(k) & smask;
         for (;;) {
-            int cur = s_head[h];
-            if (cur < 0) {
-                const int old = atomicCAS(&s_head[h], -1, (int)i);
-                if (old < 0) break;
-                cur = old;
+            uint32_t w = s_tab[h];
+            if (w == kEmpty) {
+                const uint32_t old = atomicCAS(&s_tab[h], kEmpty, i << 16);
+                if (old == kEmpty) break;
+                w = old;
             }
-            if (s_key[cur] == k) break;
-            h = (h + 1) & (kJoinSlots - 1);
+            if (s_key[w >> 16] == k) break;
+            h = (h + 1) & smask;
         }
         s_slot[i] = (uint16_t)h;
-        atomicAdd(&s_start[h], 1u);
+        atomicAdd(&s_tab[h], 1u);
     }
     __syncthreads();
-    block_excl_scan_lds<kJoinSlots / 256>(s_start, s_w4);
-    // Group left records by slot; afterwards s_start[h] = end of group h.
+    {   // exclusive scan of the counts (low halves), heads kept
+        const int E = (int)(slots >> 8), lane = t & 63, wave = t >> 6;
+        uint32_t loc[16], sum = 0;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            loc[e] = e < E ? (s_tab[t * E + e] & 0xFFFFu) : 0u;
+            sum += loc[e];
+        }
+        const uint32_t inc = wave_incl_scan(sum);
+        if (lane == 63) s_w4[wave] = inc;
+        __syncthreads();
+        uint32_t run = inc - sum;
+        for (int w = 0; w < wave; ++w) run += s_w4[w];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            if (e < E) {
+                s_tab[t * E + e] = (s_tab[t * E + e] & 0xFFFF0000u) | run;
+                run += loc[e];
+            }
+        }
+        __syncthreads();
+    }
+    // Group left records by slot; afterwards the low half is the group end.
     for (uint32_t i = t; i < nl; i += 256) {
-        const uint32_t pos = atomicAdd(&s_start[s_slot[i]], 1u);
+        const uint32_t pos = atomicAdd(&s_tab[s_slot[i]], 1u) & 0xFFFFu;
         s_grp[pos] = (uint16_t)i;
     }
     __syncthreads();
     uint64_t hits = 0;
-    for (uint32_t j = t; j < nr; j += 256) {
-        const Rec<W> rr = R[r0 + j];
-        uint32_t h = key_hash(rr.key) & (kJoinSlots - 1);
-        int found = -1;
+    auto probe = [&](const Rec<W> &r) {
+        uint32_t h = key_hash(r.key) & smask;
         for (;;) {
-            const int cur = s_head[h];
-            if (cur < 0) break;
-            if (s_key[cur] == rr.key) { found = (int)h; break; }
-            h = (h + 1) & (kJoinSlots - 1);
+            const uint32_t w = s_tab[h];
+            if (w == kEmpty) return;
+            if (s_key[w >> 16] == r.key) break;
+            h = (h + 1) & smask;
         }
-        if (found < 0) continue;
-        const uint32_t ge = s_start[found], gs = found ? s_start[found - 1] : 0u;
+        const uint32_t ge = s_tab[h] & 0xFFFFu, gs = h ? (s_tab[h - 1] & 0xFFFFu) : 0u;
         hits += ge - gs;
         if (W == 0) {
             atomicAdd((unsigned long long *)&scal[S_NSOL], (unsigned long long)(ge - gs));
             for (uint32_t q = gs; q < ge; ++q) {
                 if (scal[S_STORED] >= cap) break;
-                const uint32_t li = s_grp[q];
-                emit_solution(sol, cap, &scal[S_STORED], L[l0 + li].mask, rr.mask);
+                emit_solution(sol, cap, &scal[S_STORED], L[l0 + s_grp[q]].mask, r.mask);
             }
         } else {
             for (uint32_t q = gs; q < ge; ++q) {
-                const uint32_t li = s_grp[q];
-                if (s_v0[li] != rr.vec[0]) continue;
-                const Rec<W> ll = L[l0 + li];
-                if (rows_match<W>(ll, rr)) emit_solution(sol, cap, &scal[S_NSOL], ll.mask, rr.mask);
+                const Rec<W> ll = L[l0 + s_grp[q]];
+                if (rows_match<W>(ll, r)) emit_solution(sol, cap, &scal[S_NSOL], ll.mask, r.mask);
             }
         }
-    }
+    };
+#pragma unroll
+    for (int e = 0; e < kPre; ++e)
+        if ((uint32_t)(t + 256 * e) < nr) probe(rr[e]);
+    for (uint32_t j = t + 256 * kPre; j < nr; j += 256) probe(R[r0 + j]);
     const uint64_t tot = block_sum_u64(hits, s_s4);
     if (t == 0) add_u128(&scal[S_H_LO], &scal[S_H_HI], tot);
 }
@@ -708,8 +898,35 @@ hipError_t launch_count(const Plan &p, const DevBufs &b, int64_t idx0, int32_t K
     return hipSuccess;
 }
 
+template <int W>
+static hipError_t staged_impl(const Plan &p, const DevBufs &b, int64_t idx0, int32_t K,
+                              hipStream_t st) {
+    // Outer elements per chunk: enough pairs to fill about one batch.
+    const uint64_t T = (uint64_t)1 << p.log2T;
+    const uint64_t avg = std::max<uint64_t>(1, std::min((uint64_t)p.Q[1], (uint64_t)p.Q[3]) / T);
+    const int ac = avg >= 8 ? 256 : avg >= 4 ? 512 : 1024;
+    dim3 grid((uint32_t)K * p.parts, 2);
+    hipLaunchKernelGGL(k_scatter_staged<W>, grid, dim3(256), 0, st, p,
+                       (const QRec<W> *)b.qsrt[0], (const QRec<W> *)b.qsrt[1], b.qcnt[1],
+                       (const QRec<W> *)b.qsrt[2], (const QRec<W> *)b.qsrt[3], b.qcnt[3],
+                       b.off[0], b.off[1], (Rec<W> *)b.rec[0], (Rec<W> *)b.rec[1], idx0, ac);
+    return hipGetLastError();
+}
+
+// MSP_SCATTER=direct selects the unstaged scatter (one store per record).
+static bool scatter_direct() {
+    static bool d = [] {
+        const char *e = getenv("MSP_SCATTER");
+        return e && std::strcmp(e, "direct") == 0;
+    }();
+    return d;
+}
+
 hipError_t launch_scatter(const Plan &p, const DevBufs &b, int64_t idx0, int32_t K,
                           hipStream_t st) {
+    if ((1 << p.log2F) <= kStageMaxF && !scatter_direct()) {
+        MSP_DISPATCH_W(p.W, return staged_impl<WW>(p, b, idx0, K, st));
+    }
     MSP_DISPATCH_W(p.W, return (bucket_impl<WW, true>(p, b, idx0, K, st)));
     return hipSuccess;
 }
