@@ -152,6 +152,7 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
         // per cell (the staged scatter's LDS budget).
         log2T = std::max(p.qb - 3, 0);
         log2T = std::max(log2T, log2M - 10);
+        if (log2T > 23) log2T = std::max(23, log2M - 12);   // cell tables <= 2^23
     }
     log2T = std::min(log2T, log2M);
     if (log2M - log2T > 12) return MSP_E_INVALID;       // fine buckets per cell <= 4096

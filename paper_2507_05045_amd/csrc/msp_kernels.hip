@@ -553,10 +553,12 @@ __global__ __launch_bounds__(256) void k_hash_join(Plan p, const uint32_t *__res
     __syncthreads();
     uint64_t hits = 0;
     auto probe = [&](const Rec<W> &r) {
+        // After the scan an empty slot keeps head 0xFFFF but its low half
+        // holds a running offset, so emptiness is read from the head half.
         uint32_t h = key_hash(r.key) & smask;
         for (;;) {
             const uint32_t w = s_tab[h];
-            if (w == kEmpty) return;
+            if ((w >> 16) == 0xFFFFu) return;
             if (s_key[w >> 16] == r.key) break;
             h = (h + 1) & smask;
         }
