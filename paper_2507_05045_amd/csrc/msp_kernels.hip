@@ -272,13 +272,12 @@ __device__ uint32_t block_excl_scan_rt(T *a, int n, uint32_t *w4) {
 // batches; each batch is counting-sorted by fine bucket in LDS and written
 // out so that consecutive lanes store consecutive records of one bucket
 // (full cache lines instead of one partial line per record).
-constexpr int kStageAC = 1024;            // outer elements per chunk (max)
 constexpr int kStageMaxF = 1024;          // fine buckets handled by the staged path
 
 template <int W>
 constexpr int stage_batch() { return (int)(49152 / sizeof(Rec<W>)) & ~255; }   // ~48 KB of records
 
-template <int W>
+template <int W, int PER>
 __global__ __launch_bounds__(256) void k_scatter_staged(Plan p, const QRec<W> *__restrict__ A,
                                                         const QRec<W> *__restrict__ B,
                                                         const uint32_t *__restrict__ offB,
@@ -287,16 +286,15 @@ __global__ __launch_bounds__(256) void k_scatter_staged(Plan p, const QRec<W> *_
                                                         const uint32_t *__restrict__ offD,
                                                         const uint32_t *__restrict__ offL,
                                                         const uint32_t *__restrict__ offR,
-                                                        Rec<W> *recL, Rec<W> *recR, int64_t idx0,
-                                                        int ac) {
+                                                        Rec<W> *recL, Rec<W> *recR, int64_t idx0) {
     constexpr int BATCH = stage_batch<W>();
+    constexpr int per = PER;                     // outer elements per thread per chunk
+    constexpr int WV = W > 0 ? W : 1;
     __shared__ uint32_t s_cur[kStageMaxF];
     __shared__ uint32_t s_cnt[kStageMaxF];
     __shared__ Rec<W> s_rec[BATCH];
     __shared__ uint16_t s_f[BATCH];
     __shared__ uint16_t s_perm[BATCH];
-    __shared__ uint32_t s_pre[kStageAC + 1];
-    __shared__ uint32_t s_b0[kStageAC];
     __shared__ uint32_t s_w4[4];
     const int side = blockIdx.y;
     const int P = p.parts;
@@ -318,61 +316,73 @@ __global__ __launch_bounds__(256) void k_scatter_staged(Plan p, const QRec<W> *_
     for (int f = t; f < F; f += 256) s_cur[f] = offs[base + (uint64_t)f * P];
     const uint64_t lo = Qo * part / P, hi = Qo * (part + 1) / P;
     const int64_t smod1 = p.slice_mod - 1;
-    const int per = ac >> 8;                     // outer elements per thread per chunk
-    for (uint64_t c0 = lo; c0 < hi; c0 += ac) {
-        // Pair counts of this chunk's outer elements, scanned into s_pre.
-        __syncthreads();
-        uint32_t nloc[4];
+    for (uint64_t c0 = lo; c0 < hi; c0 += (uint64_t)256 * per) {
+        // This thread's outer elements (per of them, consecutive) and the
+        // batch-relative offsets of their pairs.
+        QRec<W> av[PER];
+        uint32_t b0[PER], nn[PER];
         uint32_t mysum = 0;
+#pragma unroll
         for (int e = 0; e < per; ++e) {
             const uint64_t i = c0 + (uint64_t)t * per + e;
-            uint32_t n = 0, b0 = 0;
+            nn[e] = 0;
+            b0[e] = 0;
             if (i < hi) {
-                const uint32_t ca = (uint32_t)outer[i].key & (T - 1);
+                av[e] = outer[i];
+                const uint32_t ca = (uint32_t)av[e].key & (T - 1);
                 const uint32_t j = side ? ((ca - k) & (T - 1)) : ((k - ca) & (T - 1));
-                b0 = ioff[j];
-                n = ioff[j + 1] - b0;
+                b0[e] = ioff[j];
+                nn[e] = ioff[j + 1] - b0[e];
             }
-            s_b0[t * per + e] = b0;
-            nloc[e] = n;
-            mysum += n;
+            mysum += nn[e];
         }
         const uint32_t inc = wave_incl_scan(mysum);
+        __syncthreads();                          // previous chunk done with s_w4
         if ((t & 63) == 63) s_w4[t >> 6] = inc;
         __syncthreads();
-        uint32_t run = inc - mysum, total = 0;
+        uint32_t myoff = inc - mysum, total = 0;
         for (int w = 0; w < 4; ++w) {
-            if (w < (t >> 6)) run += s_w4[w];
+            if (w < (t >> 6)) myoff += s_w4[w];
             total += s_w4[w];
         }
-        for (int e = 0; e < per; ++e) { s_pre[t * per + e] = run; run += nloc[e]; }
-        if (t == 0) s_pre[ac] = total;
-        __syncthreads();
         for (uint32_t P0 = 0; P0 < total; P0 += BATCH) {
             const uint32_t nb = min((uint32_t)BATCH, total - P0);
-            // Generate the batch (pair index -> outer element by binary search).
-            for (uint32_t o = t; o < nb; o += 256) {
-                const uint32_t pi = P0 + o;
-                int lo2 = 0, hi2 = ac;                     // last slot with s_pre <= pi
-                while (hi2 - lo2 > 1) {
-                    const int mid = (lo2 + hi2) >> 1;
-                    if (s_pre[mid] <= pi) lo2 = mid; else hi2 = mid;
-                }
-                const QRec<W> a = outer[c0 + lo2];
-                const QRec<W> b = inner[s_b0[lo2] + (pi - s_pre[lo2])];
-                const int64_t key = side ? a.key - b.key : a.key + b.key;
-                bool keep = side ? key >= 0 : key <= p.Kd;
-                if (p.slice_mod) keep = keep && ((key & smod1) == p.slice_res);
-                Rec<W> r;
-                r.key = key;
-                r.mask = (uint64_t)a.mask | ((uint64_t)b.mask << sh);
-#pragma unroll
-                for (int w = 0; w < (W > 0 ? W : 1); ++w)
-                    r.vec[w] = side ? resid_word(p.dpk[w], a.vec[w], b.vec[w]) : a.vec[w] + b.vec[w];
-                s_rec[o] = r;
-                s_f[o] = keep ? (uint16_t)((key & M1) >> p.log2T) : (uint16_t)0xFFFF;
-            }
             for (int f = t; f < Fs; f += 256) s_cnt[f] = 0;
+            // Generate my pairs whose index falls in [P0, P0 + nb).
+            uint32_t off = myoff;
+#pragma unroll
+            for (int e = 0; e < per; ++e) {
+                const uint32_t n = nn[e];
+                const uint32_t qa = off >= P0 ? 0u : min(n, P0 - off);
+                const uint32_t qb = (off + n <= P0 + nb) ? n : (P0 + nb > off ? P0 + nb - off : 0u);
+                // Loads of up to 8 inner records are issued together, then used.
+                constexpr int kU = 8;
+                for (uint32_t q0 = qa; q0 < qb; q0 += kU) {
+                    QRec<W> bb[kU];
+#pragma unroll
+                    for (int u = 0; u < kU; ++u)
+                        if (q0 + u < qb) bb[u] = inner[b0[e] + q0 + u];
+#pragma unroll
+                    for (int u = 0; u < kU; ++u) {
+                        if (q0 + u >= qb) break;
+                        const QRec<W> &bq = bb[u];
+                        const QRec<W> &a = av[e];
+                        const int64_t key = side ? a.key - bq.key : a.key + bq.key;
+                        bool keep = side ? key >= 0 : key <= p.Kd;
+                        if (p.slice_mod) keep = keep && ((key & smod1) == p.slice_res);
+                        const uint32_t o = off + q0 + u - P0;
+                        Rec<W> r;
+                        r.key = key;
+                        r.mask = (uint64_t)a.mask | ((uint64_t)bq.mask << sh);
+#pragma unroll
+                        for (int w = 0; w < WV; ++w)
+                            r.vec[w] = side ? resid_word(p.dpk[w], a.vec[w], bq.vec[w]) : a.vec[w] + bq.vec[w];
+                        s_rec[o] = r;
+                        s_f[o] = keep ? (uint16_t)((key & M1) >> p.log2T) : (uint16_t)0xFFFF;
+                    }
+                }
+                off += n;
+            }
             __syncthreads();
             for (uint32_t o = t; o < nb; o += 256)
                 if (s_f[o] != 0xFFFF) atomicAdd(&s_cnt[s_f[o]], 1u);
@@ -474,7 +484,9 @@ __global__ __launch_bounds__(256) void k_hash_join(Plan p, const uint32_t *__res
     // s_tab[h] = (representative left index << 16) | count, then | group end.
     constexpr uint32_t kEmpty = 0xFFFF0000u;
     constexpr int kPre = 4;                              // right records preloaded per lane
+    constexpr int WV = W > 0 ? W : 1;
     __shared__ int64_t s_key[kJoinCap];
+    __shared__ uint32_t s_vec[WV][kJoinCap];             // left packed rows, by left index
     __shared__ uint32_t s_tab[kJoinSlots];
     __shared__ uint16_t s_slot[kJoinCap];
     __shared__ uint16_t s_grp[kJoinCap];
@@ -494,16 +506,45 @@ __global__ __launch_bounds__(256) void k_hash_join(Plan p, const uint32_t *__res
         return;
     }
     const int t = threadIdx.x;
-    // Issue the right-side loads first; they are consumed after the build.
-    Rec<W> rr[kPre];
+    // Right keys and rows are loaded first and consumed after the build.
+    int64_t rk[kPre];
+    uint32_t rv[kPre][WV];
 #pragma unroll
-    for (int e = 0; e < kPre; ++e)
-        if ((uint32_t)(t + 256 * e) < nr) rr[e] = R[r0 + t + 256 * e];
+    for (int e = 0; e < kPre; ++e) {
+        const uint32_t j = t + 256 * e;
+        if (j < nr) {
+            rk[e] = R[r0 + j].key;
+#pragma unroll
+            for (int w = 0; w < WV; ++w) rv[e][w] = R[r0 + j].vec[w];
+        }
+    }
     uint32_t slots = 256;
     while (slots < 2 * nl) slots <<= 1;
     const uint32_t smask = slots - 1;
     for (uint32_t i = t; i < slots; i += 256) s_tab[i] = kEmpty;
-    for (uint32_t i = t; i < nl; i += 256) s_key[i] = L[l0 + i].key;
+    {   // all left loads of this lane issued together, then staged into LDS
+        constexpr int kLU = (kJoinCap + 255) / 256;
+        int64_t lk[kLU];
+        uint32_t lv[kLU][WV];
+#pragma unroll
+        for (int u = 0; u < kLU; ++u) {
+            const uint32_t i = t + 256 * u;
+            if (i < nl) {
+                lk[u] = L[l0 + i].key;
+#pragma unroll
+                for (int w = 0; w < WV; ++w) lv[u][w] = L[l0 + i].vec[w];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kLU; ++u) {
+            const uint32_t i = t + 256 * u;
+            if (i < nl) {
+                s_key[i] = lk[u];
+#pragma unroll
+                for (int w = 0; w < WV; ++w) s_vec[w][i] = lv[u][w];
+            }
+        }
+    }
     __syncthreads();
     // Build: one representative per distinct key, count per slot.
     for (uint32_t i = t; i < nl; i += 256) {
@@ -552,14 +593,14 @@ __global__ __launch_bounds__(256) void k_hash_join(Plan p, const uint32_t *__res
     }
     __syncthreads();
     uint64_t hits = 0;
-    auto probe = [&](const Rec<W> &r) {
+    auto probe = [&](const int64_t key, const uint32_t *v, uint32_t rj) {
         // After the scan an empty slot keeps head 0xFFFF but its low half
         // holds a running offset, so emptiness is read from the head half.
-        uint32_t h = key_hash(r.key) & smask;
+        uint32_t h = key_hash(key) & smask;
         for (;;) {
             const uint32_t w = s_tab[h];
             if ((w >> 16) == 0xFFFFu) return;
-            if (s_key[w >> 16] == r.key) break;
+            if (s_key[w >> 16] == key) break;
             h = (h + 1) & smask;
         }
         const uint32_t ge = s_tab[h] & 0xFFFFu, gs = h ? (s_tab[h - 1] & 0xFFFFu) : 0u;
@@ -568,19 +609,29 @@ __global__ __launch_bounds__(256) void k_hash_join(Plan p, const uint32_t *__res
             atomicAdd((unsigned long long *)&scal[S_NSOL], (unsigned long long)(ge - gs));
             for (uint32_t q = gs; q < ge; ++q) {
                 if (scal[S_STORED] >= cap) break;
-                emit_solution(sol, cap, &scal[S_STORED], L[l0 + s_grp[q]].mask, r.mask);
+                emit_solution(sol, cap, &scal[S_STORED], L[l0 + s_grp[q]].mask, R[r0 + rj].mask);
             }
         } else {
             for (uint32_t q = gs; q < ge; ++q) {
-                const Rec<W> ll = L[l0 + s_grp[q]];
-                if (rows_match<W>(ll, r)) emit_solution(sol, cap, &scal[S_NSOL], ll.mask, r.mask);
+                const uint32_t li = s_grp[q];
+                bool ok = true;
+#pragma unroll
+                for (int w = 0; w < WV; ++w) ok = ok && (s_vec[w][li] == v[w]);
+                if (ok) emit_solution(sol, cap, &scal[S_NSOL], L[l0 + li].mask, R[r0 + rj].mask);
             }
         }
     };
 #pragma unroll
-    for (int e = 0; e < kPre; ++e)
-        if ((uint32_t)(t + 256 * e) < nr) probe(rr[e]);
-    for (uint32_t j = t + 256 * kPre; j < nr; j += 256) probe(R[r0 + j]);
+    for (int e = 0; e < kPre; ++e) {
+        const uint32_t j = t + 256 * e;
+        if (j < nr) probe(rk[e], rv[e], j);
+    }
+    for (uint32_t j = t + 256 * kPre; j < nr; j += 256) {
+        uint32_t v[WV];
+#pragma unroll
+        for (int w = 0; w < WV; ++w) v[w] = R[r0 + j].vec[w];
+        probe(R[r0 + j].key, v, j);
+    }
     const uint64_t tot = block_sum_u64(hits, s_s4);
     if (t == 0) add_u128(&scal[S_H_LO], &scal[S_H_HI], tot);
 }
@@ -906,12 +957,17 @@ static hipError_t staged_impl(const Plan &p, const DevBufs &b, int64_t idx0, int
     // Outer elements per chunk: enough pairs to fill about one batch.
     const uint64_t T = (uint64_t)1 << p.log2T;
     const uint64_t avg = std::max<uint64_t>(1, std::min((uint64_t)p.Q[1], (uint64_t)p.Q[3]) / T);
-    const int ac = avg >= 8 ? 256 : avg >= 4 ? 512 : 1024;
+    const int per = avg >= 8 ? 1 : avg >= 4 ? 2 : 4;   // outer elements per thread per chunk
     dim3 grid((uint32_t)K * p.parts, 2);
-    hipLaunchKernelGGL(k_scatter_staged<W>, grid, dim3(256), 0, st, p,
-                       (const QRec<W> *)b.qsrt[0], (const QRec<W> *)b.qsrt[1], b.qcnt[1],
-                       (const QRec<W> *)b.qsrt[2], (const QRec<W> *)b.qsrt[3], b.qcnt[3],
-                       b.off[0], b.off[1], (Rec<W> *)b.rec[0], (Rec<W> *)b.rec[1], idx0, ac);
+#define MSP_STAGED(PERV)                                                                        \
+    hipLaunchKernelGGL((k_scatter_staged<W, PERV>), grid, dim3(256), 0, st, p,                  \
+                       (const QRec<W> *)b.qsrt[0], (const QRec<W> *)b.qsrt[1], b.qcnt[1],       \
+                       (const QRec<W> *)b.qsrt[2], (const QRec<W> *)b.qsrt[3], b.qcnt[3],       \
+                       b.off[0], b.off[1], (Rec<W> *)b.rec[0], (Rec<W> *)b.rec[1], idx0)
+    if (per == 1) MSP_STAGED(1);
+    else if (per == 2) MSP_STAGED(2);
+    else MSP_STAGED(4);
+#undef MSP_STAGED
     return hipGetLastError();
 }
 
