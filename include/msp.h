@@ -52,6 +52,7 @@ extern "C" {
 #define MSP_E_TRUNCATED    (-8)  /* caller buffer smaller than the result               */
 #define MSP_E_STATE        (-9)  /* no result yet (msp_solve not run or failed)         */
 #define MSP_E_NOLIB        (-10) /* GPU not present or not usable                       */
+#define MSP_E_BUSY         (-11) /* the context is in use by another solve or request   */
 
 typedef struct msp_ctx msp_ctx;
 
@@ -114,6 +115,45 @@ int  msp_stats(const msp_ctx *ctx, msp_stats_t *out);
 
 void msp_destroy(msp_ctx *ctx);
 const char *msp_strerror(int code);
+
+/* ------------------------------------------------------------------------
+ * Batched and served solves.  Many instances of uneven (m, n) run together:
+ * each admitted solve gets a share of one device arena and its own stream,
+ * and every scheduler step advances one residue window of every admitted
+ * solve, so their kernels overlap on the GPU.  A solve is admitted when a
+ * slot is free and its device footprint (planned for hbm_budget/max_slots,
+ * or for the whole budget when that is the only way it fits) fits in the
+ * free part of the arena; otherwise it waits, in arrival order.  Results
+ * land in each context exactly as msp_solve would leave them.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    uint64_t hbm_budget;      /* arena bytes for all admitted solves; 0 = 60% of free, <=128 GiB */
+    int32_t  max_slots;       /* solves admitted at once; 0 = 16                              */
+    int32_t  reserved;
+} msp_batch_opts;
+
+/* Solves ctxs[0..count) together; opts is NULL or an array of count
+ * options (their workspace and stream fields are ignored).  Returns the
+ * first error of any solve (each context records its own result). */
+int  msp_batch_solve(msp_ctx *const *ctxs, const msp_opts *opts, int32_t count,
+                     const msp_batch_opts *bo);
+
+/* A server runs the batched scheduler on its own thread: requests submitted
+ * while others are on the GPU join at the next step (continuous batching).
+ * A context must stay alive, and unused by anything else, until its request
+ * is done (msp_server_poll / msp_server_wait report completion). */
+typedef msp_batch_opts msp_server_opts;
+typedef struct msp_server msp_server;
+int  msp_server_start(const msp_server_opts *o, msp_server **out);
+int  msp_server_submit(msp_server *s, msp_ctx *ctx, const msp_opts *o, uint64_t *ticket);
+int  msp_server_poll(msp_server *s, uint64_t ticket, int32_t *done, int32_t *status);
+int  msp_server_wait(msp_server *s, uint64_t ticket, int32_t *status);
+/* Stops a request at its next residue window (status MSP_E_CANCELLED). */
+int  msp_server_cancel(msp_server *s, uint64_t ticket);
+/* Seconds since server start: t4 = {submit, admit, first step, finish}. */
+int  msp_server_times(msp_server *s, uint64_t ticket, double *t4);
+/* Finishes every queued request, then frees the server. */
+int  msp_server_stop(msp_server *s);
 
 /* Device workspace bytes msp_solve would use with these options, the
  * plan shrunk to fit opts->workspace_bytes when that is non-zero (0 on

@@ -4,10 +4,16 @@
 #include "msp_internal.h"
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <condition_variable>
 #include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
 #include <new>
 #include <numeric>
+#include <thread>
 #include <vector>
 
 using namespace msp;
@@ -23,8 +29,8 @@ struct msp_ctx {
     void *ws = nullptr;                // library-owned workspace (cached)
     size_t ws_bytes = 0;
     hipStream_t own_stream = nullptr;
-    hipEvent_t ev[8] = {};
     bool poisoned = false;
+    std::atomic<int> busy{0};          // a solve or request is using this context
 };
 
 namespace {
@@ -247,13 +253,504 @@ double ev_ms(hipEvent_t a, hipEvent_t b) {
     return (double)ms;
 }
 
-#define HIPCHK(x)                                      \
-    do {                                               \
-        hipError_t e_ = (x);                           \
-        if (e_ != hipSuccess) { rc = MSP_E_DEVICE; goto fail; } \
+double now_s() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+// ---------------------------------------------------------------------------
+// Device memory arena for batched / served solves: one allocation, first-fit
+// ranges, adjacent free ranges merged.  Host-side bookkeeping only.
+// ---------------------------------------------------------------------------
+struct Arena {
+    char *base = nullptr;
+    uint64_t size = 0;
+    std::map<uint64_t, uint64_t> free_;      // offset -> length
+    bool init(uint64_t bytes) {
+        if (hipMalloc((void **)&base, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            base = nullptr;
+            return false;
+        }
+        size = bytes;
+        free_.clear();
+        free_[0] = bytes;
+        return true;
+    }
+    void release_all() {
+        if (base) (void)hipFree(base);
+        base = nullptr;
+        free_.clear();
+    }
+    char *alloc(uint64_t bytes) {
+        bytes = (bytes + 4095) & ~(uint64_t)4095;
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                const uint64_t off = it->first, len = it->second;
+                free_.erase(it);
+                if (len > bytes) free_[off + bytes] = len - bytes;
+                return base + off;
+            }
+        }
+        return nullptr;
+    }
+    void free(char *p, uint64_t bytes) {
+        bytes = (bytes + 4095) & ~(uint64_t)4095;
+        uint64_t off = (uint64_t)(p - base);
+        auto nx = free_.lower_bound(off);
+        if (nx != free_.end() && off + bytes == nx->first) {
+            bytes += nx->second;
+            nx = free_.erase(nx);
+        }
+        if (nx != free_.begin()) {
+            auto pv = std::prev(nx);
+            if (pv->first + pv->second == off) {
+                pv->second += bytes;
+                return;
+            }
+        }
+        free_[off] = bytes;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// A solve in progress.  Each call of step() enqueues the next group of
+// kernels on the job's stream; the runner synchronises all jobs between
+// calls, so concurrent jobs overlap on the device.
+// ---------------------------------------------------------------------------
+enum Action { A_BEGIN, A_COUNTED, A_JOINED, A_TILED, A_FINAL1, A_FINAL2, A_DONE };
+enum Ev { E_Q0, E_Q1, E_C0, E_C1, E_C2, E_S0, E_S1, E_S2, E_V0, E_V1, E_COUNT };
+
+struct Job {
+    msp_ctx *c = nullptr;
+    msp_opts o{};
+    Prepared P;
+    DevBufs b{};
+    char *ws = nullptr;
+    uint64_t ws_bytes = 0;
+    bool arena_ws = false;
+    hipStream_t s = nullptr;
+    hipEvent_t ev[E_COUNT] = {};
+    uint64_t *hs = nullptr;              // pinned copy of the device scalars
+    Action next = A_BEGIN;
+    uint64_t idx = 0, kw = 0, K = 0;
+    bool verify_pending = false;
+    std::vector<uint64_t> solbuf;
+    msp_stats_t st{};
+    int rc = MSP_OK;
+    double t_submit = 0, t_admit = 0, t_start = 0, t_finish = 0, t_wall0 = 0;
+    uint64_t ticket = 0;
+    bool cancel = false;
+    int slot = -1;                       // runner stream slot
+};
+
+int job_setup_events(Job &j) {
+    for (auto &e : j.ev)
+        if (!e && hipEventCreate(&e) != hipSuccess) return MSP_E_DEVICE;
+    if (!j.hs && hipHostMalloc((void **)&j.hs, S_COUNT * 8, hipHostMallocDefault) != hipSuccess)
+        return MSP_E_DEVICE;
+    return MSP_OK;
+}
+
+void job_release_events(Job &j) {
+    for (auto &e : j.ev)
+        if (e) (void)hipEventDestroy(e), e = nullptr;
+    if (j.hs) (void)hipHostFree(j.hs), j.hs = nullptr;
+}
+
+void job_carve(Job &j) {
+    const Sizes &z = j.P.z;
+    char *ws = j.ws;
+    for (int x = 0; x < 4; ++x) {
+        j.b.qraw[x] = ws + z.o_qraw[x];
+        j.b.qsrt[x] = ws + z.o_qsrt[x];
+        j.b.qcnt[x] = (uint32_t *)(ws + z.o_qcnt[x]);
+        j.b.qcur[x] = (uint32_t *)(ws + z.o_qcur[x]);
+    }
+    for (int sd = 0; sd < 2; ++sd) {
+        j.b.cnt[sd] = (uint32_t *)(ws + z.o_cnt[sd]);
+        j.b.off[sd] = (uint32_t *)(ws + z.o_off[sd]);
+        j.b.rec[sd] = ws + z.o_rec[sd];
+    }
+    j.b.runs = (RunPair *)(ws + z.o_runs);
+    j.b.tiles = (uint32_t *)(ws + z.o_tiles);
+    j.b.sol = (uint64_t *)(ws + z.o_sol);
+    j.b.scal = (uint64_t *)(ws + z.o_scal);
+    j.b.scan_tmp = ws + z.o_scan;
+    j.b.scan_tmp_bytes = z.scan_bytes;
+    j.b.colw = (int64_t *)(ws + z.o_colw);
+    j.b.rows = (uint16_t *)(ws + z.o_rows);
+}
+
+#define JCHK(x)                                   \
+    do {                                          \
+        if ((x) != hipSuccess) {                  \
+            (void)hipGetLastError();              \
+            return MSP_E_DEVICE;                  \
+        }                                         \
     } while (0)
 
+int enqueue_count(Job &j) {
+    const Plan &p = j.P.p;
+    const size_t ncnt = (size_t)j.K * ((size_t)1 << p.log2F) * p.parts;
+    JCHK(hipEventRecord(j.ev[E_C0], j.s));
+    JCHK(launch_count(p, j.b, (int64_t)j.idx, (int32_t)j.K, j.s));
+    JCHK(hipEventRecord(j.ev[E_C1], j.s));
+    JCHK(scan_u32(j.b.cnt[0], j.b.off[0], ncnt, &j.b.scal[S_TOT_L], j.b.scan_tmp, j.b.scan_tmp_bytes, j.s));
+    JCHK(scan_u32(j.b.cnt[1], j.b.off[1], ncnt, &j.b.scal[S_TOT_R], j.b.scan_tmp, j.b.scan_tmp_bytes, j.s));
+    JCHK(hipEventRecord(j.ev[E_C2], j.s));
+    JCHK(hipMemcpyAsync(j.hs, j.b.scal, S_COUNT * 8, hipMemcpyDeviceToHost, j.s));
+    return MSP_OK;
+}
+
+// Run the job's next action.  Everything it enqueues is complete when the
+// runner calls step() again.
+int job_step(Job &j) {
+    const Plan &p = j.P.p;
+    const Sizes &z = j.P.z;
+    switch (j.next) {
+        case A_BEGIN: {
+            const uint64_t T = (uint64_t)1 << p.log2T;
+            JCHK(hipMemcpyAsync(j.b.colw, j.P.colw.data(), j.P.colw.size() * 8, hipMemcpyHostToDevice, j.s));
+            JCHK(hipMemcpyAsync(j.b.rows, j.P.rows.data(), j.P.rows.size() * 2, hipMemcpyHostToDevice, j.s));
+            JCHK(hipMemsetAsync(j.b.scal, 0, S_COUNT * 8, j.s));
+            for (int x = 0; x < 4; ++x) JCHK(hipMemsetAsync(j.b.qcnt[x], 0, (T + 1) * 4, j.s));
+            JCHK(hipEventRecord(j.ev[E_Q0], j.s));
+            JCHK(launch_quarters(p, j.b, 0, j.s));
+            JCHK(hipEventRecord(j.ev[E_Q1], j.s));
+            j.idx = 0;
+            j.kw = z.kwin;
+            j.K = std::min<uint64_t>(j.kw, z.ncells - j.idx);
+            int rc = enqueue_count(j);
+            if (rc) return rc;
+            j.next = A_COUNTED;
+            return MSP_OK;
+        }
+        case A_COUNTED: {
+            if (j.st.ms_quarters == 0.0) j.st.ms_quarters = ev_ms(j.ev[E_Q0], j.ev[E_Q1]);
+            if (j.verify_pending) {
+                j.st.ms_verify += ev_ms(j.ev[E_V0], j.ev[E_V1]);
+                j.verify_pending = false;
+            }
+            j.st.ms_count += ev_ms(j.ev[E_C0], j.ev[E_C1]);
+            j.st.ms_scan += ev_ms(j.ev[E_C1], j.ev[E_C2]);
+            const uint64_t totL = j.hs[S_TOT_L], totR = j.hs[S_TOT_R];
+            if (totL > z.cap_rec || totR > z.cap_rec) {
+                if (j.K == 1) return MSP_E_NOMEM;
+                j.K = (j.K + 1) / 2;
+                j.kw = j.K;
+                int rc = enqueue_count(j);
+                if (rc) return rc;
+                return MSP_OK;                  // next stays A_COUNTED
+            }
+            j.st.records_left += totL;
+            j.st.records_right += totR;
+            JCHK(hipMemsetAsync(&j.b.scal[S_NRUNS], 0, 8, j.s));
+            JCHK(hipEventRecord(j.ev[E_S0], j.s));
+            JCHK(launch_scatter(p, j.b, (int64_t)j.idx, (int32_t)j.K, j.s));
+            JCHK(hipEventRecord(j.ev[E_S1], j.s));
+            if (p.exact)
+                JCHK(launch_exact_runs(p, j.b, (int32_t)j.K, j.s));
+            else
+                JCHK(launch_hash_join(p, j.b, (int32_t)j.K, z.sol_cap, j.s));
+            JCHK(hipEventRecord(j.ev[E_S2], j.s));
+            JCHK(hipMemcpyAsync(j.hs, j.b.scal, S_COUNT * 8, hipMemcpyDeviceToHost, j.s));
+            j.next = A_JOINED;
+            return MSP_OK;
+        }
+        case A_JOINED:
+        case A_TILED: {
+            if (j.next == A_JOINED) {
+                j.st.ms_scatter += ev_ms(j.ev[E_S0], j.ev[E_S1]);
+                j.st.ms_join += ev_ms(j.ev[E_S1], j.ev[E_S2]);
+                const uint32_t nruns = (uint32_t)j.hs[S_NRUNS];
+                if (nruns) {
+                    JCHK(launch_tile_counts(p, j.b, nruns, !p.exact, j.s));
+                    JCHK(scan_u32(j.b.tiles, j.b.tiles, nruns, &j.b.scal[S_TOT_TILES], j.b.scan_tmp,
+                                  j.b.scan_tmp_bytes, j.s));
+                    JCHK(hipMemcpyAsync(&j.hs[S_TOT_TILES], &j.b.scal[S_TOT_TILES], 8,
+                                        hipMemcpyDeviceToHost, j.s));
+                    j.next = A_TILED;
+                    return MSP_OK;
+                }
+            } else {
+                const uint32_t nruns = (uint32_t)j.hs[S_NRUNS];
+                const uint32_t ntiles = (uint32_t)j.hs[S_TOT_TILES];
+                JCHK(hipEventRecord(j.ev[E_V0], j.s));
+                JCHK(launch_verify(p, j.b, nruns, ntiles, z.sol_cap, !p.exact, j.s));
+                JCHK(hipEventRecord(j.ev[E_V1], j.s));
+                j.verify_pending = true;
+                j.st.verify_launches++;
+            }
+            // Window done; move to the next one or finish.
+            j.st.windows++;
+            j.idx += j.K;
+            if (j.idx < z.ncells && !j.cancel) {
+                j.K = std::min<uint64_t>(j.kw, z.ncells - j.idx);
+                int rc = enqueue_count(j);
+                if (rc) return rc;
+                j.next = A_COUNTED;
+            } else {
+                JCHK(hipMemcpyAsync(j.hs, j.b.scal, S_COUNT * 8, hipMemcpyDeviceToHost, j.s));
+                j.next = A_FINAL1;
+            }
+            return MSP_OK;
+        }
+        case A_FINAL1: {
+            if (j.verify_pending) {
+                j.st.ms_verify += ev_ms(j.ev[E_V0], j.ev[E_V1]);
+                j.verify_pending = false;
+            }
+            if (j.cancel) return MSP_E_CANCELLED;
+            const uint64_t stored =
+                std::min<uint64_t>(z.sol_cap, p.W == 0 ? j.hs[S_STORED] : j.hs[S_NSOL]);
+            j.solbuf.resize(stored * 2);
+            if (stored)
+                JCHK(hipMemcpyAsync(j.solbuf.data(), j.b.sol, stored * 16, hipMemcpyDeviceToHost, j.s));
+            j.next = A_FINAL2;
+            return MSP_OK;
+        }
+        case A_FINAL2: {
+            // Expand half masks to x (left-half columns first) and sort
+            // canonically (lexicographic on x_1..x_n, 0 < 1).
+            msp_ctx *c = j.c;
+            const int n = c->n;
+            const uint64_t stored = j.solbuf.size() / 2;
+            std::vector<uint8_t> xs(stored * n);
+            for (uint64_t k = 0; k < stored; ++k) {
+                const uint64_t ml = j.solbuf[2 * k], mr = j.solbuf[2 * k + 1];
+                for (int jj = 0; jj < n; ++jj)
+                    xs[k * n + jj] = (uint8_t)(jj < p.hL ? (ml >> jj) & 1u : (mr >> (jj - p.hL)) & 1u);
+            }
+            std::vector<uint64_t> ord(stored);
+            std::iota(ord.begin(), ord.end(), 0);
+            std::sort(ord.begin(), ord.end(), [&](uint64_t a, uint64_t bb) {
+                return std::memcmp(&xs[a * n], &xs[bb * n], n) < 0;
+            });
+            c->sol.resize(stored * n);
+            for (uint64_t k = 0; k < stored; ++k) std::memcpy(&c->sol[k * n], &xs[ord[k] * n], n);
+            c->stored = stored;
+            c->h_lo = j.hs[S_H_LO];
+            c->h_hi = j.hs[S_H_HI];
+            c->nsol = j.hs[S_NSOL];
+            j.st.ms_total = (now_s() - j.t_wall0) * 1e3;
+            c->stats = j.st;
+            c->have_result = true;
+            j.next = A_DONE;
+            return MSP_OK;
+        }
+        case A_DONE:
+            return MSP_OK;
+    }
+    return MSP_OK;
+}
+
+// Results of a solve that needs no GPU work (a key row can never hold).
+void job_trivial(Job &j) {
+    msp_ctx *c = j.c;
+    c->h_lo = c->h_hi = c->nsol = 0;
+    c->sol.clear();
+    c->stored = 0;
+    j.st.ms_total = (now_s() - j.t_wall0) * 1e3;
+    c->stats = j.st;
+    c->have_result = true;
+    j.next = A_DONE;
+}
+
+void job_init_stats(Job &j) {
+    const Plan &p = j.P.p;
+    j.st = msp_stats_t{};
+    j.st.key_rows = p.r;
+    j.st.log2_m = p.log2M;
+    j.st.log2_cells = p.log2T;
+    j.st.parts = p.parts;
+    j.st.exact_buckets = p.exact;
+    j.st.words = p.W;
+    j.st.record_bytes = rec_bytes(p.W);
+}
+
+// ---------------------------------------------------------------------------
+// Runner: drives a set of jobs; admission by device-memory footprint.
+// ---------------------------------------------------------------------------
+struct Runner {
+    Arena arena;
+    uint64_t budget = 0;            // bytes for all admitted jobs together
+    int max_slots = 16;
+    std::vector<hipStream_t> streams;
+    std::vector<int> stream_free;
+    std::deque<Job *> pending;
+    std::vector<Job *> active;
+    double t0 = 0;
+
+    int init(uint64_t hbm_budget, int slots) {
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return MSP_E_NOLIB;
+        max_slots = slots > 0 ? slots : 16;
+        budget = hbm_budget;
+        if (!budget) {
+            size_t fr = 0, tot = 0;
+            if (hipMemGetInfo(&fr, &tot) != hipSuccess) return MSP_E_NOLIB;
+            budget = std::min<uint64_t>((uint64_t)(fr * 0.6), (uint64_t)128 << 30);
+        }
+        if (!arena.init(budget)) return MSP_E_NOMEM;
+        streams.resize(max_slots);
+        for (int i = 0; i < max_slots; ++i) {
+            if (hipStreamCreateWithFlags(&streams[i], hipStreamNonBlocking) != hipSuccess)
+                return MSP_E_DEVICE;
+            stream_free.push_back(i);
+        }
+        t0 = now_s();
+        return MSP_OK;
+    }
+    void shutdown() {
+        for (auto s : streams)
+            if (s) (void)hipStreamSynchronize(s), (void)hipStreamDestroy(s);
+        streams.clear();
+        arena.release_all();
+    }
+    // Per-job planning budget: an equal share of the arena per slot.
+    uint64_t job_budget() const { return budget / (uint64_t)max_slots; }
+
+    // Plan a job (host only).  Sets j.rc on failure.
+    void plan(Job &j) {
+        j.t_wall0 = now_s();
+        uint64_t jb = job_budget();
+        j.rc = prepare(j.c, j.o, jb, j.P);
+        if (j.rc == MSP_E_NOMEM) j.rc = prepare(j.c, j.o, budget, j.P);   // alone, it may fit
+        if (j.rc == MSP_OK) {
+            job_init_stats(j);
+            j.ws_bytes = j.P.z.total;
+        }
+    }
+
+    // Admit pending jobs while a slot and memory are free (FIFO order).
+    void admit(std::vector<Job *> &failed) {
+        while (!pending.empty() && (int)active.size() < max_slots) {
+            Job *j = pending.front();
+            if (j->rc == MSP_OK && j->c->busy.load() == 2) j->rc = MSP_E_CANCELLED;
+            if (j->rc != MSP_OK) { pending.pop_front(); failed.push_back(j); continue; }
+            if (j->P.infeasible) {
+                pending.pop_front();
+                j->t_admit = j->t_start = now_s() - t0;
+                job_trivial(*j);
+                j->t_finish = now_s() - t0;
+                failed.push_back(j);               // reported as finished (rc OK)
+                continue;
+            }
+            if (j->ws_bytes > budget) { j->rc = MSP_E_NOMEM; pending.pop_front(); failed.push_back(j); continue; }
+            char *ws = arena.alloc(j->ws_bytes);
+            if (!ws) break;                        // wait for memory to free up
+            pending.pop_front();
+            j->ws = ws;
+            j->arena_ws = true;
+            const int si = stream_free.back();
+            stream_free.pop_back();
+            j->s = streams[si];
+            j->slot = si;
+            job_carve(*j);
+            if (job_setup_events(*j) != MSP_OK) { j->rc = MSP_E_DEVICE; retire(j); failed.push_back(j); continue; }
+            j->t_admit = now_s() - t0;
+            active.push_back(j);
+        }
+    }
+
+    void retire(Job *j) {
+        if (j->arena_ws && j->ws) arena.free(j->ws, j->ws_bytes);
+        j->ws = nullptr;
+        if (j->s) {
+            (void)hipStreamSynchronize(j->s);
+            if (j->slot >= 0) stream_free.push_back(j->slot);
+            j->slot = -1;
+            j->s = nullptr;
+        }
+        job_release_events(*j);
+        j->t_finish = now_s() - t0;
+    }
+
+    // One step: every active job runs its next action, then all of them are
+    // synchronised.  Finished or failed jobs are returned in `done`.
+    void step(std::vector<Job *> &done) {
+        for (Job *j : active) {
+            if (j->t_start == 0) j->t_start = now_s() - t0;
+            const int rc = job_step(*j);
+            if (rc != MSP_OK) j->rc = rc;
+        }
+        for (Job *j : active) {
+            if (j->rc == MSP_OK && j->next != A_DONE && hipStreamSynchronize(j->s) != hipSuccess) {
+                (void)hipGetLastError();
+                j->rc = MSP_E_DEVICE;
+            }
+        }
+        std::vector<Job *> keep;
+        for (Job *j : active) {
+            if (j->rc != MSP_OK || j->next == A_DONE) {
+                retire(j);
+                done.push_back(j);
+            } else {
+                keep.push_back(j);
+            }
+        }
+        active.swap(keep);
+    }
+};
+
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// Server: the runner on its own thread; requests join while others run.
+// ---------------------------------------------------------------------------
+struct msp_server {
+    Runner run;
+    std::mutex mu;
+    std::condition_variable cv, cv_done;
+    std::deque<Job *> inbox;
+    std::map<uint64_t, Job *> jobs;        // ticket -> job (kept until stop)
+    uint64_t next_ticket = 1;
+    bool stopping = false;
+    std::thread th;
+};
+
+static void server_loop(msp_server *sv) {
+    std::vector<Job *> done;
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> lk(sv->mu);
+            sv->cv.wait(lk, [&] {
+                return sv->stopping || !sv->inbox.empty() || !sv->run.active.empty() ||
+                       !sv->run.pending.empty();
+            });
+            if (sv->stopping && sv->run.active.empty() && sv->inbox.empty() && sv->run.pending.empty())
+                break;
+            while (!sv->inbox.empty()) {
+                sv->run.pending.push_back(sv->inbox.front());
+                sv->inbox.pop_front();
+            }
+            for (Job *j : sv->run.active)
+                if (j->c->busy.load() == 2) j->cancel = true;   // cancellation request
+        }
+        done.clear();
+        sv->run.admit(done);
+        if (!sv->run.active.empty()) sv->run.step(done);
+        if (!done.empty()) {
+            std::lock_guard<std::mutex> lk(sv->mu);
+            for (Job *j : done) {
+                if (j->t_finish == 0) j->t_finish = now_s() - sv->run.t0;
+                j->c->busy.store(0);
+            }
+            sv->cv_done.notify_all();
+        }
+        if (sv->run.active.empty() && !sv->run.pending.empty() && done.empty()) {
+            // The queue head does not fit even with nothing running.
+            std::lock_guard<std::mutex> lk(sv->mu);
+            Job *j = sv->run.pending.front();
+            sv->run.pending.pop_front();
+            j->rc = MSP_E_NOMEM;
+            j->t_finish = now_s() - sv->run.t0;
+            j->c->busy.store(0);
+            sv->cv_done.notify_all();
+        }
+    }
+}
 
 extern "C" {
 
@@ -270,6 +767,7 @@ const char *msp_strerror(int code) {
         case MSP_E_TRUNCATED: return "buffer smaller than the result";
         case MSP_E_STATE: return "no result available";
         case MSP_E_NOLIB: return "no usable GPU";
+        case MSP_E_BUSY: return "context is in use by another solve";
         default: return "unknown error";
     }
 }
@@ -296,8 +794,6 @@ int msp_create(const int32_t *A, const int32_t *d, int32_t m, int32_t n, msp_ctx
 void msp_destroy(msp_ctx *c) {
     if (!c) return;
     if (c->ws) (void)hipFree(c->ws);
-    for (auto &e : c->ev)
-        if (e) (void)hipEventDestroy(e);
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
     delete c;
 }
@@ -315,198 +811,215 @@ uint64_t msp_workspace_bytes(const msp_ctx *c, const msp_opts *opts) {
 int msp_solve(msp_ctx *c, const msp_opts *opts) {
     if (!c) return MSP_E_INVALID;
     if (c->poisoned) return MSP_E_DEVICE;
-    const auto t0 = std::chrono::steady_clock::now();
-    msp_opts o;
-    msp_default_opts(&o);
-    if (opts) o = *opts;
+    int expect = 0;
+    if (!c->busy.compare_exchange_strong(expect, 1)) return MSP_E_BUSY;
+    struct Unbusy { msp_ctx *c; ~Unbusy() { c->busy.store(0); } } unbusy{c};
+    Job j;
+    j.c = c;
+    msp_default_opts(&j.o);
+    if (opts) j.o = *opts;
+    j.t_wall0 = now_s();
     c->have_result = false;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return MSP_E_NOLIB;
-
-    if (o.workspace && !o.workspace_bytes) return MSP_E_INVALID;
-    uint64_t budget = o.workspace_bytes;
-    if (!o.workspace && !budget) {
+    if (j.o.workspace && !j.o.workspace_bytes) return MSP_E_INVALID;
+    uint64_t budget = j.o.workspace_bytes;
+    if (!j.o.workspace && !budget) {
         size_t fr = 0, tot = 0;
         if (hipMemGetInfo(&fr, &tot) != hipSuccess) return MSP_E_NOLIB;
         budget = std::min<uint64_t>((uint64_t)(fr * 0.6), (uint64_t)64 << 30);
     }
-    Prepared P;
-    int rc = prepare(c, o, budget, P);
+    int rc = prepare(c, j.o, budget, j.P);
     if (rc) return rc;
-    const Plan &p = P.p;
-    const Sizes &z = P.z;
-    msp_stats_t st{};
-    st.key_rows = p.r;
-    st.log2_m = p.log2M;
-    st.log2_cells = p.log2T;
-    st.parts = p.parts;
-    st.exact_buckets = p.exact;
-    st.words = p.W;
-    st.record_bytes = rec_bytes(p.W);
-    c->sol.clear();
-    c->stored = 0;
-    if (P.infeasible) {
-        c->h_lo = c->h_hi = c->nsol = 0;
-        st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-        c->stats = st;
-        c->have_result = true;
+    job_init_stats(j);
+    if (j.P.infeasible) {
+        job_trivial(j);
         return MSP_OK;
     }
-
-    hipStream_t s = (hipStream_t)o.stream;
-    char *ws = nullptr;
-    DevBufs b{};
-    uint64_t scal[S_COUNT] = {0};
-    std::vector<uint64_t> solbuf;
-    if (!s) {
+    j.s = (hipStream_t)j.o.stream;
+    if (!j.s) {
         if (!c->own_stream && hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking) != hipSuccess)
             return MSP_E_DEVICE;
-        s = c->own_stream;
+        j.s = c->own_stream;
     }
-    for (auto &e : c->ev)
-        if (!e && hipEventCreate(&e) != hipSuccess) return MSP_E_DEVICE;
-    if (o.workspace) {
-        ws = (char *)o.workspace;
+    if (j.o.workspace) {
+        j.ws = (char *)j.o.workspace;
     } else {
-        if (c->ws_bytes < z.total) {
+        if (c->ws_bytes < j.P.z.total) {
             if (c->ws) (void)hipFree(c->ws);
             c->ws = nullptr;
             c->ws_bytes = 0;
-            if (hipMalloc(&c->ws, z.total) != hipSuccess) {
+            if (hipMalloc(&c->ws, j.P.z.total) != hipSuccess) {
                 (void)hipGetLastError();
                 return MSP_E_NOMEM;
             }
-            c->ws_bytes = z.total;
+            c->ws_bytes = j.P.z.total;
         }
-        ws = (char *)c->ws;
+        j.ws = (char *)c->ws;
     }
-    for (int x = 0; x < 4; ++x) {
-        b.qraw[x] = ws + z.o_qraw[x];
-        b.qsrt[x] = ws + z.o_qsrt[x];
-        b.qcnt[x] = (uint32_t *)(ws + z.o_qcnt[x]);
-        b.qcur[x] = (uint32_t *)(ws + z.o_qcur[x]);
-    }
-    for (int sd = 0; sd < 2; ++sd) {
-        b.cnt[sd] = (uint32_t *)(ws + z.o_cnt[sd]);
-        b.off[sd] = (uint32_t *)(ws + z.o_off[sd]);
-        b.rec[sd] = ws + z.o_rec[sd];
-    }
-    b.runs = (RunPair *)(ws + z.o_runs);
-    b.tiles = (uint32_t *)(ws + z.o_tiles);
-    b.sol = (uint64_t *)(ws + z.o_sol);
-    b.scal = (uint64_t *)(ws + z.o_scal);
-    b.scan_tmp = ws + z.o_scan;
-    b.scan_tmp_bytes = z.scan_bytes;
-    b.colw = (int64_t *)(ws + z.o_colw);
-    b.rows = (uint16_t *)(ws + z.o_rows);
-
-    {
-        const uint64_t T = (uint64_t)1 << p.log2T;
-        const int F = 1 << p.log2F;
-        HIPCHK(hipMemcpyAsync(b.colw, P.colw.data(), P.colw.size() * 8, hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemcpyAsync(b.rows, P.rows.data(), P.rows.size() * 2, hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemsetAsync(b.scal, 0, S_COUNT * 8, s));
-        for (int x = 0; x < 4; ++x) HIPCHK(hipMemsetAsync(b.qcnt[x], 0, (T + 1) * 4, s));
-        HIPCHK(hipEventRecord(c->ev[0], s));
-        HIPCHK(launch_quarters(p, b, 0, s));
-        HIPCHK(hipEventRecord(c->ev[1], s));
-
-        uint64_t idx = 0;
-        uint64_t kw = z.kwin;
-        const uint64_t rb = rec_bytes(p.W);
-        (void)rb;
-        while (idx < z.ncells) {
-            uint64_t K = std::min<uint64_t>(kw, z.ncells - idx);
-            uint64_t totL = 0, totR = 0;
-            for (;;) {
-                const size_t ncnt = (size_t)K * F * p.parts;
-                HIPCHK(hipEventRecord(c->ev[2], s));
-                HIPCHK(launch_count(p, b, (int64_t)idx, (int32_t)K, s));
-                HIPCHK(hipEventRecord(c->ev[3], s));
-                HIPCHK(scan_u32(b.cnt[0], b.off[0], ncnt, &b.scal[S_TOT_L], b.scan_tmp, b.scan_tmp_bytes, s));
-                HIPCHK(scan_u32(b.cnt[1], b.off[1], ncnt, &b.scal[S_TOT_R], b.scan_tmp, b.scan_tmp_bytes, s));
-                HIPCHK(hipEventRecord(c->ev[4], s));
-                HIPCHK(hipMemcpyAsync(scal, b.scal, S_COUNT * 8, hipMemcpyDeviceToHost, s));
-                HIPCHK(hipStreamSynchronize(s));
-                st.ms_count += ev_ms(c->ev[2], c->ev[3]);
-                st.ms_scan += ev_ms(c->ev[3], c->ev[4]);
-                totL = scal[S_TOT_L];
-                totR = scal[S_TOT_R];
-                if (totL <= z.cap_rec && totR <= z.cap_rec) break;
-                if (K == 1) { rc = MSP_E_NOMEM; goto fail; }
-                K = (K + 1) / 2;
-                kw = K;
-            }
-            st.records_left += totL;
-            st.records_right += totR;
-            HIPCHK(hipMemsetAsync(&b.scal[S_NRUNS], 0, 8, s));
-            HIPCHK(hipEventRecord(c->ev[2], s));
-            HIPCHK(launch_scatter(p, b, (int64_t)idx, (int32_t)K, s));
-            HIPCHK(hipEventRecord(c->ev[3], s));
-            if (p.exact)
-                HIPCHK(launch_exact_runs(p, b, (int32_t)K, s));
-            else
-                HIPCHK(launch_hash_join(p, b, (int32_t)K, z.sol_cap, s));
-            HIPCHK(hipEventRecord(c->ev[4], s));
-            HIPCHK(hipMemcpyAsync(scal, b.scal, S_COUNT * 8, hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            st.ms_scatter += ev_ms(c->ev[2], c->ev[3]);
-            st.ms_join += ev_ms(c->ev[3], c->ev[4]);
-            const uint32_t nruns = (uint32_t)scal[S_NRUNS];
-            if (nruns) {
-                HIPCHK(launch_tile_counts(p, b, nruns, !p.exact, s));
-                HIPCHK(scan_u32(b.tiles, b.tiles, nruns, &b.scal[S_TOT_TILES], b.scan_tmp, b.scan_tmp_bytes, s));
-                HIPCHK(hipMemcpyAsync(&scal[S_TOT_TILES], &b.scal[S_TOT_TILES], 8, hipMemcpyDeviceToHost, s));
-                HIPCHK(hipStreamSynchronize(s));
-                const uint32_t ntiles = (uint32_t)scal[S_TOT_TILES];
-                HIPCHK(hipEventRecord(c->ev[5], s));
-                HIPCHK(launch_verify(p, b, nruns, ntiles, z.sol_cap, !p.exact, s));
-                HIPCHK(hipEventRecord(c->ev[6], s));
-                HIPCHK(hipEventSynchronize(c->ev[6]));
-                st.ms_verify += ev_ms(c->ev[5], c->ev[6]);
-                st.verify_launches++;
-            }
-            st.windows++;
-            idx += K;
+    job_carve(j);
+    rc = job_setup_events(j);
+    while (rc == MSP_OK && j.next != A_DONE) {
+        rc = job_step(j);
+        if (rc == MSP_OK && j.next != A_DONE && hipStreamSynchronize(j.s) != hipSuccess) {
+            (void)hipGetLastError();
+            rc = MSP_E_DEVICE;
         }
-        HIPCHK(hipMemcpyAsync(scal, b.scal, S_COUNT * 8, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        st.ms_quarters = ev_ms(c->ev[0], c->ev[1]);
-        c->h_lo = scal[S_H_LO];
-        c->h_hi = scal[S_H_HI];
-        c->nsol = scal[S_NSOL];
-        const uint64_t stored = std::min<uint64_t>(z.sol_cap, p.W == 0 ? scal[S_STORED] : scal[S_NSOL]);
-        solbuf.resize(stored * 2);
-        if (stored) {
-            HIPCHK(hipMemcpyAsync(solbuf.data(), b.sol, stored * 16, hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-        }
-        // Expand half masks to x (columns of the left half first) and sort
-        // canonically (lexicographic on x_1..x_n, 0 < 1).
-        const int n = c->n;
-        std::vector<uint8_t> xs(stored * n);
-        for (uint64_t k = 0; k < stored; ++k) {
-            const uint64_t ml = solbuf[2 * k], mr = solbuf[2 * k + 1];
-            for (int j = 0; j < n; ++j)
-                xs[k * n + j] = (uint8_t)(j < p.hL ? (ml >> j) & 1u : (mr >> (j - p.hL)) & 1u);
-        }
-        std::vector<uint64_t> ord(stored);
-        std::iota(ord.begin(), ord.end(), 0);
-        std::sort(ord.begin(), ord.end(), [&](uint64_t a, uint64_t bb) {
-            return std::memcmp(&xs[a * n], &xs[bb * n], n) < 0;
-        });
-        c->sol.resize(stored * n);
-        for (uint64_t k = 0; k < stored; ++k) std::memcpy(&c->sol[k * n], &xs[ord[k] * n], n);
-        c->stored = stored;
     }
-    st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    c->stats = st;
-    c->have_result = true;
-    return MSP_OK;
-fail:
-    (void)hipGetLastError();
+    job_release_events(j);
     if (rc == MSP_E_DEVICE) c->poisoned = true;
     return rc;
+}
+
+int msp_batch_solve(msp_ctx *const *ctxs, const msp_opts *opts, int32_t count,
+                    const msp_batch_opts *bo) {
+    if (!ctxs || count < 0) return MSP_E_INVALID;
+    for (int32_t i = 0; i < count; ++i)
+        if (!ctxs[i]) return MSP_E_INVALID;
+    Runner run;
+    int rc = run.init(bo ? bo->hbm_budget : 0, bo ? bo->max_slots : 0);
+    if (rc) { run.shutdown(); return rc; }
+    std::vector<Job> jobs(count);
+    for (int32_t i = 0; i < count; ++i) {
+        Job &j = jobs[i];
+        j.c = ctxs[i];
+        msp_default_opts(&j.o);
+        if (opts) j.o = opts[i];
+        j.o.workspace = nullptr;
+        j.o.stream = nullptr;
+        j.c->have_result = false;
+        run.plan(j);
+        run.pending.push_back(&j);
+    }
+    std::vector<Job *> done;
+    while (!run.pending.empty() || !run.active.empty()) {
+        run.admit(done);
+        if (run.active.empty()) {
+            if (!run.pending.empty()) {      // head cannot fit even alone
+                run.pending.front()->rc = MSP_E_NOMEM;
+                done.push_back(run.pending.front());
+                run.pending.pop_front();
+            }
+            continue;
+        }
+        run.step(done);
+    }
+    run.shutdown();
+    int first = MSP_OK;
+    for (auto &j : jobs)
+        if (j.rc != MSP_OK && first == MSP_OK) first = j.rc;
+    return first;
+}
+
+int msp_server_start(const msp_server_opts *o, msp_server **out) {
+    if (!out) return MSP_E_INVALID;
+    *out = nullptr;
+    msp_server *sv = new (std::nothrow) msp_server();
+    if (!sv) return MSP_E_NOMEM;
+    int rc = sv->run.init(o ? o->hbm_budget : 0, o ? o->max_slots : 0);
+    if (rc) {
+        sv->run.shutdown();
+        delete sv;
+        return rc;
+    }
+    sv->th = std::thread(server_loop, sv);
+    *out = sv;
+    return MSP_OK;
+}
+
+int msp_server_submit(msp_server *sv, msp_ctx *c, const msp_opts *o, uint64_t *ticket) {
+    if (!sv || !c || !ticket) return MSP_E_INVALID;
+    int expect = 0;
+    if (!c->busy.compare_exchange_strong(expect, 1)) return MSP_E_BUSY;
+    Job *j = new (std::nothrow) Job();
+    if (!j) { c->busy.store(0); return MSP_E_NOMEM; }
+    j->c = c;
+    msp_default_opts(&j->o);
+    if (o) j->o = *o;
+    j->o.workspace = nullptr;
+    j->o.stream = nullptr;
+    c->have_result = false;
+    sv->run.plan(*j);                       // host-only planning, before queueing
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->stopping) { c->busy.store(0); delete j; return MSP_E_STATE; }
+    j->ticket = sv->next_ticket++;
+    j->t_submit = now_s() - sv->run.t0;
+    sv->jobs[j->ticket] = j;
+    sv->inbox.push_back(j);
+    *ticket = j->ticket;
+    sv->cv.notify_all();
+    return MSP_OK;
+}
+
+int msp_server_poll(msp_server *sv, uint64_t ticket, int32_t *done, int32_t *status) {
+    if (!sv || !done) return MSP_E_INVALID;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->jobs.find(ticket);
+    if (it == sv->jobs.end()) return MSP_E_INVALID;
+    Job *j = it->second;
+    *done = j->t_finish > 0 ? 1 : 0;
+    if (status) *status = *done ? j->rc : MSP_OK;
+    return MSP_OK;
+}
+
+int msp_server_wait(msp_server *sv, uint64_t ticket, int32_t *status) {
+    if (!sv) return MSP_E_INVALID;
+    std::unique_lock<std::mutex> lk(sv->mu);
+    auto it = sv->jobs.find(ticket);
+    if (it == sv->jobs.end()) return MSP_E_INVALID;
+    Job *j = it->second;
+    sv->cv_done.wait(lk, [&] { return j->t_finish > 0; });
+    if (status) *status = j->rc;
+    return MSP_OK;
+}
+
+int msp_server_cancel(msp_server *sv, uint64_t ticket) {
+    if (!sv) return MSP_E_INVALID;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->jobs.find(ticket);
+    if (it == sv->jobs.end()) return MSP_E_INVALID;
+    Job *j = it->second;
+    if (j->t_finish > 0) return MSP_OK;
+    for (auto p = sv->inbox.begin(); p != sv->inbox.end(); ++p) {
+        if (*p == j) {                       // not yet seen by the scheduler
+            sv->inbox.erase(p);
+            j->rc = MSP_E_CANCELLED;
+            j->t_finish = now_s() - sv->run.t0;
+            j->c->busy.store(0);
+            sv->cv_done.notify_all();
+            return MSP_OK;
+        }
+    }
+    j->c->busy.store(2);                    // the scheduler stops it at the next window
+    sv->cv.notify_all();
+    return MSP_OK;
+}
+
+int msp_server_times(msp_server *sv, uint64_t ticket, double *t4) {
+    if (!sv || !t4) return MSP_E_INVALID;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->jobs.find(ticket);
+    if (it == sv->jobs.end()) return MSP_E_INVALID;
+    const Job *j = it->second;
+    t4[0] = j->t_submit;
+    t4[1] = j->t_admit;
+    t4[2] = j->t_start;
+    t4[3] = j->t_finish;
+    return MSP_OK;
+}
+
+int msp_server_stop(msp_server *sv) {
+    if (!sv) return MSP_E_INVALID;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->stopping = true;
+        sv->cv.notify_all();
+    }
+    if (sv->th.joinable()) sv->th.join();
+    sv->run.shutdown();
+    for (auto &kv : sv->jobs) delete kv.second;
+    delete sv;
+    return MSP_OK;
 }
 
 int msp_num_solutions(const msp_ctx *c, uint64_t *count) {

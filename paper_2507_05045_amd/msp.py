@@ -21,6 +21,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libmsp.so")
 
 MSP_OK = 0
+MSP_E_CANCELLED = -7
 MSP_E_TRUNCATED = -8
 
 
@@ -49,10 +50,16 @@ class msp_stats_t(C.Structure):
                 ("words", C.c_int32)]
 
 
+class msp_batch_opts(C.Structure):
+    _fields_ = [("hbm_budget", C.c_uint64), ("max_slots", C.c_int32), ("reserved", C.c_int32)]
+
+
 # Every symbol include/msp.h declares (checked by the CPU test suite).
 EXPORTS = ["msp_create", "msp_default_opts", "msp_solve", "msp_num_solutions", "msp_hits",
            "msp_get_solutions", "msp_stats", "msp_destroy", "msp_strerror",
-           "msp_workspace_bytes"]
+           "msp_workspace_bytes", "msp_batch_solve", "msp_server_start", "msp_server_submit",
+           "msp_server_poll", "msp_server_wait", "msp_server_cancel", "msp_server_times",
+           "msp_server_stop"]
 
 # PyTorch-ROCm ships its own HIP runtime with the same soname as the system
 # one.  Load torch first so that libmsp binds to the runtime torch uses:
@@ -87,6 +94,22 @@ lib.msp_strerror.argtypes = [C.c_int]
 lib.msp_strerror.restype = C.c_char_p
 lib.msp_workspace_bytes.argtypes = [C.c_void_p, _p(msp_opts)]
 lib.msp_workspace_bytes.restype = C.c_uint64
+lib.msp_batch_solve.argtypes = [_p(C.c_void_p), _p(msp_opts), C.c_int32, _p(msp_batch_opts)]
+lib.msp_batch_solve.restype = C.c_int
+lib.msp_server_start.argtypes = [_p(msp_batch_opts), _p(C.c_void_p)]
+lib.msp_server_start.restype = C.c_int
+lib.msp_server_submit.argtypes = [C.c_void_p, C.c_void_p, _p(msp_opts), _p(C.c_uint64)]
+lib.msp_server_submit.restype = C.c_int
+lib.msp_server_poll.argtypes = [C.c_void_p, C.c_uint64, _p(C.c_int32), _p(C.c_int32)]
+lib.msp_server_poll.restype = C.c_int
+lib.msp_server_wait.argtypes = [C.c_void_p, C.c_uint64, _p(C.c_int32)]
+lib.msp_server_wait.restype = C.c_int
+lib.msp_server_cancel.argtypes = [C.c_void_p, C.c_uint64]
+lib.msp_server_cancel.restype = C.c_int
+lib.msp_server_times.argtypes = [C.c_void_p, C.c_uint64, _p(C.c_double)]
+lib.msp_server_times.restype = C.c_int
+lib.msp_server_stop.argtypes = [C.c_void_p]
+lib.msp_server_stop.restype = C.c_int
 
 
 def strerror(code: int) -> str:
@@ -202,3 +225,58 @@ def solve(A, d, **kw) -> Result:
         return ctx.result()
     finally:
         ctx.close()
+
+
+def batch_solve(contexts, opts=None, hbm_budget: int = 0, max_slots: int = 0) -> int:
+    """msp_batch_solve over Context objects; opts is None, one dict for all,
+    or a list of dicts (msp_opts fields).  Returns the status code; each
+    context holds its own result (or raises on read if it failed)."""
+    n = len(contexts)
+    arr = (C.c_void_p * max(n, 1))(*[c._ctx.value for c in contexts])
+    if opts is None:
+        oarr = None
+    else:
+        lst = opts if isinstance(opts, (list, tuple)) else [opts] * n
+        oarr = (msp_opts * max(n, 1))(*[msp_default_opts(**o) for o in lst])
+    bo = msp_batch_opts(hbm_budget, max_slots, 0)
+    return lib.msp_batch_solve(arr, oarr, n, C.byref(bo))
+
+
+class Server:
+    """msp_server_*: a continuous-batching request loop on its own thread."""
+
+    def __init__(self, hbm_budget: int = 0, max_slots: int = 0):
+        self._s = C.c_void_p()
+        bo = msp_batch_opts(hbm_budget, max_slots, 0)
+        _check(lib.msp_server_start(C.byref(bo), C.byref(self._s)), "msp_server_start")
+        self._keep = {}
+
+    def submit(self, ctx: Context, **kw) -> int:
+        t = C.c_uint64()
+        _check(lib.msp_server_submit(self._s, ctx._ctx, C.byref(msp_default_opts(**kw)),
+                                     C.byref(t)), "msp_server_submit")
+        self._keep[t.value] = ctx
+        return t.value
+
+    def poll(self, ticket: int):
+        done, st = C.c_int32(), C.c_int32()
+        _check(lib.msp_server_poll(self._s, ticket, C.byref(done), C.byref(st)), "msp_server_poll")
+        return bool(done.value), st.value
+
+    def wait(self, ticket: int) -> int:
+        st = C.c_int32()
+        _check(lib.msp_server_wait(self._s, ticket, C.byref(st)), "msp_server_wait")
+        return st.value
+
+    def cancel(self, ticket: int):
+        _check(lib.msp_server_cancel(self._s, ticket), "msp_server_cancel")
+
+    def times(self, ticket: int):
+        t4 = (C.c_double * 4)()
+        _check(lib.msp_server_times(self._s, ticket, t4), "msp_server_times")
+        return tuple(t4)
+
+    def stop(self):
+        if self._s:
+            _check(lib.msp_server_stop(self._s), "msp_server_stop")
+            self._s = C.c_void_p()
