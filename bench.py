@@ -77,13 +77,130 @@ def cpu_baseline(w, insts, budget_s=30.0):
                       f"meet-in-the-middle oracle, H={H}, {dt:.2f} s"}
 
 
+def _pct(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs, dtype=float), q)) if len(xs) else None
+
+
+def run_stream(args):
+    """Uneven stream (m in {5..8}, n = 10(m-1), r = m - 4, odd instances
+    planted): plain one-at-a-time solves, one batched solve, and a served run
+    with Poisson arrivals at twice the plain rate, plus a closed-loop served
+    run with every request at t = 0."""
+    import threading
+    import torch
+    from paper_2507_05045_amd import autotune, msp
+    from paper_2507_05045_amd.inputs import poisson_arrivals, stream_instances
+
+    insts = stream_instances(args.stream_count)
+    opts = []
+    for i in insts:
+        o = dict(key_rows=i.key_rows)
+        t = autotune.lookup(i.A, i.key_rows)
+        if t:
+            o.update(t)
+        opts.append(o)
+    # Warm-up: one solve per (m, n) class.
+    seen = set()
+    for i, o in zip(insts, opts):
+        if i.m not in seen:
+            seen.add(i.m)
+            c = msp.Context(i.A, i.d)
+            c.solve(use_torch=False, **o)
+            c.close()
+    torch.cuda.synchronize()
+
+    # Plain: one instance at a time.
+    lat, hits = [], 0
+    t0 = time.perf_counter()
+    ref = []
+    for i, o in zip(insts, opts):
+        t1 = time.perf_counter()
+        c = msp.Context(i.A, i.d)
+        c.solve(use_torch=False, **o)
+        ref.append((c.hits(), c.num_solutions()))
+        hits += ref[-1][0]
+        c.close()
+        lat.append(time.perf_counter() - t1)
+    t_plain = time.perf_counter() - t0
+    plain = {"makespan_s": t_plain, "hits_per_s": hits / t_plain,
+             "instances_per_s": len(insts) / t_plain,
+             "p50_ms": _pct(lat, 50) * 1e3, "p99_ms": _pct(lat, 99) * 1e3}
+
+    # Batched: one msp_batch_solve over the whole stream.
+    ctxs = [msp.Context(i.A, i.d) for i in insts]
+    t0 = time.perf_counter()
+    rc = msp.batch_solve(ctxs, opts, max_slots=16)
+    t_batch = time.perf_counter() - t0
+    assert rc == 0, msp.strerror(rc)
+    assert all((c.hits(), c.num_solutions()) == r for c, r in zip(ctxs, ref)), "batched != plain"
+    batched = {"makespan_s": t_batch, "hits_per_s": hits / t_batch,
+               "instances_per_s": len(insts) / t_batch}
+    for c in ctxs:
+        c.close()
+
+    def served(arrivals):
+        srv = msp.Server(max_slots=16)
+        cs = [msp.Context(i.A, i.d) for i in insts]
+        tickets = [None] * len(insts)
+
+        def feeder():
+            start = time.perf_counter()
+            for k, (c, o) in enumerate(zip(cs, opts)):
+                dt = arrivals[k] - (time.perf_counter() - start)
+                if dt > 0:
+                    time.sleep(dt)
+                tickets[k] = srv.submit(c, **o)
+
+        th = threading.Thread(target=feeder)
+        t0 = time.perf_counter()
+        th.start()
+        th.join()
+        for t in tickets:
+            assert srv.wait(t) == 0
+        make = time.perf_counter() - t0
+        times = [srv.times(t) for t in tickets]
+        assert all((c.hits(), c.num_solutions()) == r for c, r in zip(cs, ref)), "served != plain"
+        lat = [(t[3] - t[0]) for t in times]
+        first, last = min(t[0] for t in times), max(t[3] for t in times)
+        srv.stop()
+        for c in cs:
+            c.close()
+        return {"makespan_s": make, "hits_per_s": hits / (last - first),
+                "p50_ms": _pct(lat, 50) * 1e3, "p99_ms": _pct(lat, 99) * 1e3,
+                "mean_queue_ms": sum(t[1] - t[0] for t in times) / len(times) * 1e3}
+
+    rate = 2.0 * plain["instances_per_s"]
+    poisson = served(poisson_arrivals(len(insts), rate, seed=7))
+    poisson["rate_per_s"] = rate
+    closed = served([0.0] * len(insts))
+    ms = [int(i.m) for i in insts]
+    out = {
+        "metric": "1-D hits verified/s (served stream) + p50/p99 latency",
+        "value": poisson["hits_per_s"], "unit": "hits/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": poisson["makespan_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u16x2/i64", "data": "synthetic",
+        "config": {"workload": f"stream of {len(insts)} instances, m in 5..8 "
+                               f"({', '.join(f'{m}:{ms.count(m)}' for m in (5, 6, 7, 8))}), "
+                               "n = 10(m-1), key rows m-4, odd instances planted",
+                   "instances": len(insts)},
+        "hits_total": hits,
+        "plain": plain, "batched": batched, "served_poisson": poisson, "served_closed": closed,
+        "speedup_vs_plain": {"batched": t_plain / t_batch,
+                             "served_closed": t_plain / closed["makespan_s"]},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="6_50", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="6_50", choices=sorted(WORKLOADS) + ["stream"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--stream-count", type=int, default=64,
+                    help="instances of the uneven stream for --workload stream")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -107,6 +224,8 @@ def main():
     from paper_2507_05045_amd import msp
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.workload == "stream":
+        return run_stream(args)
     w = WORKLOADS[args.workload]
     insts = build_instances(w)
     ctxs = [msp.Context(i.A, i.d) for i in insts]

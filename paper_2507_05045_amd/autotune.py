@@ -1,0 +1,127 @@
+"""Autotuner for the solve plan: residue modulus M = 2^log2_m, residue cells
+T = 2^log2_cells and work-groups per cell (parts).
+
+For an instance class (m, n, key rows r, coefficient bound) it times a few
+candidates around the planner's default on a residue slice of a
+representative instance (the slice k_L mod 2^s = 0 keeps 1/2^s of the cells,
+so timing stays short), checks that every candidate returns the same 1-D hit
+count (the plan must never change the result), and caches the fastest in a
+JSON file keyed by GPU architecture and class.  The cache path is
+``$MSP_TUNE_CACHE`` or ``~/.cache/msp_tune.json``.
+
+All timing goes through the C ABI (``msp_solve``); nothing here computes any
+part of the solve.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+from typing import Dict, Optional
+
+from . import msp
+
+CACHE = os.environ.get("MSP_TUNE_CACHE", os.path.expanduser("~/.cache/msp_tune.json"))
+# Plans tuned on an MI355X for the workloads of this repository, shipped
+# with the package and consulted when the user cache has no entry.
+SHIPPED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_gfx950.json")
+
+
+def _arch() -> str:
+    try:
+        import torch
+        return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    except Exception:  # no torch or no GPU: still a valid cache key
+        return "gfx950"
+
+
+def class_key(A, key_rows: int) -> str:
+    import numpy as np
+    A = np.asarray(A)
+    return f"{_arch()}:m{A.shape[0]}:n{A.shape[1]}:r{key_rows}:amax{int(A.max())}"
+
+
+def _load() -> Dict[str, dict]:
+    try:
+        with open(CACHE) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _save(cache: Dict[str, dict]):
+    os.makedirs(os.path.dirname(CACHE) or ".", exist_ok=True)
+    tmp = CACHE + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, CACHE)
+
+
+def lookup(A, key_rows: int) -> Optional[dict]:
+    key = class_key(A, key_rows)
+    hit = _load().get(key)
+    if hit is None:
+        try:
+            with open(SHIPPED) as f:
+                hit = json.load(f).get(key)
+        except (OSError, ValueError):
+            hit = None
+    return hit["opts"] if hit else None
+
+
+def tune(A, d, key_rows: int = 1, max_seconds: float = 20.0, slice_bits: Optional[int] = None,
+         force: bool = False, verbose: bool = False) -> dict:
+    """Return the fastest plan options for this instance's class (cached)."""
+    key = class_key(A, key_rows)
+    cache = _load()
+    if key in cache and not force:
+        return cache[key]["opts"]
+    ctx = msp.Context(A, d)
+    ctx.solve(key_rows=key_rows)
+    base = ctx.stats()
+    full_ms = base["ms_total"]
+    lm, lc, parts = base["log2_m"], base["log2_cells"], base["parts"]
+    if slice_bits is None:
+        # Aim at ~0.2 s per timed solve; the slice must stay a set of cells.
+        s = 0
+        while full_ms / (1 << s) > 200.0 and s < min(lc, 10):
+            s += 1
+        slice_bits = s
+    sl = dict(slice_mod=(1 << slice_bits) if slice_bits else 0, slice_res=0)
+    cands = []
+    for dm in ((0,) if base["exact_buckets"] else (0, -1, 1)):
+        for dc in (0, -1, 1):
+            m2, c2 = lm + dm, lc + dc
+            if c2 < max(slice_bits, 0) or c2 > m2 or m2 - c2 > 12 or c2 > 23 or m2 < 1:
+                continue
+            for p2 in sorted({parts, parts * 2, parts * 4}):
+                cands.append(dict(log2_m=m2, log2_cells=c2, parts=min(p2, 256)))
+    t_end = time.time() + max_seconds
+    best, best_t, ref_h = None, float("inf"), None
+    for c in cands:
+        if time.time() > t_end:
+            break
+        try:
+            ctx.solve(key_rows=key_rows, **c, **sl)
+        except msp.MspError:
+            continue
+        h = ctx.hits()
+        if ref_h is None:
+            ref_h = h
+        if h != ref_h:
+            raise RuntimeError(f"plan {c} changed the hit count: {h} != {ref_h}")
+        t0 = time.perf_counter()
+        ctx.solve(key_rows=key_rows, **c, **sl)
+        dt = time.perf_counter() - t0
+        if verbose:
+            print(f"  {c} {dt * 1e3:.1f} ms", flush=True)
+        if dt < best_t:
+            best, best_t = c, dt
+    ctx.close()
+    if best is None:
+        best = dict(log2_m=lm, log2_cells=lc, parts=parts)
+    cache = _load()
+    cache[key] = {"opts": best, "slice_bits": slice_bits, "ms_slice": best_t * 1e3,
+                  "default": dict(log2_m=lm, log2_cells=lc, parts=parts)}
+    _save(cache)
+    return best

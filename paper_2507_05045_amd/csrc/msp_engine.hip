@@ -201,7 +201,7 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
     }
     int parts = o.parts;
     if (!parts) {
-        const uint64_t target = 2048;
+        const uint64_t target = 8192;            // work-groups per launch (tuned: 4x fill)
         parts = (int)std::min<uint64_t>(64, std::max<uint64_t>(1, (target + kwin - 1) / kwin));
         parts = (int)std::min<uint64_t>(parts, std::max<uint64_t>(1, p.Q[0] / 256));
         parts = (int)std::min<uint64_t>(parts, std::max<uint64_t>(1, p.Q[2] / 256));
