@@ -664,7 +664,31 @@ __device__ __forceinline__ uint32_t fingerprint(const uint32_t *v) {
     return h;
 }
 
-template <int W, bool CK, int kKR>
+// Lanes of this wave whose 8 right fingerprints hold any of the 4 left
+// fingerprints q.x..q.w.  Each v_cmpx_ne clears the EXEC bit of a lane that
+// saw equality, so the 32 compares need no scalar work; the flagged lanes
+// are EXEC before XOR EXEC after, and EXEC is restored inside the block.
+#define MSP_CMPX(r, l) "v_cmpx_ne_u32_e32 vcc, %" #r ", %" #l "\n\t"
+#define MSP_CMPX8(l) MSP_CMPX(2, l) MSP_CMPX(3, l) MSP_CMPX(4, l) MSP_CMPX(5, l) \
+                     MSP_CMPX(6, l) MSP_CMPX(7, l) MSP_CMPX(8, l) MSP_CMPX(9, l)
+__device__ __forceinline__ uint64_t match4x8(const uint32_t *rf, uint4 q) {
+    uint64_t save, flag;
+    asm volatile(
+        "s_mov_b64 %0, exec\n\t"
+        MSP_CMPX8(10) MSP_CMPX8(11) MSP_CMPX8(12) MSP_CMPX8(13)
+        "s_nop 4\n\t"
+        "s_xor_b64 %1, exec, %0\n\t"
+        "s_mov_b64 exec, %0\n\t"
+        : "=&s"(save), "=&s"(flag)
+        : "v"(rf[0]), "v"(rf[1]), "v"(rf[2]), "v"(rf[3]), "v"(rf[4]), "v"(rf[5]), "v"(rf[6]),
+          "v"(rf[7]), "v"(q.x), "v"(q.y), "v"(q.z), "v"(q.w)
+        : "vcc");
+    return flag;
+}
+#undef MSP_CMPX8
+#undef MSP_CMPX
+
+template <int W, bool CK, int kKR, bool CMPX = false>
 __global__ __launch_bounds__(256) void k_verify(Plan p, const Rec<W> *__restrict__ L,
                                                 const Rec<W> *__restrict__ R,
                                                 const RunPair *__restrict__ runs,
@@ -739,14 +763,18 @@ __global__ __launch_bounds__(256) void k_verify(Plan p, const Rec<W> *__restrict
             for (; j + 4 <= cn; j += 4) {
                 const uint4 q = *reinterpret_cast<const uint4 *>(&s_fp[j]);
                 uint64_t acc = 0;
+                if constexpr (CMPX && kKR == 8) {
+                    acc = match4x8(rf, q);
+                } else {
 #pragma unroll
-                for (int k = 0; k < kKR; ++k) acc |= __builtin_amdgcn_ballot_w64(rf[k] == q.x);
+                    for (int k = 0; k < kKR; ++k) acc |= __builtin_amdgcn_ballot_w64(rf[k] == q.x);
 #pragma unroll
-                for (int k = 0; k < kKR; ++k) acc |= __builtin_amdgcn_ballot_w64(rf[k] == q.y);
+                    for (int k = 0; k < kKR; ++k) acc |= __builtin_amdgcn_ballot_w64(rf[k] == q.y);
 #pragma unroll
-                for (int k = 0; k < kKR; ++k) acc |= __builtin_amdgcn_ballot_w64(rf[k] == q.z);
+                    for (int k = 0; k < kKR; ++k) acc |= __builtin_amdgcn_ballot_w64(rf[k] == q.z);
 #pragma unroll
-                for (int k = 0; k < kKR; ++k) acc |= __builtin_amdgcn_ballot_w64(rf[k] == q.w);
+                    for (int k = 0; k < kKR; ++k) acc |= __builtin_amdgcn_ballot_w64(rf[k] == q.w);
+                }
                 if (__builtin_expect(acc != 0, 0)) {
 #pragma unroll
                     for (int k = 0; k < kKR; ++k) {
@@ -1022,10 +1050,20 @@ int verify_kr() {
     return kr;
 }
 
+// The EXEC-mask candidate test (v_cmpx) is the default; MSP_VERIFY_CMPX=0
+// selects the ballot-OR form (one scalar OR per compare).
+bool verify_cmpx() {
+    static bool on = [] {
+        const char *e = getenv("MSP_VERIFY_CMPX");
+        return !(e && atoi(e) == 0);
+    }();
+    return on;
+}
+
 hipError_t launch_tile_counts(const Plan &, const DevBufs &b, uint32_t nruns, int ck,
                               hipStream_t st) {
     if (nruns == 0) return hipSuccess;
-    const uint32_t tile_r = 256u * (ck ? 8 : verify_kr());
+    const uint32_t tile_r = 256u * ((ck || verify_cmpx()) ? 8 : verify_kr());
     hipLaunchKernelGGL(k_tile_counts, dim3((nruns + 255) / 256), dim3(256), 0, st, b.runs, b.scal,
                        b.tiles, tile_r);
     return hipGetLastError();
@@ -1036,6 +1074,10 @@ static hipError_t verify_impl(const Plan &p, const DevBufs &b, uint32_t nruns, u
                               uint64_t cap, int ck, hipStream_t st) {
     if (ck)
         hipLaunchKernelGGL((k_verify<W, true, 8>), dim3(ntiles), dim3(256), 0, st, p,
+                           (const Rec<W> *)b.rec[0], (const Rec<W> *)b.rec[1], b.runs, b.tiles,
+                           nruns, b.scal, b.sol, cap);
+    else if (verify_cmpx())
+        hipLaunchKernelGGL((k_verify<W, false, 8, true>), dim3(ntiles), dim3(256), 0, st, p,
                            (const Rec<W> *)b.rec[0], (const Rec<W> *)b.rec[1], b.runs, b.tiles,
                            nruns, b.scal, b.sol, cap);
     else if (verify_kr() == 16)
