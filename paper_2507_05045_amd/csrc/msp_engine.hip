@@ -52,6 +52,7 @@ struct Sizes {
     // offsets into the workspace
     uint64_t o_qraw[4], o_qsrt[4], o_qcnt[4], o_qcur[4], o_cnt[2], o_off[2], o_rec[2];
     uint64_t o_runs, o_tiles, o_sol, o_scal, o_scan, scan_bytes, o_colw, o_rows;
+    uint64_t o_iruns, o_itiles, o_idx, n_iruns;
 };
 
 struct Prepared {
@@ -220,9 +221,18 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
         for (int s = 0; s < 2; ++s) z.o_rec[s] = take(cap_rec * rb);
         z.o_runs = take(kw * F * sizeof(RunPair));
         z.o_tiles = take((kw * F + 1) * 4);
+        // Large equal-key groups exported by the hash join: each has at
+        // least kBigPairs pairs, hence at least 2*sqrt(kBigPairs) = 128
+        // records, so there are at most 2*cap_rec/128 of them.
+        const uint64_t nI = p.exact ? 1 : cap_rec / 64 + 1024;
+        z.n_iruns = nI;
+        z.o_iruns = take(nI * sizeof(RunPair));
+        z.o_itiles = take((nI + 1) * 4);
+        z.o_idx = take(p.exact ? 4 : 2 * cap_rec * 4);
         z.o_sol = take(z.sol_cap * 16);
         z.o_scal = take(S_COUNT * 8);
-        z.scan_bytes = scan_tmp_bytes(std::max<uint64_t>(std::max<uint64_t>(T + 1, ncnt), kw * F + 1));
+        z.scan_bytes = scan_tmp_bytes(std::max<uint64_t>(std::max<uint64_t>(T + 1, ncnt),
+                                                         std::max<uint64_t>(kw * F + 1, nI + 1)));
         z.o_scan = take(z.scan_bytes);
         z.o_colw = take((uint64_t)n * 8);
         z.o_rows = take(P.rows.size() * 2);
@@ -374,6 +384,9 @@ void job_carve(Job &j) {
     }
     j.b.runs = (RunPair *)(ws + z.o_runs);
     j.b.tiles = (uint32_t *)(ws + z.o_tiles);
+    j.b.iruns = (RunPair *)(ws + z.o_iruns);
+    j.b.itiles = (uint32_t *)(ws + z.o_itiles);
+    j.b.idx = (uint32_t *)(ws + z.o_idx);
     j.b.sol = (uint64_t *)(ws + z.o_sol);
     j.b.scal = (uint64_t *)(ws + z.o_scal);
     j.b.scan_tmp = ws + z.o_scan;
@@ -446,6 +459,7 @@ int job_step(Job &j) {
             j.st.records_left += totL;
             j.st.records_right += totR;
             JCHK(hipMemsetAsync(&j.b.scal[S_NRUNS], 0, 8, j.s));
+            JCHK(hipMemsetAsync(&j.b.scal[S_NIRUNS], 0, 3 * 8, j.s));   // NIRUNS, TOT_ITILES, IDX
             JCHK(hipEventRecord(j.ev[E_S0], j.s));
             JCHK(launch_scatter(p, j.b, (int64_t)j.idx, (int32_t)j.K, j.s));
             JCHK(hipEventRecord(j.ev[E_S1], j.s));
@@ -460,27 +474,38 @@ int job_step(Job &j) {
         }
         case A_JOINED:
         case A_TILED: {
+            const uint32_t nruns = (uint32_t)j.hs[S_NRUNS];
+            const uint32_t niruns = (uint32_t)j.hs[S_NIRUNS];
             if (j.next == A_JOINED) {
                 j.st.ms_scatter += ev_ms(j.ev[E_S0], j.ev[E_S1]);
                 j.st.ms_join += ev_ms(j.ev[E_S1], j.ev[E_S2]);
-                const uint32_t nruns = (uint32_t)j.hs[S_NRUNS];
-                if (nruns) {
-                    JCHK(launch_tile_counts(p, j.b, nruns, !p.exact, j.s));
-                    JCHK(scan_u32(j.b.tiles, j.b.tiles, nruns, &j.b.scal[S_TOT_TILES], j.b.scan_tmp,
-                                  j.b.scan_tmp_bytes, j.s));
-                    JCHK(hipMemcpyAsync(&j.hs[S_TOT_TILES], &j.b.scal[S_TOT_TILES], 8,
-                                        hipMemcpyDeviceToHost, j.s));
+                if (niruns > z.n_iruns) return MSP_E_DEVICE;       // bound violated: cannot happen
+                if (nruns || niruns) {
+                    if (nruns) {
+                        JCHK(launch_tile_counts(p, j.b, nruns, p.exact ? 0 : 1, j.s));
+                        JCHK(scan_u32(j.b.tiles, j.b.tiles, nruns, &j.b.scal[S_TOT_TILES],
+                                      j.b.scan_tmp, j.b.scan_tmp_bytes, j.s));
+                    }
+                    if (niruns) {
+                        JCHK(launch_tile_counts(p, j.b, niruns, 2, j.s));
+                        JCHK(scan_u32(j.b.itiles, j.b.itiles, niruns, &j.b.scal[S_TOT_ITILES],
+                                      j.b.scan_tmp, j.b.scan_tmp_bytes, j.s));
+                    }
+                    JCHK(hipMemcpyAsync(j.hs, j.b.scal, S_COUNT * 8, hipMemcpyDeviceToHost, j.s));
                     j.next = A_TILED;
                     return MSP_OK;
                 }
             } else {
-                const uint32_t nruns = (uint32_t)j.hs[S_NRUNS];
-                const uint32_t ntiles = (uint32_t)j.hs[S_TOT_TILES];
                 JCHK(hipEventRecord(j.ev[E_V0], j.s));
-                JCHK(launch_verify(p, j.b, nruns, ntiles, z.sol_cap, !p.exact, j.s));
+                if (nruns)
+                    JCHK(launch_verify(p, j.b, nruns, (uint32_t)j.hs[S_TOT_TILES], z.sol_cap,
+                                       p.exact ? 0 : 1, j.s));
+                if (niruns)
+                    JCHK(launch_verify(p, j.b, niruns, (uint32_t)j.hs[S_TOT_ITILES], z.sol_cap, 2,
+                                       j.s));
                 JCHK(hipEventRecord(j.ev[E_V1], j.s));
                 j.verify_pending = true;
-                j.st.verify_launches++;
+                j.st.verify_launches += (nruns ? 1 : 0) + (niruns ? 1 : 0);
             }
             // Window done; move to the next one or finish.
             j.st.windows++;

@@ -13,6 +13,8 @@ constexpr int kJoinCap = 1536;      // left records per bucket held in LDS by th
 constexpr int kJoinSlots = 4096;    // LDS hash slots of the join (power of two)
 constexpr int kTileL = 4096;        // left records per verify tile
 constexpr int kThreads = 256;
+constexpr int kBigPairs = 4096;     // equal-key groups with this many pairs go to the tiled verify
+constexpr int kMaxBig = 64;         // such groups exported per bucket (the rest verified in place)
 
 // Everything the kernels need to know about one solve.
 struct Plan {
@@ -59,8 +61,11 @@ struct DevBufs {
     uint32_t *cnt[2];                // window counts per side (K*F*P + 1)
     uint32_t *off[2];                // scanned offsets per side
     void *rec[2];                    // window records per side
-    RunPair *runs;                   // run pairs for the tiled verify
+    RunPair *runs;                   // run pairs for the tiled verify (record ranges)
     uint32_t *tiles;                 // per run pair tile counts -> offsets (+1)
+    RunPair *iruns;                  // run pairs given as ranges of `idx`
+    uint32_t *itiles;                // tile offsets of iruns (+1)
+    uint32_t *idx;                   // record indices of large equal-key groups
     uint64_t *sol;                   // solutions: (maskL, maskR) pairs
     uint64_t *scal;                  // scalars (see Scal)
     void *scan_tmp;                  // scratch of the device-wide scan
@@ -71,7 +76,8 @@ struct DevBufs {
 
 // Slots of DevBufs::scal.
 enum Scal {
-    S_H_LO = 0, S_H_HI, S_NSOL, S_NRUNS, S_TOT_L, S_TOT_R, S_TOT_TILES, S_STORED, S_COUNT
+    S_H_LO = 0, S_H_HI, S_NSOL, S_NRUNS, S_TOT_L, S_TOT_R, S_TOT_TILES, S_STORED,
+    S_NIRUNS, S_TOT_ITILES, S_IDX, S_COUNT
 };
 
 // Launchers (kernels.hip).  All asynchronous on `st`.
@@ -81,9 +87,10 @@ hipError_t launch_scatter(const Plan &p, const DevBufs &b, int64_t idx0, int32_t
 hipError_t launch_exact_runs(const Plan &p, const DevBufs &b, int32_t K, hipStream_t st);
 hipError_t launch_hash_join(const Plan &p, const DevBufs &b, int32_t K, uint64_t sol_cap,
                             hipStream_t st);
+// mode 0: exact run pairs, 1: key-checked run pairs, 2: indexed run pairs.
 hipError_t launch_verify(const Plan &p, const DevBufs &b, uint32_t nruns, uint32_t ntiles,
-                         uint64_t sol_cap, int check_key, hipStream_t st);
-hipError_t launch_tile_counts(const Plan &p, const DevBufs &b, uint32_t nruns, int check_key,
+                         uint64_t sol_cap, int mode, hipStream_t st);
+hipError_t launch_tile_counts(const Plan &p, const DevBufs &b, uint32_t nruns, int mode,
                               hipStream_t st);
 // Exclusive scan of n uint32 values (out[n] = total; out may equal in);
 // the total is also stored to *total64 when non-null.

@@ -437,9 +437,9 @@ __global__ __launch_bounds__(256) void k_exact_runs(Plan p, const uint32_t *__re
 }
 
 __global__ void k_tile_counts(const RunPair *__restrict__ runs, const uint64_t *__restrict__ scal,
-                              uint32_t *tiles, uint32_t tile_r) {
+                              uint32_t *tiles, uint32_t tile_r, int count_slot) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t n = scal[S_NRUNS];
+    const uint64_t n = scal[count_slot];
     if (i >= n) return;
     const RunPair r = runs[i];
     tiles[i] = ((r.nl + kTileL - 1) / kTileL) * ((r.nr + tile_r - 1) / tile_r);
@@ -480,6 +480,7 @@ __global__ __launch_bounds__(256) void k_hash_join(Plan p, const uint32_t *__res
                                                    const uint32_t *__restrict__ offR,
                                                    const Rec<W> *__restrict__ L,
                                                    const Rec<W> *__restrict__ R, RunPair *runs,
+                                                   RunPair *iruns, uint32_t *idx,
                                                    uint64_t *scal, uint64_t *sol, uint64_t cap) {
     // s_tab[h] = (representative left index << 16) | count, then | group end.
     constexpr uint32_t kEmpty = 0xFFFF0000u;
@@ -488,8 +489,14 @@ __global__ __launch_bounds__(256) void k_hash_join(Plan p, const uint32_t *__res
     __shared__ int64_t s_key[kJoinCap];
     __shared__ uint32_t s_vec[WV][kJoinCap];             // left packed rows, by left index
     __shared__ uint32_t s_tab[kJoinSlots];
+    __shared__ uint32_t s_rcnt[kJoinSlots];              // right records per slot
+    __shared__ uint8_t s_bigidx[kJoinSlots];             // slot -> exported group, or 0xFF
     __shared__ uint16_t s_slot[kJoinCap];
+    __shared__ uint16_t s_lpos[kJoinCap];                // position of a left record in s_grp
     __shared__ uint16_t s_grp[kJoinCap];
+    __shared__ uint16_t s_rslot[kJoinCap];               // slot of a right record, 0xFFFF = none
+    __shared__ uint32_t s_bbase[kMaxBig], s_bgl[kMaxBig], s_bfill[kMaxBig];
+    __shared__ uint32_t s_nbig;
     __shared__ uint32_t s_w4[4];
     __shared__ uint64_t s_s4[4];
     const uint32_t b = blockIdx.x;
@@ -498,10 +505,10 @@ __global__ __launch_bounds__(256) void k_hash_join(Plan p, const uint32_t *__res
     const uint32_t r0 = offR[b * P], r1 = offR[(b + 1) * P];
     const uint32_t nl = l1 - l0, nr = r1 - r0;
     if (nl == 0 || nr == 0) return;                     // uniform across the block
-    if (nl > (uint32_t)kJoinCap) {
+    if (nl > (uint32_t)kJoinCap || nr > (uint32_t)kJoinCap) {
         if (threadIdx.x == 0) {
-            const uint64_t idx = atomicAdd((unsigned long long *)&scal[S_NRUNS], 1ull);
-            runs[idx] = RunPair{l0, nl, r0, nr};
+            const uint64_t i = atomicAdd((unsigned long long *)&scal[S_NRUNS], 1ull);
+            runs[i] = RunPair{l0, nl, r0, nr};
         }
         return;
     }
@@ -521,7 +528,12 @@ __global__ __launch_bounds__(256) void k_hash_join(Plan p, const uint32_t *__res
     uint32_t slots = 256;
     while (slots < 2 * nl) slots <<= 1;
     const uint32_t smask = slots - 1;
-    for (uint32_t i = t; i < slots; i += 256) s_tab[i] = kEmpty;
+    for (uint32_t i = t; i < slots; i += 256) {
+        s_tab[i] = kEmpty;
+        s_rcnt[i] = 0;
+        s_bigidx[i] = 0xFF;
+    }
+    if (t == 0) s_nbig = 0;
     {   // all left loads of this lane issued together, then staged into LDS
         constexpr int kLU = (kJoinCap + 255) / 256;
         int64_t lk[kLU];
@@ -590,26 +602,80 @@ __global__ __launch_bounds__(256) void k_hash_join(Plan p, const uint32_t *__res
     for (uint32_t i = t; i < nl; i += 256) {
         const uint32_t pos = atomicAdd(&s_tab[s_slot[i]], 1u) & 0xFFFFu;
         s_grp[pos] = (uint16_t)i;
+        s_lpos[i] = (uint16_t)pos;
     }
     __syncthreads();
-    uint64_t hits = 0;
-    auto probe = [&](const int64_t key, const uint32_t *v, uint32_t rj) {
-        // After the scan an empty slot keeps head 0xFFFF but its low half
-        // holds a running offset, so emptiness is read from the head half.
+    // Slot of a key, or 0xFFFF.  After the scan an empty slot keeps head
+    // 0xFFFF but its low half holds a running offset, so emptiness is read
+    // from the head half.
+    auto find = [&](const int64_t key) -> uint32_t {
         uint32_t h = key_hash(key) & smask;
         for (;;) {
             const uint32_t w = s_tab[h];
-            if ((w >> 16) == 0xFFFFu) return;
-            if (s_key[w >> 16] == key) break;
+            if ((w >> 16) == 0xFFFFu) return 0xFFFFu;
+            if (s_key[w >> 16] == key) return h;
             h = (h + 1) & smask;
         }
-        const uint32_t ge = s_tab[h] & 0xFFFFu, gs = h ? (s_tab[h - 1] & 0xFFFFu) : 0u;
-        hits += ge - gs;
+    };
+    auto gstart = [&](uint32_t h) { return h ? (s_tab[h - 1] & 0xFFFFu) : 0u; };
+    // Right records: slot of each, 1-D hits, right count per slot.
+    uint64_t hits = 0;
+    auto classify = [&](uint32_t j, int64_t key) {
+        const uint32_t h = find(key);
+        s_rslot[j] = (uint16_t)h;
+        if (h != 0xFFFFu) {
+            const uint32_t g = (s_tab[h] & 0xFFFFu) - gstart(h);
+            hits += g;
+            atomicAdd(&s_rcnt[h], 1u);
+            if (W == 0)
+                atomicAdd((unsigned long long *)&scal[S_NSOL], (unsigned long long)g);
+        }
+    };
+#pragma unroll
+    for (int e = 0; e < kPre; ++e) {
+        const uint32_t j = t + 256 * e;
+        if (j < nr) classify(j, rk[e]);
+    }
+    for (uint32_t j = t + 256 * kPre; j < nr; j += 256) classify(j, R[r0 + j].key);
+    __syncthreads();
+    // Large groups go to the tiled verify as index lists.
+    for (uint32_t h = t; h < slots; h += 256) {
+        const uint32_t gr = s_rcnt[h];
+        if (!gr) continue;
+        const uint32_t gl = (s_tab[h] & 0xFFFFu) - gstart(h);
+        if ((uint64_t)gl * gr < (uint64_t)kBigPairs) continue;
+        const uint32_t bi = atomicAdd(&s_nbig, 1u);
+        if (bi >= (uint32_t)kMaxBig) continue;
+        const uint32_t base = (uint32_t)atomicAdd((unsigned long long *)&scal[S_IDX],
+                                                  (unsigned long long)(gl + gr));
+        s_bbase[bi] = base;
+        s_bgl[bi] = gl;
+        s_bfill[bi] = 0;
+        s_bigidx[h] = (uint8_t)bi;
+        const uint64_t ri = atomicAdd((unsigned long long *)&scal[S_NIRUNS], 1ull);
+        iruns[ri] = RunPair{base, gl, base + gl, gr};
+    }
+    __syncthreads();
+    for (uint32_t i = t; i < nl; i += 256) {
+        const uint32_t h = s_slot[i], bi = s_bigidx[h];
+        if (bi != 0xFFu) idx[s_bbase[bi] + (s_lpos[i] - gstart(h))] = l0 + i;
+    }
+    for (uint32_t j = t; j < nr; j += 256) {
+        const uint32_t h = s_rslot[j];
+        if (h == 0xFFFFu || s_bigidx[h] == 0xFFu) continue;
+        const uint32_t bi = s_bigidx[h];
+        const uint32_t rp = atomicAdd(&s_bfill[bi], 1u);
+        idx[s_bbase[bi] + s_bgl[bi] + rp] = r0 + j;
+    }
+    // Small groups are verified here, one right record per lane.
+    auto verify_small = [&](uint32_t j, const uint32_t *v) {
+        const uint32_t h = s_rslot[j];
+        if (h == 0xFFFFu || s_bigidx[h] != 0xFFu) return;
+        const uint32_t ge = s_tab[h] & 0xFFFFu, gs = gstart(h);
         if (W == 0) {
-            atomicAdd((unsigned long long *)&scal[S_NSOL], (unsigned long long)(ge - gs));
             for (uint32_t q = gs; q < ge; ++q) {
                 if (scal[S_STORED] >= cap) break;
-                emit_solution(sol, cap, &scal[S_STORED], L[l0 + s_grp[q]].mask, R[r0 + rj].mask);
+                emit_solution(sol, cap, &scal[S_STORED], L[l0 + s_grp[q]].mask, R[r0 + j].mask);
             }
         } else {
             for (uint32_t q = gs; q < ge; ++q) {
@@ -617,20 +683,20 @@ __global__ __launch_bounds__(256) void k_hash_join(Plan p, const uint32_t *__res
                 bool ok = true;
 #pragma unroll
                 for (int w = 0; w < WV; ++w) ok = ok && (s_vec[w][li] == v[w]);
-                if (ok) emit_solution(sol, cap, &scal[S_NSOL], L[l0 + li].mask, R[r0 + rj].mask);
+                if (ok) emit_solution(sol, cap, &scal[S_NSOL], L[l0 + li].mask, R[r0 + j].mask);
             }
         }
     };
 #pragma unroll
     for (int e = 0; e < kPre; ++e) {
         const uint32_t j = t + 256 * e;
-        if (j < nr) probe(rk[e], rv[e], j);
+        if (j < nr) verify_small(j, rv[e]);
     }
     for (uint32_t j = t + 256 * kPre; j < nr; j += 256) {
         uint32_t v[WV];
 #pragma unroll
         for (int w = 0; w < WV; ++w) v[w] = R[r0 + j].vec[w];
-        probe(R[r0 + j].key, v, j);
+        verify_small(j, v);
     }
     const uint64_t tot = block_sum_u64(hits, s_s4);
     if (t == 0) add_u128(&scal[S_H_LO], &scal[S_H_HI], tot);
@@ -688,13 +754,16 @@ __device__ __forceinline__ uint64_t match4x8(const uint32_t *rf, uint4 q) {
 #undef MSP_CMPX8
 #undef MSP_CMPX
 
-template <int W, bool CK, int kKR, bool CMPX = false>
+template <int W, bool CK, int kKR, bool CMPX = false, bool IDX = false>
 __global__ __launch_bounds__(256) void k_verify(Plan p, const Rec<W> *__restrict__ L,
                                                 const Rec<W> *__restrict__ R,
                                                 const RunPair *__restrict__ runs,
                                                 const uint32_t *__restrict__ toff,
                                                 uint32_t nruns, uint64_t *scal, uint64_t *sol,
-                                                uint64_t cap) {
+                                                uint64_t cap, const uint32_t *__restrict__ idx) {
+    // IDX: run ranges index `idx`, which holds the record positions.
+    auto lrec = [&](uint32_t i) -> const Rec<W> & { return IDX ? L[idx[i]] : L[i]; };
+    auto rrec = [&](uint32_t i) -> const Rec<W> & { return IDX ? R[idx[i]] : R[i]; };
     __shared__ __attribute__((aligned(16))) uint32_t s_fp[kChunk];
     __shared__ int64_t s_lk[CK ? kChunk : 1];
     __shared__ uint64_t s_s4[4];
@@ -723,7 +792,7 @@ __global__ __launch_bounds__(256) void k_verify(Plan p, const Rec<W> *__restrict
             for (int k = 0; k < kKR; ++k) {
                 const uint32_t ri = rb + k * 256 + t;
                 if (ri < re && scal[S_STORED] < cap)
-                    emit_solution(sol, cap, &scal[S_STORED], L[li].mask, R[ri].mask);
+                    emit_solution(sol, cap, &scal[S_STORED], lrec(li).mask, rrec(ri).mask);
             }
         }
         return;
@@ -737,16 +806,16 @@ __global__ __launch_bounds__(256) void k_verify(Plan p, const Rec<W> *__restrict
         rf[k] = 0u;
         if (CK) rk[k] = -1;                       // never equals a left key (>= 0)
         if (ri < re) {
-            if (W > 0) rf[k] = fingerprint<W>(R[ri].vec);
-            if (CK) rk[k] = R[ri].key;
+            if (W > 0) rf[k] = fingerprint<W>(rrec(ri).vec);
+            if (CK) rk[k] = rrec(ri).key;
         }
     }
     // Full check of a flagged (left j, right slot k) pair.
     auto check = [&](uint32_t li, int k) {
         const uint32_t ri = rb + k * 256 + t;
         if (ri >= re) return;
-        const Rec<W> ll = L[li];
-        const Rec<W> rr = R[ri];
+        const Rec<W> ll = lrec(li);
+        const Rec<W> rr = rrec(ri);
         if (rows_match<W>(ll, rr)) emit_solution(sol, cap, &scal[S_NSOL], ll.mask, rr.mask);
     };
     uint64_t hits = 0;
@@ -754,8 +823,8 @@ __global__ __launch_bounds__(256) void k_verify(Plan p, const Rec<W> *__restrict
         const uint32_t cn = min((uint32_t)kChunk, le - c0);
         __syncthreads();
         for (uint32_t i = t; i < cn; i += 256) {
-            s_fp[i] = W > 0 ? fingerprint<W>(L[c0 + i].vec) : 0u;
-            if (CK) s_lk[i] = L[c0 + i].key;
+            s_fp[i] = W > 0 ? fingerprint<W>(lrec(c0 + i).vec) : 0u;
+            if (CK) s_lk[i] = lrec(c0 + i).key;
         }
         __syncthreads();
         if (!CK) {
@@ -802,8 +871,8 @@ __global__ __launch_bounds__(256) void k_verify(Plan p, const Rec<W> *__restrict
                         if (W == 0) {
                             atomicAdd((unsigned long long *)&scal[S_NSOL], 1ull);
                             if (scal[S_STORED] < cap)
-                                emit_solution(sol, cap, &scal[S_STORED], L[c0 + jj].mask,
-                                              R[rb + k * 256 + t].mask);
+                                emit_solution(sol, cap, &scal[S_STORED], lrec(c0 + jj).mask,
+                                              rrec(rb + k * 256 + t).mask);
                         } else if (rf[k] == x) {
                             check(c0 + jj, k);
                         }
@@ -1029,8 +1098,8 @@ static hipError_t join_impl(const Plan &p, const DevBufs &b, int32_t K, uint64_t
                             hipStream_t st) {
     const uint32_t nb = (uint32_t)K << p.log2F;
     hipLaunchKernelGGL(k_hash_join<W>, dim3(nb), dim3(256), 0, st, p, b.off[0], b.off[1],
-                       (const Rec<W> *)b.rec[0], (const Rec<W> *)b.rec[1], b.runs, b.scal,
-                       b.sol, cap);
+                       (const Rec<W> *)b.rec[0], (const Rec<W> *)b.rec[1], b.runs, b.iruns,
+                       b.idx, b.scal, b.sol, cap);
     return hipGetLastError();
 }
 
@@ -1060,41 +1129,45 @@ bool verify_cmpx() {
     return on;
 }
 
-hipError_t launch_tile_counts(const Plan &, const DevBufs &b, uint32_t nruns, int ck,
+hipError_t launch_tile_counts(const Plan &, const DevBufs &b, uint32_t nruns, int mode,
                               hipStream_t st) {
     if (nruns == 0) return hipSuccess;
-    const uint32_t tile_r = 256u * ((ck || verify_cmpx()) ? 8 : verify_kr());
-    hipLaunchKernelGGL(k_tile_counts, dim3((nruns + 255) / 256), dim3(256), 0, st, b.runs, b.scal,
-                       b.tiles, tile_r);
+    const uint32_t tile_r = 256u * ((mode != 0 || verify_cmpx()) ? 8 : verify_kr());
+    if (mode == 2)
+        hipLaunchKernelGGL(k_tile_counts, dim3((nruns + 255) / 256), dim3(256), 0, st, b.iruns,
+                           b.scal, b.itiles, tile_r, (int)S_NIRUNS);
+    else
+        hipLaunchKernelGGL(k_tile_counts, dim3((nruns + 255) / 256), dim3(256), 0, st, b.runs,
+                           b.scal, b.tiles, tile_r, (int)S_NRUNS);
     return hipGetLastError();
 }
 
 template <int W>
 static hipError_t verify_impl(const Plan &p, const DevBufs &b, uint32_t nruns, uint32_t ntiles,
-                              uint64_t cap, int ck, hipStream_t st) {
-    if (ck)
-        hipLaunchKernelGGL((k_verify<W, true, 8>), dim3(ntiles), dim3(256), 0, st, p,
-                           (const Rec<W> *)b.rec[0], (const Rec<W> *)b.rec[1], b.runs, b.tiles,
-                           nruns, b.scal, b.sol, cap);
+                              uint64_t cap, int mode, hipStream_t st) {
+    const Rec<W> *L = (const Rec<W> *)b.rec[0], *R = (const Rec<W> *)b.rec[1];
+    if (mode == 2)
+        hipLaunchKernelGGL((k_verify<W, false, 8, true, true>), dim3(ntiles), dim3(256), 0, st, p,
+                           L, R, b.iruns, b.itiles, nruns, b.scal, b.sol, cap, b.idx);
+    else if (mode == 1)
+        hipLaunchKernelGGL((k_verify<W, true, 8>), dim3(ntiles), dim3(256), 0, st, p, L, R,
+                           b.runs, b.tiles, nruns, b.scal, b.sol, cap, b.idx);
     else if (verify_cmpx())
-        hipLaunchKernelGGL((k_verify<W, false, 8, true>), dim3(ntiles), dim3(256), 0, st, p,
-                           (const Rec<W> *)b.rec[0], (const Rec<W> *)b.rec[1], b.runs, b.tiles,
-                           nruns, b.scal, b.sol, cap);
+        hipLaunchKernelGGL((k_verify<W, false, 8, true>), dim3(ntiles), dim3(256), 0, st, p, L, R,
+                           b.runs, b.tiles, nruns, b.scal, b.sol, cap, b.idx);
     else if (verify_kr() == 16)
-        hipLaunchKernelGGL((k_verify<W, false, 16>), dim3(ntiles), dim3(256), 0, st, p,
-                           (const Rec<W> *)b.rec[0], (const Rec<W> *)b.rec[1], b.runs, b.tiles,
-                           nruns, b.scal, b.sol, cap);
+        hipLaunchKernelGGL((k_verify<W, false, 16>), dim3(ntiles), dim3(256), 0, st, p, L, R,
+                           b.runs, b.tiles, nruns, b.scal, b.sol, cap, b.idx);
     else
-        hipLaunchKernelGGL((k_verify<W, false, 8>), dim3(ntiles), dim3(256), 0, st, p,
-                           (const Rec<W> *)b.rec[0], (const Rec<W> *)b.rec[1], b.runs, b.tiles,
-                           nruns, b.scal, b.sol, cap);
+        hipLaunchKernelGGL((k_verify<W, false, 8>), dim3(ntiles), dim3(256), 0, st, p, L, R,
+                           b.runs, b.tiles, nruns, b.scal, b.sol, cap, b.idx);
     return hipGetLastError();
 }
 
 hipError_t launch_verify(const Plan &p, const DevBufs &b, uint32_t nruns, uint32_t ntiles,
-                         uint64_t cap, int check_key, hipStream_t st) {
+                         uint64_t cap, int mode, hipStream_t st) {
     if (ntiles == 0) return hipSuccess;
-    MSP_DISPATCH_W(p.W, return verify_impl<WW>(p, b, nruns, ntiles, cap, check_key, st));
+    MSP_DISPATCH_W(p.W, return verify_impl<WW>(p, b, nruns, ntiles, cap, mode, st));
     return hipSuccess;
 }
 

@@ -44,6 +44,7 @@ SMALL = [
     dict(m=4, n=21, K=100, zero=0, r=2),
     dict(m=4, n=22, K=6, zero=0, r=1),      # heavy key ties
     dict(m=4, n=22, K=6, zero=0, r=3),
+    dict(m=4, n=24, K=4, zero=0, r=2),      # large equal-key groups (tiled verify by index)
     dict(m=3, n=19, K=100, zero=3, r=1),    # zero columns
     dict(m=5, n=17, K=3, zero=2, r=2),
     dict(m=2, n=5, K=4, zero=0, r=1),
