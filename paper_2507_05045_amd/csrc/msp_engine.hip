@@ -52,7 +52,7 @@ struct Sizes {
     // offsets into the workspace
     uint64_t o_qraw[4], o_qsrt[4], o_qcnt[4], o_qcur[4], o_cnt[2], o_off[2], o_rec[2];
     uint64_t o_runs, o_tiles, o_sol, o_scal, o_scan, scan_bytes, o_colw, o_rows;
-    uint64_t o_iruns, o_itiles, o_idx, n_iruns;
+    uint64_t o_iruns, o_itiles, o_idx, n_iruns, o_heavy, idx_n;
 };
 
 struct Prepared {
@@ -221,14 +221,20 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
         for (int s = 0; s < 2; ++s) z.o_rec[s] = take(cap_rec * rb);
         z.o_runs = take(kw * F * sizeof(RunPair));
         z.o_tiles = take((kw * F + 1) * 4);
-        // Large equal-key groups exported by the hash join: each has at
-        // least kBigPairs pairs, hence at least 2*sqrt(kBigPairs) = 128
-        // records, so there are at most 2*cap_rec/128 of them.
-        const uint64_t nI = p.exact ? 1 : cap_rec / 64 + 1024;
+        // Large equal-key groups exported by the hash join as index lists.
+        // A left chunk exports each record at most once and each right
+        // record once per left chunk; sized for three records' worth per
+        // record (buckets of up to two left chunks).  The join checks both
+        // capacities on the device and verifies in place what does not fit.
+        // Each group has >= kBigPairs pairs, hence >= 128 records.
+        const uint64_t idx_n = p.exact ? 1 : 3 * cap_rec;
+        const uint64_t nI = p.exact ? 1 : idx_n / 128 + 1024;
         z.n_iruns = nI;
+        z.idx_n = idx_n;
         z.o_iruns = take(nI * sizeof(RunPair));
         z.o_itiles = take((nI + 1) * 4);
-        z.o_idx = take(p.exact ? 4 : 2 * cap_rec * 4);
+        z.o_idx = take(idx_n * 4);
+        z.o_heavy = take(p.exact ? 4 : kw * F * 4);
         z.o_sol = take(z.sol_cap * 16);
         z.o_scal = take(S_COUNT * 8);
         z.scan_bytes = scan_tmp_bytes(std::max<uint64_t>(std::max<uint64_t>(T + 1, ncnt),
@@ -387,6 +393,9 @@ void job_carve(Job &j) {
     j.b.iruns = (RunPair *)(ws + z.o_iruns);
     j.b.itiles = (uint32_t *)(ws + z.o_itiles);
     j.b.idx = (uint32_t *)(ws + z.o_idx);
+    j.b.heavy = (uint32_t *)(ws + z.o_heavy);
+    j.b.iruns_cap = z.n_iruns;
+    j.b.idx_cap = z.idx_n;
     j.b.sol = (uint64_t *)(ws + z.o_sol);
     j.b.scal = (uint64_t *)(ws + z.o_scal);
     j.b.scan_tmp = ws + z.o_scan;
@@ -459,7 +468,7 @@ int job_step(Job &j) {
             j.st.records_left += totL;
             j.st.records_right += totR;
             JCHK(hipMemsetAsync(&j.b.scal[S_NRUNS], 0, 8, j.s));
-            JCHK(hipMemsetAsync(&j.b.scal[S_NIRUNS], 0, 3 * 8, j.s));   // NIRUNS, TOT_ITILES, IDX
+            JCHK(hipMemsetAsync(&j.b.scal[S_NIRUNS], 0, 4 * 8, j.s));   // NIRUNS, TOT_ITILES, IDX, NHEAVY
             JCHK(hipEventRecord(j.ev[E_S0], j.s));
             JCHK(launch_scatter(p, j.b, (int64_t)j.idx, (int32_t)j.K, j.s));
             JCHK(hipEventRecord(j.ev[E_S1], j.s));
@@ -475,11 +484,11 @@ int job_step(Job &j) {
         case A_JOINED:
         case A_TILED: {
             const uint32_t nruns = (uint32_t)j.hs[S_NRUNS];
-            const uint32_t niruns = (uint32_t)j.hs[S_NIRUNS];
+            // Reservations past the capacity were not written (see k_join_heavy).
+            const uint32_t niruns = (uint32_t)std::min<uint64_t>(j.hs[S_NIRUNS], z.n_iruns);
             if (j.next == A_JOINED) {
                 j.st.ms_scatter += ev_ms(j.ev[E_S0], j.ev[E_S1]);
                 j.st.ms_join += ev_ms(j.ev[E_S1], j.ev[E_S2]);
-                if (niruns > z.n_iruns) return MSP_E_DEVICE;       // bound violated: cannot happen
                 if (nruns || niruns) {
                     if (nruns) {
                         JCHK(launch_tile_counts(p, j.b, nruns, p.exact ? 0 : 1, j.s));

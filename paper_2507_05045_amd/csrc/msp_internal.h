@@ -14,7 +14,8 @@ constexpr int kJoinSlots = 4096;    // LDS hash slots of the join (power of two)
 constexpr int kTileL = 4096;        // left records per verify tile
 constexpr int kThreads = 256;
 constexpr int kBigPairs = 4096;     // equal-key groups with this many pairs go to the tiled verify
-constexpr int kMaxBig = 64;         // such groups exported per bucket (the rest verified in place)
+constexpr int kMaxBig = 64;         // such groups exported per chunk pair (the rest verified in place)
+constexpr int kLightGroup = 64;     // largest left group the light join verifies per lane
 
 // Everything the kernels need to know about one solve.
 struct Plan {
@@ -66,6 +67,8 @@ struct DevBufs {
     RunPair *iruns;                  // run pairs given as ranges of `idx`
     uint32_t *itiles;                // tile offsets of iruns (+1)
     uint32_t *idx;                   // record indices of large equal-key groups
+    uint32_t *heavy;                 // buckets deferred to the heavy join
+    uint64_t iruns_cap, idx_cap;     // capacities of iruns and idx
     uint64_t *sol;                   // solutions: (maskL, maskR) pairs
     uint64_t *scal;                  // scalars (see Scal)
     void *scan_tmp;                  // scratch of the device-wide scan
@@ -77,7 +80,7 @@ struct DevBufs {
 // Slots of DevBufs::scal.
 enum Scal {
     S_H_LO = 0, S_H_HI, S_NSOL, S_NRUNS, S_TOT_L, S_TOT_R, S_TOT_TILES, S_STORED,
-    S_NIRUNS, S_TOT_ITILES, S_IDX, S_COUNT
+    S_NIRUNS, S_TOT_ITILES, S_IDX, S_NHEAVY, S_COUNT
 };
 
 // Launchers (kernels.hip).  All asynchronous on `st`.

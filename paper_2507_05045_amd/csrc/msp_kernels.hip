@@ -436,10 +436,9 @@ __global__ __launch_bounds__(256) void k_exact_runs(Plan p, const uint32_t *__re
     }
 }
 
-__global__ void k_tile_counts(const RunPair *__restrict__ runs, const uint64_t *__restrict__ scal,
-                              uint32_t *tiles, uint32_t tile_r, int count_slot) {
+__global__ void k_tile_counts(const RunPair *__restrict__ runs, uint32_t n, uint32_t *tiles,
+                              uint32_t tile_r) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t n = scal[count_slot];
     if (i >= n) return;
     const RunPair r = runs[i];
     tiles[i] = ((r.nl + kTileL - 1) / kTileL) * ((r.nr + tile_r - 1) / tile_r);
@@ -476,11 +475,10 @@ __device__ __forceinline__ uint32_t key_hash(int64_t k) {
 }
 
 template <int W>
-__global__ __launch_bounds__(256) void k_hash_join(Plan p, const uint32_t *__restrict__ offL,
+__global__ __launch_bounds__(256) void k_join_light(Plan p, const uint32_t *__restrict__ offL,
                                                    const uint32_t *__restrict__ offR,
                                                    const Rec<W> *__restrict__ L,
-                                                   const Rec<W> *__restrict__ R, RunPair *runs,
-                                                   RunPair *iruns, uint32_t *idx,
+                                                   const Rec<W> *__restrict__ R, uint32_t *heavy,
                                                    uint64_t *scal, uint64_t *sol, uint64_t cap) {
     // s_tab[h] = (representative left index << 16) | count, then | group end.
     constexpr uint32_t kEmpty = 0xFFFF0000u;
@@ -489,27 +487,20 @@ __global__ __launch_bounds__(256) void k_hash_join(Plan p, const uint32_t *__res
     __shared__ int64_t s_key[kJoinCap];
     __shared__ uint32_t s_vec[WV][kJoinCap];             // left packed rows, by left index
     __shared__ uint32_t s_tab[kJoinSlots];
-    __shared__ uint32_t s_rcnt[kJoinSlots];              // right records per slot
-    __shared__ uint8_t s_bigidx[kJoinSlots];             // slot -> exported group, or 0xFF
     __shared__ uint16_t s_slot[kJoinCap];
-    __shared__ uint16_t s_lpos[kJoinCap];                // position of a left record in s_grp
     __shared__ uint16_t s_grp[kJoinCap];
-    __shared__ uint16_t s_rslot[kJoinCap];               // slot of a right record, 0xFFFF = none
-    __shared__ uint32_t s_bbase[kMaxBig], s_bgl[kMaxBig], s_bfill[kMaxBig];
-    __shared__ uint32_t s_nbig;
     __shared__ uint32_t s_w4[4];
     __shared__ uint64_t s_s4[4];
+    __shared__ uint32_t s_gmax;
     const uint32_t b = blockIdx.x;
     const uint64_t P = p.parts;
     const uint32_t l0 = offL[b * P], l1 = offL[(b + 1) * P];
     const uint32_t r0 = offR[b * P], r1 = offR[(b + 1) * P];
     const uint32_t nl = l1 - l0, nr = r1 - r0;
     if (nl == 0 || nr == 0) return;                     // uniform across the block
-    if (nl > (uint32_t)kJoinCap || nr > (uint32_t)kJoinCap) {
-        if (threadIdx.x == 0) {
-            const uint64_t i = atomicAdd((unsigned long long *)&scal[S_NRUNS], 1ull);
-            runs[i] = RunPair{l0, nl, r0, nr};
-        }
+    if (nl > (uint32_t)kJoinCap) {                      // too big for LDS: heavy kernel
+        if (threadIdx.x == 0)
+            heavy[atomicAdd((unsigned long long *)&scal[S_NHEAVY], 1ull)] = b;
         return;
     }
     const int t = threadIdx.x;
@@ -528,12 +519,175 @@ __global__ __launch_bounds__(256) void k_hash_join(Plan p, const uint32_t *__res
     uint32_t slots = 256;
     while (slots < 2 * nl) slots <<= 1;
     const uint32_t smask = slots - 1;
+    for (uint32_t i = t; i < slots; i += 256) s_tab[i] = kEmpty;
+    if (t == 0) s_gmax = 0;
+    {   // all left loads of this lane issued together, then staged into LDS
+        constexpr int kLU = (kJoinCap + 255) / 256;
+        int64_t lk[kLU];
+        uint32_t lv[kLU][WV];
+#pragma unroll
+        for (int u = 0; u < kLU; ++u) {
+            const uint32_t i = t + 256 * u;
+            if (i < nl) {
+                lk[u] = L[l0 + i].key;
+#pragma unroll
+                for (int w = 0; w < WV; ++w) lv[u][w] = L[l0 + i].vec[w];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kLU; ++u) {
+            const uint32_t i = t + 256 * u;
+            if (i < nl) {
+                s_key[i] = lk[u];
+#pragma unroll
+                for (int w = 0; w < WV; ++w) s_vec[w][i] = lv[u][w];
+            }
+        }
+    }
+    __syncthreads();
+    // Build: one representative per distinct key, count per slot.
+    for (uint32_t i = t; i < nl; i += 256) {
+        const int64_t k = s_key[i];
+        uint32_t h = key_hash(k) & smask;
+        for (;;) {
+            uint32_t w = s_tab[h];
+            if (w == kEmpty) {
+                const uint32_t old = atomicCAS(&s_tab[h], kEmpty, i << 16);
+                if (old == kEmpty) break;
+                w = old;
+            }
+            if (s_key[w >> 16] == k) break;
+            h = (h + 1) & smask;
+        }
+        s_slot[i] = (uint16_t)h;
+        atomicAdd(&s_tab[h], 1u);
+    }
+    __syncthreads();
+    {   // exclusive scan of the counts (low halves), heads kept
+        const int E = (int)(slots >> 8), lane = t & 63, wave = t >> 6;
+        uint32_t loc[16], sum = 0, gm = 0;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            loc[e] = e < E ? (s_tab[t * E + e] & 0xFFFFu) : 0u;
+            sum += loc[e];
+            gm = max(gm, loc[e]);
+        }
+        atomicMax(&s_gmax, gm);
+        const uint32_t inc = wave_incl_scan(sum);
+        if (lane == 63) s_w4[wave] = inc;
+        __syncthreads();
+        uint32_t run = inc - sum;
+        for (int w = 0; w < wave; ++w) run += s_w4[w];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            if (e < E) {
+                s_tab[t * E + e] = (s_tab[t * E + e] & 0xFFFF0000u) | run;
+                run += loc[e];
+            }
+        }
+        __syncthreads();
+    }
+    // A left group larger than kLightGroup makes per-lane loops slow: the
+    // whole bucket goes to the heavy kernel (tiled verify of big groups).
+    if (s_gmax > (uint32_t)kLightGroup) {
+        if (t == 0) heavy[atomicAdd((unsigned long long *)&scal[S_NHEAVY], 1ull)] = b;
+        return;
+    }
+    // Group left records by slot; afterwards the low half is the group end.
+    for (uint32_t i = t; i < nl; i += 256) {
+        const uint32_t pos = atomicAdd(&s_tab[s_slot[i]], 1u) & 0xFFFFu;
+        s_grp[pos] = (uint16_t)i;
+    }
+    __syncthreads();
+    uint64_t hits = 0;
+    auto probe = [&](const int64_t key, const uint32_t *v, uint32_t rj) {
+        // After the scan an empty slot keeps head 0xFFFF but its low half
+        // holds a running offset, so emptiness is read from the head half.
+        uint32_t h = key_hash(key) & smask;
+        for (;;) {
+            const uint32_t w = s_tab[h];
+            if ((w >> 16) == 0xFFFFu) return;
+            if (s_key[w >> 16] == key) break;
+            h = (h + 1) & smask;
+        }
+        const uint32_t ge = s_tab[h] & 0xFFFFu, gs = h ? (s_tab[h - 1] & 0xFFFFu) : 0u;
+        hits += ge - gs;
+        if (W == 0) {
+            atomicAdd((unsigned long long *)&scal[S_NSOL], (unsigned long long)(ge - gs));
+            for (uint32_t q = gs; q < ge; ++q) {
+                if (scal[S_STORED] >= cap) break;
+                emit_solution(sol, cap, &scal[S_STORED], L[l0 + s_grp[q]].mask, R[r0 + rj].mask);
+            }
+        } else {
+            for (uint32_t q = gs; q < ge; ++q) {
+                const uint32_t li = s_grp[q];
+                bool ok = true;
+#pragma unroll
+                for (int w = 0; w < WV; ++w) ok = ok && (s_vec[w][li] == v[w]);
+                if (ok) emit_solution(sol, cap, &scal[S_NSOL], L[l0 + li].mask, R[r0 + rj].mask);
+            }
+        }
+    };
+#pragma unroll
+    for (int e = 0; e < kPre; ++e) {
+        const uint32_t j = t + 256 * e;
+        if (j < nr) probe(rk[e], rv[e], j);
+    }
+    for (uint32_t j = t + 256 * kPre; j < nr; j += 256) {
+        uint32_t v[WV];
+#pragma unroll
+        for (int w = 0; w < WV; ++w) v[w] = R[r0 + j].vec[w];
+        probe(R[r0 + j].key, v, j);
+    }
+    const uint64_t tot = block_sum_u64(hits, s_s4);
+    if (t == 0) add_u128(&scal[S_H_LO], &scal[S_H_HI], tot);
+}
+
+template <int W>
+__global__ __launch_bounds__(256) void k_join_heavy(Plan p, const uint32_t *__restrict__ offL,
+                                                   const uint32_t *__restrict__ offR,
+                                                   const Rec<W> *__restrict__ L,
+                                                   const Rec<W> *__restrict__ R,
+                                                   const uint32_t *__restrict__ heavy,
+                                                   RunPair *iruns, uint32_t *idx,
+                                                   uint64_t *scal, uint64_t *sol, uint64_t cap,
+                                                   uint64_t iruns_cap, uint64_t idx_cap) {
+    // s_tab[h] = (representative left index << 16) | count, then | group end.
+    constexpr uint32_t kEmpty = 0xFFFF0000u;
+    constexpr int WV = W > 0 ? W : 1;
+    __shared__ int64_t s_key[kJoinCap];
+    __shared__ uint32_t s_vec[WV][kJoinCap];             // left packed rows, by left index
+    __shared__ uint32_t s_tab[kJoinSlots];
+    __shared__ uint32_t s_rcnt[kJoinSlots];              // right records per slot
+    __shared__ uint8_t s_bigidx[kJoinSlots];             // slot -> exported group, or 0xFF
+    __shared__ uint16_t s_slot[kJoinCap];
+    __shared__ uint16_t s_lpos[kJoinCap];                // position of a left record in s_grp
+    __shared__ uint16_t s_grp[kJoinCap];
+    __shared__ uint32_t s_bbase[kMaxBig], s_bgl[kMaxBig], s_bfill[kMaxBig];
+    __shared__ uint32_t s_nbig;
+    __shared__ uint32_t s_w4[4];
+    __shared__ uint64_t s_s4[4];
+    const int t = threadIdx.x;
+    const uint32_t nheavy = (uint32_t)scal[S_NHEAVY];
+    uint64_t hits = 0;
+    for (uint32_t hb = blockIdx.x; hb < nheavy; hb += gridDim.x) {
+    const uint32_t b = heavy[hb];
+    const uint64_t P = p.parts;
+    const uint32_t L0 = offL[b * P], L1 = offL[(b + 1) * P];
+    const uint32_t R0 = offR[b * P], R1 = offR[(b + 1) * P];
+    // Left chunks of at most kJoinCap records, each against the whole right
+    // side: every (left, right) pair of the bucket is met exactly once.
+    for (uint32_t lc0 = L0; lc0 < L1; lc0 += kJoinCap) {
+    const uint32_t l0 = lc0, nl = min((uint32_t)kJoinCap, L1 - lc0);
+    __syncthreads();                                    // previous chunk done with LDS
+    uint32_t slots = 256;
+    while (slots < 2 * nl) slots <<= 1;
+    const uint32_t smask = slots - 1;
     for (uint32_t i = t; i < slots; i += 256) {
         s_tab[i] = kEmpty;
         s_rcnt[i] = 0;
         s_bigidx[i] = 0xFF;
     }
-    if (t == 0) s_nbig = 0;
     {   // all left loads of this lane issued together, then staged into LDS
         constexpr int kLU = (kJoinCap + 255) / 256;
         int64_t lk[kLU];
@@ -618,11 +772,20 @@ __global__ __launch_bounds__(256) void k_hash_join(Plan p, const uint32_t *__res
         }
     };
     auto gstart = [&](uint32_t h) { return h ? (s_tab[h - 1] & 0xFFFFu) : 0u; };
-    // Right records: slot of each, 1-D hits, right count per slot.
-    uint64_t hits = 0;
-    auto classify = [&](uint32_t j, int64_t key) {
-        const uint32_t h = find(key);
-        s_rslot[j] = (uint16_t)h;
+    // All right records of the bucket against this left chunk.  Pass 1
+    // counts 1-D hits and right records per slot; large groups are then
+    // exported as index lists (when the lists have room, else verified here);
+    // pass 2 probes again, writes right indices of exported groups and
+    // verifies the small groups in place.
+    const uint32_t r0 = R0, nr = R1 - R0;
+    for (uint32_t i = t; i < slots; i += 256) {
+        s_rcnt[i] = 0;
+        s_bigidx[i] = 0xFF;
+    }
+    if (t == 0) s_nbig = 0;
+    __syncthreads();
+    for (uint32_t j = t; j < nr; j += 256) {
+        const uint32_t h = find(R[r0 + j].key);
         if (h != 0xFFFFu) {
             const uint32_t g = (s_tab[h] & 0xFFFFu) - gstart(h);
             hits += g;
@@ -630,15 +793,8 @@ __global__ __launch_bounds__(256) void k_hash_join(Plan p, const uint32_t *__res
             if (W == 0)
                 atomicAdd((unsigned long long *)&scal[S_NSOL], (unsigned long long)g);
         }
-    };
-#pragma unroll
-    for (int e = 0; e < kPre; ++e) {
-        const uint32_t j = t + 256 * e;
-        if (j < nr) classify(j, rk[e]);
     }
-    for (uint32_t j = t + 256 * kPre; j < nr; j += 256) classify(j, R[r0 + j].key);
     __syncthreads();
-    // Large groups go to the tiled verify as index lists.
     for (uint32_t h = t; h < slots; h += 256) {
         const uint32_t gr = s_rcnt[h];
         if (!gr) continue;
@@ -646,14 +802,19 @@ __global__ __launch_bounds__(256) void k_hash_join(Plan p, const uint32_t *__res
         if ((uint64_t)gl * gr < (uint64_t)kBigPairs) continue;
         const uint32_t bi = atomicAdd(&s_nbig, 1u);
         if (bi >= (uint32_t)kMaxBig) continue;
-        const uint32_t base = (uint32_t)atomicAdd((unsigned long long *)&scal[S_IDX],
-                                                  (unsigned long long)(gl + gr));
-        s_bbase[bi] = base;
+        const uint64_t ri = atomicAdd((unsigned long long *)&scal[S_NIRUNS], 1ull);
+        if (ri >= iruns_cap) continue;                  // no room: verified in place
+        const uint64_t base = atomicAdd((unsigned long long *)&scal[S_IDX],
+                                        (unsigned long long)(gl + gr));
+        if (base + gl + gr > idx_cap) {                 // no room: empty run, verified in place
+            iruns[ri] = RunPair{0, 0, 0, 0};
+            continue;
+        }
+        s_bbase[bi] = (uint32_t)base;
         s_bgl[bi] = gl;
         s_bfill[bi] = 0;
         s_bigidx[h] = (uint8_t)bi;
-        const uint64_t ri = atomicAdd((unsigned long long *)&scal[S_NIRUNS], 1ull);
-        iruns[ri] = RunPair{base, gl, base + gl, gr};
+        iruns[ri] = RunPair{(uint32_t)base, gl, (uint32_t)base + gl, gr};
     }
     __syncthreads();
     for (uint32_t i = t; i < nl; i += 256) {
@@ -661,16 +822,14 @@ __global__ __launch_bounds__(256) void k_hash_join(Plan p, const uint32_t *__res
         if (bi != 0xFFu) idx[s_bbase[bi] + (s_lpos[i] - gstart(h))] = l0 + i;
     }
     for (uint32_t j = t; j < nr; j += 256) {
-        const uint32_t h = s_rslot[j];
-        if (h == 0xFFFFu || s_bigidx[h] == 0xFFu) continue;
+        const uint32_t h = find(R[r0 + j].key);
+        if (h == 0xFFFFu) continue;
         const uint32_t bi = s_bigidx[h];
-        const uint32_t rp = atomicAdd(&s_bfill[bi], 1u);
-        idx[s_bbase[bi] + s_bgl[bi] + rp] = r0 + j;
-    }
-    // Small groups are verified here, one right record per lane.
-    auto verify_small = [&](uint32_t j, const uint32_t *v) {
-        const uint32_t h = s_rslot[j];
-        if (h == 0xFFFFu || s_bigidx[h] != 0xFFu) return;
+        if (bi != 0xFFu) {
+            const uint32_t rp = atomicAdd(&s_bfill[bi], 1u);
+            idx[s_bbase[bi] + s_bgl[bi] + rp] = r0 + j;
+            continue;
+        }
         const uint32_t ge = s_tab[h] & 0xFFFFu, gs = gstart(h);
         if (W == 0) {
             for (uint32_t q = gs; q < ge; ++q) {
@@ -678,6 +837,9 @@ __global__ __launch_bounds__(256) void k_hash_join(Plan p, const uint32_t *__res
                 emit_solution(sol, cap, &scal[S_STORED], L[l0 + s_grp[q]].mask, R[r0 + j].mask);
             }
         } else {
+            uint32_t v[WV];
+#pragma unroll
+            for (int w = 0; w < WV; ++w) v[w] = R[r0 + j].vec[w];
             for (uint32_t q = gs; q < ge; ++q) {
                 const uint32_t li = s_grp[q];
                 bool ok = true;
@@ -686,18 +848,9 @@ __global__ __launch_bounds__(256) void k_hash_join(Plan p, const uint32_t *__res
                 if (ok) emit_solution(sol, cap, &scal[S_NSOL], L[l0 + li].mask, R[r0 + j].mask);
             }
         }
-    };
-#pragma unroll
-    for (int e = 0; e < kPre; ++e) {
-        const uint32_t j = t + 256 * e;
-        if (j < nr) verify_small(j, rv[e]);
     }
-    for (uint32_t j = t + 256 * kPre; j < nr; j += 256) {
-        uint32_t v[WV];
-#pragma unroll
-        for (int w = 0; w < WV; ++w) v[w] = R[r0 + j].vec[w];
-        verify_small(j, v);
-    }
+    }   // left chunks
+    }   // heavy buckets
     const uint64_t tot = block_sum_u64(hits, s_s4);
     if (t == 0) add_u128(&scal[S_H_LO], &scal[S_H_HI], tot);
 }
@@ -1097,9 +1250,15 @@ template <int W>
 static hipError_t join_impl(const Plan &p, const DevBufs &b, int32_t K, uint64_t cap,
                             hipStream_t st) {
     const uint32_t nb = (uint32_t)K << p.log2F;
-    hipLaunchKernelGGL(k_hash_join<W>, dim3(nb), dim3(256), 0, st, p, b.off[0], b.off[1],
-                       (const Rec<W> *)b.rec[0], (const Rec<W> *)b.rec[1], b.runs, b.iruns,
-                       b.idx, b.scal, b.sol, cap);
+    const Rec<W> *L = (const Rec<W> *)b.rec[0], *R = (const Rec<W> *)b.rec[1];
+    hipLaunchKernelGGL(k_join_light<W>, dim3(nb), dim3(256), 0, st, p, b.off[0], b.off[1], L, R,
+                       b.heavy, b.scal, b.sol, cap);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // Buckets deferred by the light join (count read on the device).
+    hipLaunchKernelGGL(k_join_heavy<W>, dim3(std::min<uint32_t>(nb, 2048)), dim3(256), 0, st, p,
+                       b.off[0], b.off[1], L, R, b.heavy, b.iruns, b.idx, b.scal, b.sol, cap,
+                       b.iruns_cap, b.idx_cap);
     return hipGetLastError();
 }
 
@@ -1135,10 +1294,10 @@ hipError_t launch_tile_counts(const Plan &, const DevBufs &b, uint32_t nruns, in
     const uint32_t tile_r = 256u * ((mode != 0 || verify_cmpx()) ? 8 : verify_kr());
     if (mode == 2)
         hipLaunchKernelGGL(k_tile_counts, dim3((nruns + 255) / 256), dim3(256), 0, st, b.iruns,
-                           b.scal, b.itiles, tile_r, (int)S_NIRUNS);
+                           nruns, b.itiles, tile_r);
     else
         hipLaunchKernelGGL(k_tile_counts, dim3((nruns + 255) / 256), dim3(256), 0, st, b.runs,
-                           b.scal, b.tiles, tile_r, (int)S_NRUNS);
+                           nruns, b.tiles, tile_r);
     return hipGetLastError();
 }
 

@@ -184,3 +184,15 @@ def test_8_70_full_solve_properties():
     # Residue classes mod 64 partition the solve.
     parts = [gsolve(inst.A, inst.d, key_rows=4, slice_mod=64, slice_res=s) for s in (0, 1)]
     assert all(p.H < g.H for p in parts)
+
+
+@pytest.mark.parametrize("lm", [6, 8])
+def test_oversized_buckets_vs_oracle(lm):
+    # A modulus far below the key range makes buckets of thousands of records
+    # per side: the join walks them in chunk pairs and exports big groups.
+    for planted in (False, True):
+        inst = make_instance(5, 40, 5, planted=planted)
+        ref = O.ss_heap(inst.A, inst.d, key_rows=2)
+        say("oversized", inst.name, lm)
+        same(gsolve(inst.A, inst.d, key_rows=2, log2_m=lm, log2_cells=min(lm, 4)), ref,
+             f"{inst.name} M=2^{lm}")
