@@ -151,6 +151,16 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
     } else {
         log2M = std::max(p.qa + p.qb - 10, 1);
     }
+    // Records keep key >> log2M in the bits above the two quarter positions.
+    p.hsh = p.qa + p.qb;
+    {
+        const int key_room = 64 - p.hsh;
+        const int need = lgKd - key_room;          // smallest log2M that fits
+        if (log2M < need) {
+            if (o.log2_m) return MSP_E_INVALID;
+            log2M = need;
+        }
+    }
     p.exact = (((uint64_t)1 << std::min(log2M, 62)) > (uint64_t)p.Kd) ? 1 : 0;
     if (o.log2_cells) {
         log2T = o.log2_cells;

@@ -15,7 +15,7 @@ constexpr int kTileL = 4096;        // left records per verify tile
 constexpr int kThreads = 256;
 constexpr int kBigPairs = 4096;     // equal-key groups with this many pairs go to the tiled verify
 constexpr int kMaxBig = 64;         // such groups exported per chunk pair (the rest verified in place)
-constexpr int kLightGroup = 64;     // largest left group the light join verifies per lane
+constexpr int kLightGroup = 256;    // largest left group the light join verifies per lane
 
 // Everything the kernels need to know about one solve.
 struct Plan {
@@ -24,6 +24,7 @@ struct Plan {
     int32_t log2M, log2T, log2F;     // modulus M, cells T, fine buckets per cell F
     int32_t parts;                   // work-groups per cell in count/scatter
     int32_t exact;                   // 1: M > K_d, each bucket is one key value
+    int32_t hsh;                     // qa + qb: shift of the key in Rec::hdr
     int64_t Kd;                      // target key
     int64_t slice_mod, slice_res;    // slice on the left key (0 = none)
     int64_t kstep, kfirst;           // cell k = kfirst + idx * kstep
@@ -40,12 +41,14 @@ struct alignas(8) QRec {
     uint32_t vec[W > 0 ? W : 1];
 };
 
-// A half record in a bucket: left (k_a + k_b, packed row sums) or right
-// (K_d - k_c - k_d, packed d' - row sums with 0xFFFF for negatives).
+// A half record in a bucket: left (key k_a + k_b, packed row sums) or right
+// (key K_d - k_c - k_d, packed d' - row sums with 0xFFFF for negatives).
+// hdr = outer position | inner position << qa | (key >> log2M) << (qa + qb):
+// the low log2M key bits are the bucket's residue, and the subset masks are
+// read back from the sorted quarter lists only for solutions.
 template <int W>
 struct alignas(8) Rec {
-    int64_t key;
-    uint64_t mask;                   // subset of the half (A|B<<qa, or C|D<<qc)
+    uint64_t hdr;
     uint32_t vec[W > 0 ? W : 1];
 };
 

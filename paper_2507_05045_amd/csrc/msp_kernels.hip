@@ -102,6 +102,20 @@ template <int W>
 struct QPtrs { QRec<W> *q[4]; };
 struct UPtrs { uint32_t *q[4]; };
 
+// Key bits above the residue, and the subset masks of a half record.
+template <int W>
+__device__ __forceinline__ int64_t rkey(const Plan &p, const Rec<W> &r) {
+    return (int64_t)(r.hdr >> p.hsh);
+}
+template <int W>
+__device__ __forceinline__ uint64_t half_mask(const Plan &p, const QPtrs<W> &qs, int side,
+                                              uint64_t hdr) {
+    const uint32_t o = (uint32_t)(hdr & ((1ull << p.qa) - 1));
+    const uint32_t i = (uint32_t)((hdr >> p.qa) & ((1ull << p.qb) - 1));
+    const QRec<W> *outer = qs.q[side ? 2 : 0], *inner = qs.q[side ? 3 : 1];
+    return (uint64_t)outer[o].mask | ((uint64_t)inner[i].mask << (side ? p.qc : p.qa));
+}
+
 // ---------------------------------------------------------------------------
 // Quarter lists (Algorithm 1, the power sets 2^A .. 2^D with their sums)
 // ---------------------------------------------------------------------------
@@ -193,7 +207,6 @@ __global__ __launch_bounds__(256) void k_bucket(Plan p, const QRec<W> *__restric
     const QRec<W> *inner = side ? Dq : B;
     const uint32_t *ioff = side ? offD : offB;
     const uint64_t Qo = side ? p.Q[2] : p.Q[0];
-    const int sh = side ? p.qc : p.qa;
     const uint32_t *offs = side ? offR : offL;
     uint32_t *cnt = side ? cntR : cntL;
     Rec<W> *rec = side ? recR : recL;
@@ -220,8 +233,7 @@ __global__ __launch_bounds__(256) void k_bucket(Plan p, const QRec<W> *__restric
             } else {
                 const uint32_t slot = atomicAdd(&s_f[f], 1u);
                 Rec<W> r;
-                r.key = key;
-                r.mask = (uint64_t)a.mask | ((uint64_t)b.mask << sh);
+                r.hdr = i | ((uint64_t)q << p.qa) | ((uint64_t)(key >> p.log2M) << p.hsh);
 #pragma unroll
                 for (int w = 0; w < (W > 0 ? W : 1); ++w)
                     r.vec[w] = side ? resid_word(p.dpk[w], a.vec[w], b.vec[w])
@@ -309,7 +321,6 @@ __global__ __launch_bounds__(256) void k_scatter_staged(Plan p, const QRec<W> *_
     const QRec<W> *inner = side ? Dq : B;
     const uint32_t *ioff = side ? offD : offB;
     const uint64_t Qo = side ? p.Q[2] : p.Q[0];
-    const int sh = side ? p.qc : p.qa;
     const uint32_t *offs = side ? offR : offL;
     Rec<W> *rec = side ? recR : recL;
     const uint64_t base = ((uint64_t)cw * F) * P + part;
@@ -321,12 +332,14 @@ __global__ __launch_bounds__(256) void k_scatter_staged(Plan p, const QRec<W> *_
         // batch-relative offsets of their pairs.
         QRec<W> av[PER];
         uint32_t b0[PER], nn[PER];
+        uint64_t ai[PER];
         uint32_t mysum = 0;
 #pragma unroll
         for (int e = 0; e < per; ++e) {
             const uint64_t i = c0 + (uint64_t)t * per + e;
             nn[e] = 0;
             b0[e] = 0;
+            ai[e] = i;
             if (i < hi) {
                 av[e] = outer[i];
                 const uint32_t ca = (uint32_t)av[e].key & (T - 1);
@@ -372,8 +385,8 @@ __global__ __launch_bounds__(256) void k_scatter_staged(Plan p, const QRec<W> *_
                         if (p.slice_mod) keep = keep && ((key & smod1) == p.slice_res);
                         const uint32_t o = off + q0 + u - P0;
                         Rec<W> r;
-                        r.key = key;
-                        r.mask = (uint64_t)a.mask | ((uint64_t)bq.mask << sh);
+                        r.hdr = ai[e] | ((uint64_t)(b0[e] + q0 + u) << p.qa) |
+                                ((uint64_t)(key >> p.log2M) << p.hsh);
 #pragma unroll
                         for (int w = 0; w < WV; ++w)
                             r.vec[w] = side ? resid_word(p.dpk[w], a.vec[w], bq.vec[w]) : a.vec[w] + bq.vec[w];
@@ -479,7 +492,8 @@ __global__ __launch_bounds__(256) void k_join_light(Plan p, const uint32_t *__re
                                                    const uint32_t *__restrict__ offR,
                                                    const Rec<W> *__restrict__ L,
                                                    const Rec<W> *__restrict__ R, uint32_t *heavy,
-                                                   uint64_t *scal, uint64_t *sol, uint64_t cap) {
+                                                   uint64_t *scal, uint64_t *sol, uint64_t cap,
+                                                   QPtrs<W> qs) {
     // s_tab[h] = (representative left index << 16) | count, then | group end.
     constexpr uint32_t kEmpty = 0xFFFF0000u;
     constexpr int kPre = 4;                              // right records preloaded per lane
@@ -511,7 +525,7 @@ __global__ __launch_bounds__(256) void k_join_light(Plan p, const uint32_t *__re
     for (int e = 0; e < kPre; ++e) {
         const uint32_t j = t + 256 * e;
         if (j < nr) {
-            rk[e] = R[r0 + j].key;
+            rk[e] = rkey(p, R[r0 + j]);
 #pragma unroll
             for (int w = 0; w < WV; ++w) rv[e][w] = R[r0 + j].vec[w];
         }
@@ -529,7 +543,7 @@ __global__ __launch_bounds__(256) void k_join_light(Plan p, const uint32_t *__re
         for (int u = 0; u < kLU; ++u) {
             const uint32_t i = t + 256 * u;
             if (i < nl) {
-                lk[u] = L[l0 + i].key;
+                lk[u] = rkey(p, L[l0 + i]);
 #pragma unroll
                 for (int w = 0; w < WV; ++w) lv[u][w] = L[l0 + i].vec[w];
             }
@@ -616,7 +630,8 @@ __global__ __launch_bounds__(256) void k_join_light(Plan p, const uint32_t *__re
             atomicAdd((unsigned long long *)&scal[S_NSOL], (unsigned long long)(ge - gs));
             for (uint32_t q = gs; q < ge; ++q) {
                 if (scal[S_STORED] >= cap) break;
-                emit_solution(sol, cap, &scal[S_STORED], L[l0 + s_grp[q]].mask, R[r0 + rj].mask);
+                emit_solution(sol, cap, &scal[S_STORED], half_mask(p, qs, 0, L[l0 + s_grp[q]].hdr),
+                              half_mask(p, qs, 1, R[r0 + rj].hdr));
             }
         } else {
             for (uint32_t q = gs; q < ge; ++q) {
@@ -624,7 +639,9 @@ __global__ __launch_bounds__(256) void k_join_light(Plan p, const uint32_t *__re
                 bool ok = true;
 #pragma unroll
                 for (int w = 0; w < WV; ++w) ok = ok && (s_vec[w][li] == v[w]);
-                if (ok) emit_solution(sol, cap, &scal[S_NSOL], L[l0 + li].mask, R[r0 + rj].mask);
+                if (ok)
+                    emit_solution(sol, cap, &scal[S_NSOL], half_mask(p, qs, 0, L[l0 + li].hdr),
+                                  half_mask(p, qs, 1, R[r0 + rj].hdr));
             }
         }
     };
@@ -637,7 +654,7 @@ __global__ __launch_bounds__(256) void k_join_light(Plan p, const uint32_t *__re
         uint32_t v[WV];
 #pragma unroll
         for (int w = 0; w < WV; ++w) v[w] = R[r0 + j].vec[w];
-        probe(R[r0 + j].key, v, j);
+        probe(rkey(p, R[r0 + j]), v, j);
     }
     const uint64_t tot = block_sum_u64(hits, s_s4);
     if (t == 0) add_u128(&scal[S_H_LO], &scal[S_H_HI], tot);
@@ -651,7 +668,8 @@ __global__ __launch_bounds__(256) void k_join_heavy(Plan p, const uint32_t *__re
                                                    const uint32_t *__restrict__ heavy,
                                                    RunPair *iruns, uint32_t *idx,
                                                    uint64_t *scal, uint64_t *sol, uint64_t cap,
-                                                   uint64_t iruns_cap, uint64_t idx_cap) {
+                                                   uint64_t iruns_cap, uint64_t idx_cap,
+                                                   QPtrs<W> qs) {
     // s_tab[h] = (representative left index << 16) | count, then | group end.
     constexpr uint32_t kEmpty = 0xFFFF0000u;
     constexpr int WV = W > 0 ? W : 1;
@@ -696,7 +714,7 @@ __global__ __launch_bounds__(256) void k_join_heavy(Plan p, const uint32_t *__re
         for (int u = 0; u < kLU; ++u) {
             const uint32_t i = t + 256 * u;
             if (i < nl) {
-                lk[u] = L[l0 + i].key;
+                lk[u] = rkey(p, L[l0 + i]);
 #pragma unroll
                 for (int w = 0; w < WV; ++w) lv[u][w] = L[l0 + i].vec[w];
             }
@@ -785,7 +803,7 @@ __global__ __launch_bounds__(256) void k_join_heavy(Plan p, const uint32_t *__re
     if (t == 0) s_nbig = 0;
     __syncthreads();
     for (uint32_t j = t; j < nr; j += 256) {
-        const uint32_t h = find(R[r0 + j].key);
+        const uint32_t h = find(rkey(p, R[r0 + j]));
         if (h != 0xFFFFu) {
             const uint32_t g = (s_tab[h] & 0xFFFFu) - gstart(h);
             hits += g;
@@ -822,7 +840,7 @@ __global__ __launch_bounds__(256) void k_join_heavy(Plan p, const uint32_t *__re
         if (bi != 0xFFu) idx[s_bbase[bi] + (s_lpos[i] - gstart(h))] = l0 + i;
     }
     for (uint32_t j = t; j < nr; j += 256) {
-        const uint32_t h = find(R[r0 + j].key);
+        const uint32_t h = find(rkey(p, R[r0 + j]));
         if (h == 0xFFFFu) continue;
         const uint32_t bi = s_bigidx[h];
         if (bi != 0xFFu) {
@@ -834,7 +852,8 @@ __global__ __launch_bounds__(256) void k_join_heavy(Plan p, const uint32_t *__re
         if (W == 0) {
             for (uint32_t q = gs; q < ge; ++q) {
                 if (scal[S_STORED] >= cap) break;
-                emit_solution(sol, cap, &scal[S_STORED], L[l0 + s_grp[q]].mask, R[r0 + j].mask);
+                emit_solution(sol, cap, &scal[S_STORED], half_mask(p, qs, 0, L[l0 + s_grp[q]].hdr),
+                              half_mask(p, qs, 1, R[r0 + j].hdr));
             }
         } else {
             uint32_t v[WV];
@@ -845,7 +864,9 @@ __global__ __launch_bounds__(256) void k_join_heavy(Plan p, const uint32_t *__re
                 bool ok = true;
 #pragma unroll
                 for (int w = 0; w < WV; ++w) ok = ok && (s_vec[w][li] == v[w]);
-                if (ok) emit_solution(sol, cap, &scal[S_NSOL], L[l0 + li].mask, R[r0 + j].mask);
+                if (ok)
+                    emit_solution(sol, cap, &scal[S_NSOL], half_mask(p, qs, 0, L[l0 + li].hdr),
+                                  half_mask(p, qs, 1, R[r0 + j].hdr));
             }
         }
     }
@@ -913,7 +934,8 @@ __global__ __launch_bounds__(256) void k_verify(Plan p, const Rec<W> *__restrict
                                                 const RunPair *__restrict__ runs,
                                                 const uint32_t *__restrict__ toff,
                                                 uint32_t nruns, uint64_t *scal, uint64_t *sol,
-                                                uint64_t cap, const uint32_t *__restrict__ idx) {
+                                                uint64_t cap, const uint32_t *__restrict__ idx,
+                                                QPtrs<W> qs) {
     // IDX: run ranges index `idx`, which holds the record positions.
     auto lrec = [&](uint32_t i) -> const Rec<W> & { return IDX ? L[idx[i]] : L[i]; };
     auto rrec = [&](uint32_t i) -> const Rec<W> & { return IDX ? R[idx[i]] : R[i]; };
@@ -945,7 +967,8 @@ __global__ __launch_bounds__(256) void k_verify(Plan p, const Rec<W> *__restrict
             for (int k = 0; k < kKR; ++k) {
                 const uint32_t ri = rb + k * 256 + t;
                 if (ri < re && scal[S_STORED] < cap)
-                    emit_solution(sol, cap, &scal[S_STORED], lrec(li).mask, rrec(ri).mask);
+                    emit_solution(sol, cap, &scal[S_STORED], half_mask(p, qs, 0, lrec(li).hdr),
+                                  half_mask(p, qs, 1, rrec(ri).hdr));
             }
         }
         return;
@@ -960,7 +983,7 @@ __global__ __launch_bounds__(256) void k_verify(Plan p, const Rec<W> *__restrict
         if (CK) rk[k] = -1;                       // never equals a left key (>= 0)
         if (ri < re) {
             if (W > 0) rf[k] = fingerprint<W>(rrec(ri).vec);
-            if (CK) rk[k] = rrec(ri).key;
+            if (CK) rk[k] = rkey(p, rrec(ri));
         }
     }
     // Full check of a flagged (left j, right slot k) pair.
@@ -969,7 +992,8 @@ __global__ __launch_bounds__(256) void k_verify(Plan p, const Rec<W> *__restrict
         if (ri >= re) return;
         const Rec<W> ll = lrec(li);
         const Rec<W> rr = rrec(ri);
-        if (rows_match<W>(ll, rr)) emit_solution(sol, cap, &scal[S_NSOL], ll.mask, rr.mask);
+        if (rows_match<W>(ll, rr))
+            emit_solution(sol, cap, &scal[S_NSOL], half_mask(p, qs, 0, ll.hdr), half_mask(p, qs, 1, rr.hdr));
     };
     uint64_t hits = 0;
     for (uint32_t c0 = lb; c0 < le; c0 += kChunk) {
@@ -977,7 +1001,7 @@ __global__ __launch_bounds__(256) void k_verify(Plan p, const Rec<W> *__restrict
         __syncthreads();
         for (uint32_t i = t; i < cn; i += 256) {
             s_fp[i] = W > 0 ? fingerprint<W>(lrec(c0 + i).vec) : 0u;
-            if (CK) s_lk[i] = lrec(c0 + i).key;
+            if (CK) s_lk[i] = rkey(p, lrec(c0 + i));
         }
         __syncthreads();
         if (!CK) {
@@ -1024,8 +1048,9 @@ __global__ __launch_bounds__(256) void k_verify(Plan p, const Rec<W> *__restrict
                         if (W == 0) {
                             atomicAdd((unsigned long long *)&scal[S_NSOL], 1ull);
                             if (scal[S_STORED] < cap)
-                                emit_solution(sol, cap, &scal[S_STORED], lrec(c0 + jj).mask,
-                                              rrec(rb + k * 256 + t).mask);
+                                emit_solution(sol, cap, &scal[S_STORED],
+                                              half_mask(p, qs, 0, lrec(c0 + jj).hdr),
+                                              half_mask(p, qs, 1, rrec(rb + k * 256 + t).hdr));
                         } else if (rf[k] == x) {
                             check(c0 + jj, k);
                         }
@@ -1142,6 +1167,13 @@ size_t rec_bytes(int W) {
     }
 }
 
+template <int W>
+static QPtrs<W> sorted_quarters(const DevBufs &b) {
+    QPtrs<W> q;
+    for (int x = 0; x < 4; ++x) q.q[x] = (QRec<W> *)b.qsrt[x];
+    return q;
+}
+
 #define MSP_DISPATCH_W(W, CALL)                       \
     switch (W) {                                      \
         case 0: { constexpr int WW = 0; CALL; } break; \
@@ -1252,13 +1284,13 @@ static hipError_t join_impl(const Plan &p, const DevBufs &b, int32_t K, uint64_t
     const uint32_t nb = (uint32_t)K << p.log2F;
     const Rec<W> *L = (const Rec<W> *)b.rec[0], *R = (const Rec<W> *)b.rec[1];
     hipLaunchKernelGGL(k_join_light<W>, dim3(nb), dim3(256), 0, st, p, b.off[0], b.off[1], L, R,
-                       b.heavy, b.scal, b.sol, cap);
+                       b.heavy, b.scal, b.sol, cap, sorted_quarters<W>(b));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // Buckets deferred by the light join (count read on the device).
     hipLaunchKernelGGL(k_join_heavy<W>, dim3(std::min<uint32_t>(nb, 2048)), dim3(256), 0, st, p,
                        b.off[0], b.off[1], L, R, b.heavy, b.iruns, b.idx, b.scal, b.sol, cap,
-                       b.iruns_cap, b.idx_cap);
+                       b.iruns_cap, b.idx_cap, sorted_quarters<W>(b));
     return hipGetLastError();
 }
 
@@ -1307,19 +1339,24 @@ static hipError_t verify_impl(const Plan &p, const DevBufs &b, uint32_t nruns, u
     const Rec<W> *L = (const Rec<W> *)b.rec[0], *R = (const Rec<W> *)b.rec[1];
     if (mode == 2)
         hipLaunchKernelGGL((k_verify<W, false, 8, true, true>), dim3(ntiles), dim3(256), 0, st, p,
-                           L, R, b.iruns, b.itiles, nruns, b.scal, b.sol, cap, b.idx);
+                           L, R, b.iruns, b.itiles, nruns, b.scal, b.sol, cap, b.idx,
+                           sorted_quarters<W>(b));
     else if (mode == 1)
         hipLaunchKernelGGL((k_verify<W, true, 8>), dim3(ntiles), dim3(256), 0, st, p, L, R,
-                           b.runs, b.tiles, nruns, b.scal, b.sol, cap, b.idx);
+                           b.runs, b.tiles, nruns, b.scal, b.sol, cap, b.idx,
+                           sorted_quarters<W>(b));
     else if (verify_cmpx())
         hipLaunchKernelGGL((k_verify<W, false, 8, true>), dim3(ntiles), dim3(256), 0, st, p, L, R,
-                           b.runs, b.tiles, nruns, b.scal, b.sol, cap, b.idx);
+                           b.runs, b.tiles, nruns, b.scal, b.sol, cap, b.idx,
+                           sorted_quarters<W>(b));
     else if (verify_kr() == 16)
         hipLaunchKernelGGL((k_verify<W, false, 16>), dim3(ntiles), dim3(256), 0, st, p, L, R,
-                           b.runs, b.tiles, nruns, b.scal, b.sol, cap, b.idx);
+                           b.runs, b.tiles, nruns, b.scal, b.sol, cap, b.idx,
+                           sorted_quarters<W>(b));
     else
         hipLaunchKernelGGL((k_verify<W, false, 8>), dim3(ntiles), dim3(256), 0, st, p, L, R,
-                           b.runs, b.tiles, nruns, b.scal, b.sol, cap, b.idx);
+                           b.runs, b.tiles, nruns, b.scal, b.sol, cap, b.idx,
+                           sorted_quarters<W>(b));
     return hipGetLastError();
 }
 
