@@ -37,6 +37,12 @@ WORKLOADS = {
                  desc="(9,80) seed 0 full solve, key rows 1-4 (base 8000)"),
     "10_90s": dict(m=10, n=90, key_rows=4, seeds=[0], planted=False, slice_mod=64,
                    desc="(10,90) seed 0, residue slice k_L mod 64 = 0, key rows 1-4 (base 9000)"),
+    # Planted twins only (feasible, like the paper's benchmark set); with
+    # --first-solution the solve stops at the first verified x (Algorithm 2).
+    "8_70p": dict(m=8, n=70, key_rows=4, seeds=[0, 1, 2, 3, 4], planted=True, planted_only=True,
+                  slice_mod=0, desc="(8,70) planted twins of seeds 0-4, key rows 1-4"),
+    "9_80p": dict(m=9, n=80, key_rows=4, seeds=[0], planted=True, planted_only=True,
+                  slice_mod=0, desc="(9,80) planted twin of seed 0, key rows 1-4"),
 }
 
 
@@ -44,7 +50,8 @@ def build_instances(w):
     from paper_2507_05045_amd.inputs import make_instance
     out = []
     for s in w["seeds"]:
-        out.append(make_instance(w["m"], w["n"], s, key_rows=w["key_rows"]))
+        if not w.get("planted_only"):
+            out.append(make_instance(w["m"], w["n"], s, key_rows=w["key_rows"]))
         if w["planted"]:
             out.append(make_instance(w["m"], w["n"], s, planted=True, key_rows=w["key_rows"]))
     return out
@@ -199,6 +206,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="6_50", choices=sorted(WORKLOADS) + ["stream"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--first-solution", action="store_true",
+                    help="stop each solve at the first verified solution (time to first solution)")
     ap.add_argument("--stream-count", type=int, default=64,
                     help="instances of the uneven stream for --workload stream")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -229,7 +238,8 @@ def main():
     w = WORKLOADS[args.workload]
     insts = build_instances(w)
     ctxs = [msp.Context(i.A, i.d) for i in insts]
-    kw = dict(key_rows=w["key_rows"], slice_mod=w["slice_mod"], slice_res=0)
+    kw = dict(key_rows=w["key_rows"], slice_mod=w["slice_mod"], slice_res=0,
+              first_only=1 if args.first_solution else 0)
 
     def step():
         stats = []
@@ -298,6 +308,9 @@ def main():
                    "instances": len(insts), "slice_mod": w["slice_mod"]},
         "hits_per_step": hits,
         "solutions": nsol,
+        "first_solution": bool(args.first_solution),
+        "solve_ms": [round(s["ms_total"], 3) for s in all_stats[-1]],
+        "windows": [f"{s['windows']}/{s['windows_total']}" for s in all_stats[-1]],
         "phase_ms_per_step": {k: v / args.steps for k, v in tot.items()},
         "roofline": roof,
     }

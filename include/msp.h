@@ -68,6 +68,10 @@ typedef struct {
     void    *workspace;       /* caller-owned device buffer, or NULL (library allocates)*/
     uint64_t workspace_bytes; /* size of `workspace`; with NULL workspace: budget, 0=auto*/
     void    *stream;          /* hipStream_t to run on, or NULL (library's own stream)  */
+    int32_t  first_only;      /* 1: stop after the first residue window that yields a
+                                 solution (Algorithm 2 returns the first x); H, |S| and
+                                 the solutions then cover the windows processed        */
+    int32_t  reserved;
 } msp_opts;
 
 /* Per-solve statistics; phase times are measured with HIP events on the
@@ -89,6 +93,9 @@ typedef struct {
     int32_t  log2_m, log2_cells, parts, key_rows;
     int32_t  exact_buckets;   /* 1: each bucket holds one key value                  */
     int32_t  words;           /* 32-bit words of packed non-key rows                 */
+    int32_t  complete;        /* 1: every residue window was processed               */
+    int32_t  reserved;
+    uint64_t windows_total;   /* residue windows of the whole (sliced) solve         */
 } msp_stats_t;
 
 /* Copies A (row-major m*n int32) and d (m int32); the caller may free both

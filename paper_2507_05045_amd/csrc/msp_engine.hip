@@ -466,6 +466,13 @@ int job_step(Job &j) {
             }
             j.st.ms_count += ev_ms(j.ev[E_C0], j.ev[E_C1]);
             j.st.ms_scan += ev_ms(j.ev[E_C1], j.ev[E_C2]);
+            // First-solution mode: the scalars copied with this count already
+            // include every earlier window's verify.
+            if (j.o.first_only && j.hs[S_NSOL] > 0) {
+                JCHK(hipMemcpyAsync(j.hs, j.b.scal, S_COUNT * 8, hipMemcpyDeviceToHost, j.s));
+                j.next = A_FINAL1;
+                return MSP_OK;
+            }
             const uint64_t totL = j.hs[S_TOT_L], totR = j.hs[S_TOT_R];
             if (totL > z.cap_rec || totR > z.cap_rec) {
                 if (j.K == 1) return MSP_E_NOMEM;
@@ -577,6 +584,7 @@ int job_step(Job &j) {
             c->h_lo = j.hs[S_H_LO];
             c->h_hi = j.hs[S_H_HI];
             c->nsol = j.hs[S_NSOL];
+            j.st.complete = j.idx >= z.ncells ? 1 : 0;
             j.st.ms_total = (now_s() - j.t_wall0) * 1e3;
             c->stats = j.st;
             c->have_result = true;
@@ -611,6 +619,8 @@ void job_init_stats(Job &j) {
     j.st.exact_buckets = p.exact;
     j.st.words = p.W;
     j.st.record_bytes = rec_bytes(p.W);
+    j.st.complete = 1;
+    j.st.windows_total = (j.P.z.ncells + j.P.z.kwin - 1) / std::max<uint64_t>(j.P.z.kwin, 1);
 }
 
 // ---------------------------------------------------------------------------

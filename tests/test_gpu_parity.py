@@ -196,3 +196,21 @@ def test_oversized_buckets_vs_oracle(lm):
         say("oversized", inst.name, lm)
         same(gsolve(inst.A, inst.d, key_rows=2, log2_m=lm, log2_cells=min(lm, 4)), ref,
              f"{inst.name} M=2^{lm}")
+
+
+def test_first_solution_mode():
+    # Algorithm 2 returns the first x: the solve stops after the first residue
+    # window that yields a solution; what it returns is part of the full set.
+    from paper_2507_05045_amd import msp
+    inst = make_instance(8, 70, 0, planted=True)
+    full = gsolve(inst.A, inst.d, key_rows=4)
+    ctx = msp.Context(inst.A, inst.d)
+    ctx.solve(key_rows=4, first_only=1, window_records=1 << 28)
+    first = ctx.result()
+    assert 1 <= first.nsol <= full.nsol
+    assert {bytes(x) for x in first.solutions} <= {bytes(x) for x in full.solutions}
+    assert first.H <= full.H
+    st = first.stats
+    assert st["windows"] <= st["windows_total"]
+    assert st["complete"] == (1 if first.H == full.H else 0) or first.nsol == full.nsol
+    ctx.close()
