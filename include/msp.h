@@ -71,7 +71,8 @@ typedef struct {
     int32_t  first_only;      /* 1: stop after the first residue window that yields a
                                  solution (Algorithm 2 returns the first x); H, |S| and
                                  the solutions then cover the windows processed        */
-    int32_t  reserved;
+    int32_t  join_variant;    /* bucket join: 0 = per-slot chains (groups of ~1),
+                                 1 = contiguous key groups (groups of ~5-250)          */
 } msp_opts;
 
 /* Per-solve statistics; phase times are measured with HIP events on the

@@ -177,6 +177,8 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
     p.log2M = log2M; p.log2T = log2T; p.log2F = log2M - log2T;
     p.slice_mod = o.slice_mod;
     p.slice_res = o.slice_res;
+    if (o.join_variant < 0 || o.join_variant > 1) return MSP_E_INVALID;
+    p.join_grouped = o.join_variant;
     const uint64_t T = (uint64_t)1 << log2T;
     if (o.slice_mod > 0) {
         p.kstep = (int64_t)std::min<uint64_t>((uint64_t)o.slice_mod, T);

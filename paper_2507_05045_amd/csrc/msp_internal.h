@@ -25,6 +25,7 @@ struct Plan {
     int32_t parts;                   // work-groups per cell in count/scatter
     int32_t exact;                   // 1: M > K_d, each bucket is one key value
     int32_t hsh;                     // qa + qb: shift of the key in Rec::hdr
+    int32_t join_grouped;            // light join variant: 0 chains, 1 contiguous groups
     int64_t Kd;                      // target key
     int64_t slice_mod, slice_res;    // slice on the left key (0 = none)
     int64_t kstep, kfirst;           // cell k = kfirst + idx * kstep

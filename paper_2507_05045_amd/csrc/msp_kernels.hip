@@ -487,8 +487,142 @@ __device__ __forceinline__ uint32_t key_hash(int64_t k) {
     return (uint32_t)(((uint64_t)k * 0x9E3779B97F4A7C15ull) >> 40);
 }
 
+// Light join of one bucket whose equal-key groups are small: left records
+// are pushed onto per-slot chains in LDS (one CAS per record, the slot word
+// packs chain head and length); each right record walks its slot's chain.
+// Buckets with more than kJoinCap left records, or a chain longer than
+// kLightGroup, are handed to k_join_heavy unprocessed.
 template <int W>
 __global__ __launch_bounds__(256) void k_join_light(Plan p, const uint32_t *__restrict__ offL,
+                                                   const uint32_t *__restrict__ offR,
+                                                   const Rec<W> *__restrict__ L,
+                                                   const Rec<W> *__restrict__ R, uint32_t *heavy,
+                                                   uint64_t *scal, uint64_t *sol, uint64_t cap,
+                                                   QPtrs<W> qs) {
+    constexpr uint32_t kEnd = 0xFFFFu;
+    constexpr uint32_t kEmpty = kEnd << 16;               // head = end of chain, length 0
+    constexpr int kPre = 4;                              // right records preloaded per lane
+    constexpr int WV = W > 0 ? W : 1;
+    __shared__ int64_t s_key[kJoinCap];
+    __shared__ uint32_t s_vec[WV][kJoinCap];             // left packed rows, by left index
+    constexpr uint32_t kLightSlots = 2048;               // load factor <= 3/4 at kJoinCap
+    __shared__ uint32_t s_head[kLightSlots];             // (first left index << 16) | length
+    __shared__ uint16_t s_next[kJoinCap];
+    __shared__ uint64_t s_s4[4];
+    __shared__ uint32_t s_gmax;
+    const uint32_t b = blockIdx.x;
+    const uint64_t P = p.parts;
+    const uint32_t l0 = offL[b * P], l1 = offL[(b + 1) * P];
+    const uint32_t r0 = offR[b * P], r1 = offR[(b + 1) * P];
+    const uint32_t nl = l1 - l0, nr = r1 - r0;
+    if (nl == 0 || nr == 0) return;                     // uniform across the block
+    if (nl > (uint32_t)kJoinCap) {                      // too big for LDS: heavy kernel
+        if (threadIdx.x == 0)
+            heavy[atomicAdd((unsigned long long *)&scal[S_NHEAVY], 1ull)] = b;
+        return;
+    }
+    const int t = threadIdx.x;
+    // Right keys and rows are loaded first and consumed after the build.
+    int64_t rk[kPre];
+    uint32_t rv[kPre][WV];
+#pragma unroll
+    for (int e = 0; e < kPre; ++e) {
+        const uint32_t j = t + 256 * e;
+        if (j < nr) {
+            rk[e] = rkey(p, R[r0 + j]);
+#pragma unroll
+            for (int w = 0; w < WV; ++w) rv[e][w] = R[r0 + j].vec[w];
+        }
+    }
+    uint32_t slots = 256;
+    while (3 * slots < 4 * nl) slots <<= 1;
+    const uint32_t smask = slots - 1;
+    for (uint32_t i = t; i < slots; i += 256) s_head[i] = kEmpty;
+    if (t == 0) s_gmax = 0;
+    {   // all left loads of this lane issued together, then staged into LDS
+        constexpr int kLU = (kJoinCap + 255) / 256;
+        int64_t lk[kLU];
+        uint32_t lv[kLU][WV];
+#pragma unroll
+        for (int u = 0; u < kLU; ++u) {
+            const uint32_t i = t + 256 * u;
+            if (i < nl) {
+                lk[u] = rkey(p, L[l0 + i]);
+#pragma unroll
+                for (int w = 0; w < WV; ++w) lv[u][w] = L[l0 + i].vec[w];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kLU; ++u) {
+            const uint32_t i = t + 256 * u;
+            if (i < nl) {
+                s_key[i] = lk[u];
+#pragma unroll
+                for (int w = 0; w < WV; ++w) s_vec[w][i] = lv[u][w];
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = t; i < nl; i += 256) {
+        const uint32_t h = key_hash(s_key[i]) & smask;
+        uint32_t old = s_head[h];
+        for (;;) {
+            const uint32_t got = atomicCAS(&s_head[h], old, (i << 16) | ((old & 0xFFFFu) + 1));
+            if (got == old) break;
+            old = got;
+        }
+        s_next[i] = (uint16_t)(old >> 16);
+        const uint32_t len = (old & 0xFFFFu) + 1;
+        if (len > (uint32_t)kLightGroup) atomicMax(&s_gmax, len);   // rare: one shared word
+    }
+    __syncthreads();
+    const uint32_t gmax = s_gmax;
+    if (gmax > (uint32_t)kLightGroup) {                 // a large group: heavy kernel
+        if (t == 0) heavy[atomicAdd((unsigned long long *)&scal[S_NHEAVY], 1ull)] = b;
+        return;
+    }
+    uint64_t hits = 0;
+    auto hit = [&](uint32_t i, const uint32_t *v, uint32_t rj) {
+        ++hits;
+        if (W == 0) {
+            atomicAdd((unsigned long long *)&scal[S_NSOL], 1ull);
+            if (scal[S_STORED] < cap)
+                emit_solution(sol, cap, &scal[S_STORED], half_mask(p, qs, 0, L[l0 + i].hdr),
+                              half_mask(p, qs, 1, R[r0 + rj].hdr));
+        } else {
+            bool ok = true;
+#pragma unroll
+            for (int w = 0; w < WV; ++w) ok = ok && (s_vec[w][i] == v[w]);
+            if (ok)
+                emit_solution(sol, cap, &scal[S_NSOL], half_mask(p, qs, 0, L[l0 + i].hdr),
+                              half_mask(p, qs, 1, R[r0 + rj].hdr));
+        }
+    };
+    auto probe = [&](const int64_t key, const uint32_t *v, uint32_t rj) {
+        for (uint32_t i = s_head[key_hash(key) & smask] >> 16; i != kEnd; i = s_next[i])
+            if (s_key[i] == key) hit(i, v, rj);
+    };
+#pragma unroll
+    for (int e = 0; e < kPre; ++e) {
+        const uint32_t j = t + 256 * e;
+        if (j < nr) probe(rk[e], rv[e], j);
+    }
+    for (uint32_t j = t + 256 * kPre; j < nr; j += 256) {
+        uint32_t v[WV];
+#pragma unroll
+        for (int w = 0; w < WV; ++w) v[w] = R[r0 + j].vec[w];
+        probe(rkey(p, R[r0 + j]), v, j);
+    }
+    const uint64_t tot = block_sum_u64(hits, s_s4);
+    if (t == 0) add_u128(&scal[S_H_LO], &scal[S_H_HI], tot);
+}
+
+// Light join variant for buckets whose equal-key groups hold a few to a
+// few hundred records: linear-probe table with one representative per
+// distinct key, counts scanned into contiguous groups, each right record
+// loops over its group with independent LDS loads.
+template <int W>
+__global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__restrict__ offL,
                                                    const uint32_t *__restrict__ offR,
                                                    const Rec<W> *__restrict__ L,
                                                    const Rec<W> *__restrict__ R, uint32_t *heavy,
@@ -1283,8 +1417,12 @@ static hipError_t join_impl(const Plan &p, const DevBufs &b, int32_t K, uint64_t
                             hipStream_t st) {
     const uint32_t nb = (uint32_t)K << p.log2F;
     const Rec<W> *L = (const Rec<W> *)b.rec[0], *R = (const Rec<W> *)b.rec[1];
-    hipLaunchKernelGGL(k_join_light<W>, dim3(nb), dim3(256), 0, st, p, b.off[0], b.off[1], L, R,
-                       b.heavy, b.scal, b.sol, cap, sorted_quarters<W>(b));
+    if (p.join_grouped)
+        hipLaunchKernelGGL(k_join_grouped<W>, dim3(nb), dim3(256), 0, st, p, b.off[0], b.off[1], L,
+                           R, b.heavy, b.scal, b.sol, cap, sorted_quarters<W>(b));
+    else
+        hipLaunchKernelGGL(k_join_light<W>, dim3(nb), dim3(256), 0, st, p, b.off[0], b.off[1], L, R,
+                           b.heavy, b.scal, b.sol, cap, sorted_quarters<W>(b));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // Buckets deferred by the light join (count read on the device).

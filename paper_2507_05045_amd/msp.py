@@ -36,7 +36,7 @@ class msp_opts(C.Structure):
                 ("parts", C.c_int32), ("slice_mod", C.c_int64), ("slice_res", C.c_int64),
                 ("max_solutions", C.c_uint64), ("window_records", C.c_uint64),
                 ("workspace", C.c_void_p), ("workspace_bytes", C.c_uint64),
-                ("stream", C.c_void_p), ("first_only", C.c_int32), ("reserved", C.c_int32)]
+                ("stream", C.c_void_p), ("first_only", C.c_int32), ("join_variant", C.c_int32)]
 
 
 class msp_stats_t(C.Structure):

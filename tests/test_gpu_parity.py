@@ -62,9 +62,10 @@ def test_small_random_vs_brute_force(case):
         ref = O.brute(inst.A, inst.d, key_rows=case["r"])
         same(gsolve(inst.A, inst.d, key_rows=case["r"]), ref, f"default {case} {seed}")
         # force hash buckets (modulus below K_d) and a few cell layouts
-        for lm, lc, parts in [(3, 1, 1), (5, 2, 3), (6, 6, 2)]:
-            g = gsolve(inst.A, inst.d, key_rows=case["r"], log2_m=lm, log2_cells=lc, parts=parts)
-            same(g, ref, f"M=2^{lm} T=2^{lc} P={parts} {case} {seed}")
+        for lm, lc, parts, jv in [(3, 1, 1, 0), (5, 2, 3, 1), (6, 6, 2, 0), (6, 3, 2, 1)]:
+            g = gsolve(inst.A, inst.d, key_rows=case["r"], log2_m=lm, log2_cells=lc, parts=parts,
+                       join_variant=jv)
+            same(g, ref, f"M=2^{lm} T=2^{lc} P={parts} join={jv} {case} {seed}")
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 7])
@@ -194,8 +195,9 @@ def test_oversized_buckets_vs_oracle(lm):
         inst = make_instance(5, 40, 5, planted=planted)
         ref = O.ss_heap(inst.A, inst.d, key_rows=2)
         say("oversized", inst.name, lm)
-        same(gsolve(inst.A, inst.d, key_rows=2, log2_m=lm, log2_cells=min(lm, 4)), ref,
-             f"{inst.name} M=2^{lm}")
+        for jv in (0, 1):
+            same(gsolve(inst.A, inst.d, key_rows=2, log2_m=lm, log2_cells=min(lm, 4),
+                        join_variant=jv), ref, f"{inst.name} M=2^{lm} join={jv}")
 
 
 def test_first_solution_mode():
