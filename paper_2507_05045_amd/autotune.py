@@ -77,7 +77,10 @@ def tune(A, d, key_rows: int = 1, max_seconds: float = 20.0, slice_bits: Optiona
     if key in cache and not force:
         return cache[key]["opts"]
     ctx = msp.Context(A, d)
-    ctx.solve(key_rows=key_rows)
+    # With a slice given, the planner's default is read off a sliced solve:
+    # a whole solve of a large class can take minutes.
+    ctx.solve(key_rows=key_rows, **(dict(slice_mod=1 << slice_bits, slice_res=0)
+                                    if slice_bits else {}))
     base = ctx.stats()
     full_ms = base["ms_total"]
     lm, lc, parts = base["log2_m"], base["log2_cells"], base["parts"]
