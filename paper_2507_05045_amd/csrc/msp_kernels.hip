@@ -283,13 +283,13 @@ __device__ uint32_t block_excl_scan_rt(T *a, int n, uint32_t *w4) {
 // Bucket scatter staged through LDS.  The work-group enumerates its pairs in
 // batches; each batch is counting-sorted by fine bucket in LDS and written
 // out so that consecutive lanes store consecutive records of one bucket
-// (full cache lines instead of one partial line per record).
-constexpr int kStageMaxF = 1024;          // fine buckets handled by the staged path
+// (whole cache lines instead of one partial line per record).  Only the pair
+// (outer element, inner element) and its fine bucket are staged, 8 bytes per
+// pair: the record itself is rebuilt from the quarter lists at write-out,
+// which costs two cached loads instead of a 16-24 byte LDS round trip.
+constexpr int kStageBatch = 3072;          // pairs per LDS batch
 
-template <int W>
-constexpr int stage_batch() { return (int)(49152 / sizeof(Rec<W>)) & ~255; }   // ~48 KB of records
-
-template <int W, int PER>
+template <int W, int PER, int MAXF>
 __global__ __launch_bounds__(256) void k_scatter_staged(Plan p, const QRec<W> *__restrict__ A,
                                                         const QRec<W> *__restrict__ B,
                                                         const uint32_t *__restrict__ offB,
@@ -299,13 +299,15 @@ __global__ __launch_bounds__(256) void k_scatter_staged(Plan p, const QRec<W> *_
                                                         const uint32_t *__restrict__ offL,
                                                         const uint32_t *__restrict__ offR,
                                                         Rec<W> *recL, Rec<W> *recR, int64_t idx0) {
-    constexpr int BATCH = stage_batch<W>();
+    constexpr int BATCH = kStageBatch;
     constexpr int per = PER;                     // outer elements per thread per chunk
     constexpr int WV = W > 0 ? W : 1;
-    __shared__ uint32_t s_cur[kStageMaxF];
-    __shared__ uint32_t s_cnt[kStageMaxF];
-    __shared__ Rec<W> s_rec[BATCH];
-    __shared__ uint16_t s_f[BATCH];
+    static_assert(256 * PER <= 65536, "chunk-relative outer index must fit 16 bits");
+    __shared__ uint32_t s_cur[MAXF];
+    __shared__ uint32_t s_cnt[MAXF];
+    __shared__ uint32_t s_q[BATCH];              // inner element of the pair
+    __shared__ uint16_t s_io[BATCH];             // outer element, relative to the chunk
+    __shared__ uint16_t s_f[BATCH];              // fine bucket, 0xFFFF = filtered out
     __shared__ uint16_t s_perm[BATCH];
     __shared__ uint32_t s_w4[4];
     const int side = blockIdx.y;
@@ -329,20 +331,19 @@ __global__ __launch_bounds__(256) void k_scatter_staged(Plan p, const QRec<W> *_
     const int64_t smod1 = p.slice_mod - 1;
     for (uint64_t c0 = lo; c0 < hi; c0 += (uint64_t)256 * per) {
         // This thread's outer elements (per of them, consecutive) and the
-        // batch-relative offsets of their pairs.
-        QRec<W> av[PER];
+        // chunk-relative offsets of their pairs.
+        int64_t akey[PER];
         uint32_t b0[PER], nn[PER];
-        uint64_t ai[PER];
         uint32_t mysum = 0;
 #pragma unroll
         for (int e = 0; e < per; ++e) {
             const uint64_t i = c0 + (uint64_t)t * per + e;
             nn[e] = 0;
             b0[e] = 0;
-            ai[e] = i;
+            akey[e] = 0;
             if (i < hi) {
-                av[e] = outer[i];
-                const uint32_t ca = (uint32_t)av[e].key & (T - 1);
+                akey[e] = outer[i].key;
+                const uint32_t ca = (uint32_t)akey[e] & (T - 1);
                 const uint32_t j = side ? ((ca - k) & (T - 1)) : ((k - ca) & (T - 1));
                 b0[e] = ioff[j];
                 nn[e] = ioff[j + 1] - b0[e];
@@ -361,36 +362,29 @@ __global__ __launch_bounds__(256) void k_scatter_staged(Plan p, const QRec<W> *_
         for (uint32_t P0 = 0; P0 < total; P0 += BATCH) {
             const uint32_t nb = min((uint32_t)BATCH, total - P0);
             for (int f = t; f < Fs; f += 256) s_cnt[f] = 0;
-            // Generate my pairs whose index falls in [P0, P0 + nb).
+            // Stage my pairs whose index falls in [P0, P0 + nb).
             uint32_t off = myoff;
 #pragma unroll
             for (int e = 0; e < per; ++e) {
                 const uint32_t n = nn[e];
                 const uint32_t qa = off >= P0 ? 0u : min(n, P0 - off);
                 const uint32_t qb = (off + n <= P0 + nb) ? n : (P0 + nb > off ? P0 + nb - off : 0u);
-                // Loads of up to 8 inner records are issued together, then used.
+                // Keys of up to 8 inner elements are loaded together, then used.
                 constexpr int kU = 8;
                 for (uint32_t q0 = qa; q0 < qb; q0 += kU) {
-                    QRec<W> bb[kU];
+                    int64_t bk[kU];
 #pragma unroll
                     for (int u = 0; u < kU; ++u)
-                        if (q0 + u < qb) bb[u] = inner[b0[e] + q0 + u];
+                        if (q0 + u < qb) bk[u] = inner[b0[e] + q0 + u].key;
 #pragma unroll
                     for (int u = 0; u < kU; ++u) {
                         if (q0 + u >= qb) break;
-                        const QRec<W> &bq = bb[u];
-                        const QRec<W> &a = av[e];
-                        const int64_t key = side ? a.key - bq.key : a.key + bq.key;
+                        const int64_t key = side ? akey[e] - bk[u] : akey[e] + bk[u];
                         bool keep = side ? key >= 0 : key <= p.Kd;
                         if (p.slice_mod) keep = keep && ((key & smod1) == p.slice_res);
                         const uint32_t o = off + q0 + u - P0;
-                        Rec<W> r;
-                        r.hdr = ai[e] | ((uint64_t)(b0[e] + q0 + u) << p.qa) |
-                                ((uint64_t)(key >> p.log2M) << p.hsh);
-#pragma unroll
-                        for (int w = 0; w < WV; ++w)
-                            r.vec[w] = side ? resid_word(p.dpk[w], a.vec[w], bq.vec[w]) : a.vec[w] + bq.vec[w];
-                        s_rec[o] = r;
+                        s_q[o] = b0[e] + q0 + u;
+                        s_io[o] = (uint16_t)(t * per + e);
                         s_f[o] = keep ? (uint16_t)((key & M1) >> p.log2T) : (uint16_t)0xFFFF;
                     }
                 }
@@ -411,7 +405,17 @@ __global__ __launch_bounds__(256) void k_scatter_staged(Plan p, const QRec<W> *_
                 const uint32_t slot = s_perm[o];
                 const uint32_t f = s_f[slot];
                 const uint32_t start = f ? s_cnt[f - 1] : 0u;
-                rec[s_cur[f] + (o - start)] = s_rec[slot];
+                const uint32_t q = s_q[slot];
+                const uint64_t ai = c0 + s_io[slot];
+                const QRec<W> a = outer[ai];
+                const QRec<W> bq = inner[q];
+                const int64_t key = side ? a.key - bq.key : a.key + bq.key;
+                Rec<W> r;
+                r.hdr = ai | ((uint64_t)q << p.qa) | ((uint64_t)(key >> p.log2M) << p.hsh);
+#pragma unroll
+                for (int w = 0; w < WV; ++w)
+                    r.vec[w] = side ? resid_word(p.dpk[w], a.vec[w], bq.vec[w]) : a.vec[w] + bq.vec[w];
+                rec[s_cur[f] + (o - start)] = r;
             }
             __syncthreads();
             for (int f = t; f < F; f += 256) s_cur[f] += s_cnt[f] - (f ? s_cnt[f - 1] : 0u);
@@ -1374,15 +1378,22 @@ static hipError_t staged_impl(const Plan &p, const DevBufs &b, int64_t idx0, int
     const uint64_t T = (uint64_t)1 << p.log2T;
     const uint64_t avg = std::max<uint64_t>(1, std::min((uint64_t)p.Q[1], (uint64_t)p.Q[3]) / T);
     const int per = avg >= 8 ? 1 : avg >= 4 ? 2 : 4;   // outer elements per thread per chunk
+    const bool small_f = (1 << p.log2F) <= 1024;        // smaller LDS, more work-groups per CU
     dim3 grid((uint32_t)K * p.parts, 2);
-#define MSP_STAGED(PERV)                                                                        \
-    hipLaunchKernelGGL((k_scatter_staged<W, PERV>), grid, dim3(256), 0, st, p,                  \
+#define MSP_STAGED(PERV, MF)                                                                    \
+    hipLaunchKernelGGL((k_scatter_staged<W, PERV, MF>), grid, dim3(256), 0, st, p,              \
                        (const QRec<W> *)b.qsrt[0], (const QRec<W> *)b.qsrt[1], b.qcnt[1],       \
                        (const QRec<W> *)b.qsrt[2], (const QRec<W> *)b.qsrt[3], b.qcnt[3],       \
                        b.off[0], b.off[1], (Rec<W> *)b.rec[0], (Rec<W> *)b.rec[1], idx0)
-    if (per == 1) MSP_STAGED(1);
-    else if (per == 2) MSP_STAGED(2);
-    else MSP_STAGED(4);
+    if (small_f) {
+        if (per == 1) MSP_STAGED(1, 1024);
+        else if (per == 2) MSP_STAGED(2, 1024);
+        else MSP_STAGED(4, 1024);
+    } else {
+        if (per == 1) MSP_STAGED(1, kMaxFine);
+        else if (per == 2) MSP_STAGED(2, kMaxFine);
+        else MSP_STAGED(4, kMaxFine);
+    }
 #undef MSP_STAGED
     return hipGetLastError();
 }
@@ -1398,7 +1409,7 @@ static bool scatter_direct() {
 
 hipError_t launch_scatter(const Plan &p, const DevBufs &b, int64_t idx0, int32_t K,
                           hipStream_t st) {
-    if ((1 << p.log2F) <= kStageMaxF && !scatter_direct()) {
+    if ((1 << p.log2F) <= kMaxFine && !scatter_direct()) {
         MSP_DISPATCH_W(p.W, return staged_impl<WW>(p, b, idx0, K, st));
     }
     MSP_DISPATCH_W(p.W, return (bucket_impl<WW, true>(p, b, idx0, K, st)));
