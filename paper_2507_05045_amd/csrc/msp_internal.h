@@ -34,9 +34,10 @@ struct Plan {
 };
 
 // A quarter subset: 1-D key (for quarter C: K_d - key), subset mask, packed
-// partial sums of the non-key rows.
+// partial sums of the non-key rows.  Records are packed at 4-byte alignment
+// (no padding word for odd W): every access is a dword-aligned load or store.
 template <int W>
-struct alignas(8) QRec {
+struct __attribute__((packed, aligned(4))) QRec {
     int64_t key;
     uint32_t mask;
     uint32_t vec[W > 0 ? W : 1];
@@ -46,12 +47,15 @@ struct alignas(8) QRec {
 // (key K_d - k_c - k_d, packed d' - row sums with 0xFFFF for negatives).
 // hdr = outer position | inner position << qa | (key >> log2M) << (qa + qb):
 // the low log2M key bits are the bucket's residue, and the subset masks are
-// read back from the sorted quarter lists only for solutions.
+// read back from the sorted quarter lists only for solutions.  Packed at
+// 4-byte alignment like QRec: 12 + 4W bytes, so odd W costs no padding.
 template <int W>
-struct alignas(8) Rec {
+struct __attribute__((packed, aligned(4))) Rec {
     uint64_t hdr;
     uint32_t vec[W > 0 ? W : 1];
 };
+
+static_assert(sizeof(Rec<3>) == 20 && sizeof(QRec<3>) == 24, "packed record layout");
 
 struct RunPair {
     uint32_t l0, nl, r0, nr;         // window-relative record ranges

@@ -623,8 +623,11 @@ __global__ __launch_bounds__(256) void k_join_light(Plan p, const uint32_t *__re
 
 // Light join variant for buckets whose equal-key groups hold a few to a
 // few hundred records: linear-probe table with one representative per
-// distinct key, counts scanned into contiguous groups, each right record
-// loops over its group with independent LDS loads.
+// distinct key, counts scanned into contiguous groups.  The left rows are
+// then laid out in group order and the right records of a chunk are
+// counting-sorted by group, so that neighbouring lanes walk the same group:
+// the left words they compare are LDS broadcasts and the loop trip counts
+// agree across most of a wave.
 template <int W>
 __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__restrict__ offL,
                                                    const uint32_t *__restrict__ offR,
@@ -634,13 +637,19 @@ __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__
                                                    QPtrs<W> qs) {
     // s_tab[h] = (representative left index << 16) | count, then | group end.
     constexpr uint32_t kEmpty = 0xFFFF0000u;
-    constexpr int kPre = 4;                              // right records preloaded per lane
     constexpr int WV = W > 0 ? W : 1;
+    constexpr uint32_t kNone = 0xFFFFu;
+    constexpr uint32_t kRChunk = 1024;                   // right records sorted per pass
     __shared__ int64_t s_key[kJoinCap];
-    __shared__ uint32_t s_vec[WV][kJoinCap];             // left packed rows, by left index
+    __shared__ uint32_t s_vec[WV][kJoinCap + 8];         // left rows: by left index, then by group
     __shared__ uint32_t s_tab[kJoinSlots];
     __shared__ uint16_t s_slot[kJoinCap];
-    __shared__ uint16_t s_grp[kJoinCap];
+    __shared__ uint16_t s_grp[kJoinCap];                 // group order -> left index
+    __shared__ uint16_t s_rgs[kRChunk];                 // right chunk: group start, kNone if none
+    __shared__ uint16_t s_rge[kRChunk];                 // right chunk: group end
+    __shared__ uint16_t s_rrk[kRChunk];                 // right chunk: rank within its group
+    __shared__ uint16_t s_rperm[kRChunk];               // right chunk in group order
+    __shared__ uint32_t s_rcnt[kJoinCap];                // right records per group start
     __shared__ uint32_t s_w4[4];
     __shared__ uint64_t s_s4[4];
     __shared__ uint32_t s_gmax;
@@ -656,18 +665,6 @@ __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__
         return;
     }
     const int t = threadIdx.x;
-    // Right keys and rows are loaded first and consumed after the build.
-    int64_t rk[kPre];
-    uint32_t rv[kPre][WV];
-#pragma unroll
-    for (int e = 0; e < kPre; ++e) {
-        const uint32_t j = t + 256 * e;
-        if (j < nr) {
-            rk[e] = rkey(p, R[r0 + j]);
-#pragma unroll
-            for (int w = 0; w < WV; ++w) rv[e][w] = R[r0 + j].vec[w];
-        }
-    }
     uint32_t slots = 256;
     while (slots < 2 * nl) slots <<= 1;
     const uint32_t smask = slots - 1;
@@ -751,48 +748,101 @@ __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__
         s_grp[pos] = (uint16_t)i;
     }
     __syncthreads();
-    uint64_t hits = 0;
-    auto probe = [&](const int64_t key, const uint32_t *v, uint32_t rj) {
-        // After the scan an empty slot keeps head 0xFFFF but its low half
-        // holds a running offset, so emptiness is read from the head half.
-        uint32_t h = key_hash(key) & smask;
-        for (;;) {
-            const uint32_t w = s_tab[h];
-            if ((w >> 16) == 0xFFFFu) return;
-            if (s_key[w >> 16] == key) break;
-            h = (h + 1) & smask;
-        }
-        const uint32_t ge = s_tab[h] & 0xFFFFu, gs = h ? (s_tab[h - 1] & 0xFFFFu) : 0u;
-        hits += ge - gs;
-        if (W == 0) {
-            atomicAdd((unsigned long long *)&scal[S_NSOL], (unsigned long long)(ge - gs));
-            for (uint32_t q = gs; q < ge; ++q) {
-                if (scal[S_STORED] >= cap) break;
-                emit_solution(sol, cap, &scal[S_STORED], half_mask(p, qs, 0, L[l0 + s_grp[q]].hdr),
-                              half_mask(p, qs, 1, R[r0 + rj].hdr));
-            }
-        } else {
-            for (uint32_t q = gs; q < ge; ++q) {
+    {   // left rows into group order
+        constexpr int kLU = (kJoinCap + 255) / 256;
+        uint32_t tmp[kLU][WV];
+#pragma unroll
+        for (int u = 0; u < kLU; ++u) {
+            const uint32_t q = t + 256 * u;
+            if (q < nl) {
                 const uint32_t li = s_grp[q];
-                bool ok = true;
 #pragma unroll
-                for (int w = 0; w < WV; ++w) ok = ok && (s_vec[w][li] == v[w]);
-                if (ok)
-                    emit_solution(sol, cap, &scal[S_NSOL], half_mask(p, qs, 0, L[l0 + li].hdr),
-                                  half_mask(p, qs, 1, R[r0 + rj].hdr));
+                for (int w = 0; w < WV; ++w) tmp[u][w] = s_vec[w][li];
             }
         }
-    };
+        __syncthreads();
 #pragma unroll
-    for (int e = 0; e < kPre; ++e) {
-        const uint32_t j = t + 256 * e;
-        if (j < nr) probe(rk[e], rv[e], j);
+        for (int u = 0; u < kLU; ++u) {
+            const uint32_t q = t + 256 * u;
+            if (q < nl) {
+#pragma unroll
+                for (int w = 0; w < WV; ++w) s_vec[w][q] = tmp[u][w];
+            }
+        }
     }
-    for (uint32_t j = t + 256 * kPre; j < nr; j += 256) {
-        uint32_t v[WV];
+    uint64_t hits = 0;
+    for (uint32_t rc0 = 0; rc0 < nr; rc0 += kRChunk) {
+        const uint32_t n = min(kRChunk, nr - rc0);
+        for (uint32_t q = t; q < (uint32_t)kJoinCap; q += 256) s_rcnt[q] = 0;
+        __syncthreads();                                // also: s_vec reordered, last chunk done
+        for (uint32_t j = t; j < n; j += 256) {
+            const int64_t key = rkey(p, R[r0 + rc0 + j]);
+            // After the scan an empty slot keeps head 0xFFFF but its low half
+            // holds a running offset, so emptiness is read from the head half.
+            uint32_t h = key_hash(key) & smask;
+            uint32_t gs = kNone, ge = 0;
+            for (;;) {
+                const uint32_t w = s_tab[h];
+                if ((w >> 16) == 0xFFFFu) break;
+                if (s_key[w >> 16] == key) {
+                    ge = w & 0xFFFFu;
+                    gs = h ? (s_tab[h - 1] & 0xFFFFu) : 0u;
+                    break;
+                }
+                h = (h + 1) & smask;
+            }
+            s_rgs[j] = (uint16_t)gs;
+            s_rge[j] = (uint16_t)ge;
+            if (gs != kNone) {
+                hits += ge - gs;
+                s_rrk[j] = (uint16_t)atomicAdd(&s_rcnt[gs], 1u);
+            }
+        }
+        __syncthreads();
+        const uint32_t nm = block_excl_scan_rt<uint32_t>(s_rcnt, kJoinCap, s_w4);
+        for (uint32_t j = t; j < n; j += 256)
+            if (s_rgs[j] != kNone) s_rperm[s_rcnt[s_rgs[j]] + s_rrk[j]] = (uint16_t)j;
+        __syncthreads();
+        for (uint32_t o = t; o < nm; o += 256) {
+            const uint32_t j = s_rperm[o];
+            const uint32_t gs = s_rgs[j], ge = s_rge[j];
+            const uint32_t rj = rc0 + j;
+            if (W == 0) {
+                atomicAdd((unsigned long long *)&scal[S_NSOL], (unsigned long long)(ge - gs));
+                for (uint32_t q = gs; q < ge; ++q) {
+                    if (scal[S_STORED] >= cap) break;
+                    emit_solution(sol, cap, &scal[S_STORED],
+                                  half_mask(p, qs, 0, L[l0 + s_grp[q]].hdr),
+                                  half_mask(p, qs, 1, R[r0 + rj].hdr));
+                }
+            } else {
+                uint32_t v[WV];
 #pragma unroll
-        for (int w = 0; w < WV; ++w) v[w] = R[r0 + j].vec[w];
-        probe(rkey(p, R[r0 + j]), v, j);
+                for (int w = 0; w < WV; ++w) v[w] = R[r0 + rj].vec[w];
+                // Eight first words in flight per step; the rest of a word
+                // vector is read only where the first word matches.
+                for (uint32_t q0 = gs; q0 < ge; q0 += 8) {
+                    uint32_t x[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) x[u] = s_vec[0][q0 + u];   // padded past nl
+                    uint32_t m = 0;
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        m |= (uint32_t)(x[u] == v[0] && q0 + u < ge) << u;
+                    while (m) {
+                        const uint32_t q = q0 + __builtin_ctz(m);
+                        m &= m - 1;
+                        bool ok = true;
+#pragma unroll
+                        for (int w = 1; w < WV; ++w) ok = ok && (s_vec[w][q] == v[w]);
+                        if (ok)
+                            emit_solution(sol, cap, &scal[S_NSOL],
+                                          half_mask(p, qs, 0, L[l0 + s_grp[q]].hdr),
+                                          half_mask(p, qs, 1, R[r0 + rj].hdr));
+                    }
+                }
+            }
+        }
     }
     const uint64_t tot = block_sum_u64(hits, s_s4);
     if (t == 0) add_u128(&scal[S_H_LO], &scal[S_H_HI], tot);
@@ -1378,17 +1428,22 @@ static hipError_t staged_impl(const Plan &p, const DevBufs &b, int64_t idx0, int
     const uint64_t T = (uint64_t)1 << p.log2T;
     const uint64_t avg = std::max<uint64_t>(1, std::min((uint64_t)p.Q[1], (uint64_t)p.Q[3]) / T);
     const int per = avg >= 8 ? 1 : avg >= 4 ? 2 : 4;   // outer elements per thread per chunk
-    const bool small_f = (1 << p.log2F) <= 1024;        // smaller LDS, more work-groups per CU
+    // LDS for the per-bucket cursors is sized to F: more work-groups per CU.
+    const int F = 1 << p.log2F;
     dim3 grid((uint32_t)K * p.parts, 2);
 #define MSP_STAGED(PERV, MF)                                                                    \
     hipLaunchKernelGGL((k_scatter_staged<W, PERV, MF>), grid, dim3(256), 0, st, p,              \
                        (const QRec<W> *)b.qsrt[0], (const QRec<W> *)b.qsrt[1], b.qcnt[1],       \
                        (const QRec<W> *)b.qsrt[2], (const QRec<W> *)b.qsrt[3], b.qcnt[3],       \
                        b.off[0], b.off[1], (Rec<W> *)b.rec[0], (Rec<W> *)b.rec[1], idx0)
-    if (small_f) {
+    if (F <= 1024) {
         if (per == 1) MSP_STAGED(1, 1024);
         else if (per == 2) MSP_STAGED(2, 1024);
         else MSP_STAGED(4, 1024);
+    } else if (F <= 2048) {
+        if (per == 1) MSP_STAGED(1, 2048);
+        else if (per == 2) MSP_STAGED(2, 2048);
+        else MSP_STAGED(4, 2048);
     } else {
         if (per == 1) MSP_STAGED(1, kMaxFine);
         else if (per == 2) MSP_STAGED(2, kMaxFine);
