@@ -73,6 +73,13 @@ typedef struct {
                                  the solutions then cover the windows processed        */
     int32_t  join_variant;    /* bucket join: 0 = per-slot chains (groups of ~1),
                                  1 = contiguous key groups (groups of ~5-250)          */
+    int32_t  verify_join;     /* 1: with exact buckets (each bucket one key value),
+                                 decide every equal-key run pair by an exact hash join
+                                 on the packed non-key rows instead of checking its
+                                 |G_L||G_R| pairs one by one (the sort/search check of
+                                 Algorithms 3-4 with an exact key in place of a
+                                 hash).  Same H, |S| and solutions; no effect with
+                                 hash buckets or when every row is a key row       */
 } msp_opts;
 
 /* Per-solve statistics; phase times are measured with HIP events on the
@@ -95,7 +102,7 @@ typedef struct {
     int32_t  exact_buckets;   /* 1: each bucket holds one key value                  */
     int32_t  words;           /* 32-bit words of packed non-key rows                 */
     int32_t  complete;        /* 1: every residue window was processed               */
-    int32_t  reserved;
+    int32_t  vector_join;     /* 1: equal-key runs were decided by the vector join   */
     uint64_t windows_total;   /* residue windows of the whole (sliced) solve         */
 } msp_stats_t;
 

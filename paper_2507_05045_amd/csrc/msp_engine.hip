@@ -53,6 +53,7 @@ struct Sizes {
     uint64_t o_qraw[4], o_qsrt[4], o_qcnt[4], o_qcur[4], o_cnt[2], o_off[2], o_rec[2];
     uint64_t o_runs, o_tiles, o_sol, o_scal, o_scan, scan_bytes, o_colw, o_rows;
     uint64_t o_iruns, o_itiles, o_idx, n_iruns, o_heavy, idx_n;
+    uint64_t o_vtab, vtab_slots;
 };
 
 struct Prepared {
@@ -179,6 +180,8 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
     p.slice_res = o.slice_res;
     if (o.join_variant < 0 || o.join_variant > 1) return MSP_E_INVALID;
     p.join_grouped = o.join_variant;
+    if (o.verify_join < 0 || o.verify_join > 1) return MSP_E_INVALID;
+    p.vjoin = (o.verify_join && p.exact && p.W > 0) ? 1 : 0;
     const uint64_t T = (uint64_t)1 << log2T;
     if (o.slice_mod > 0) {
         p.kstep = (int64_t)std::min<uint64_t>((uint64_t)o.slice_mod, T);
@@ -247,6 +250,11 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
         z.o_itiles = take((nI + 1) * 4);
         z.o_idx = take(idx_n * 4);
         z.o_heavy = take(p.exact ? 4 : kw * F * 4);
+        // Vector join table: at most half full, so every probe ends.
+        z.vtab_slots = 1;
+        if (p.vjoin)
+            while (z.vtab_slots < 2 * cap_rec) z.vtab_slots <<= 1;
+        z.o_vtab = take(z.vtab_slots * 4);
         z.o_sol = take(z.sol_cap * 16);
         z.o_scal = take(S_COUNT * 8);
         z.scan_bytes = scan_tmp_bytes(std::max<uint64_t>(std::max<uint64_t>(T + 1, ncnt),
@@ -406,6 +414,8 @@ void job_carve(Job &j) {
     j.b.itiles = (uint32_t *)(ws + z.o_itiles);
     j.b.idx = (uint32_t *)(ws + z.o_idx);
     j.b.heavy = (uint32_t *)(ws + z.o_heavy);
+    j.b.vtab = (uint32_t *)(ws + z.o_vtab);
+    j.b.vtab_mask = (uint32_t)(z.vtab_slots - 1);
     j.b.iruns_cap = z.n_iruns;
     j.b.idx_cap = z.idx_n;
     j.b.sol = (uint64_t *)(ws + z.o_sol);
@@ -508,7 +518,14 @@ int job_step(Job &j) {
             if (j.next == A_JOINED) {
                 j.st.ms_scatter += ev_ms(j.ev[E_S0], j.ev[E_S1]);
                 j.st.ms_join += ev_ms(j.ev[E_S1], j.ev[E_S2]);
-                if (nruns || niruns) {
+                if (p.vjoin && nruns) {
+                    // Exact runs: one hash join on the packed rows decides them all.
+                    JCHK(hipEventRecord(j.ev[E_V0], j.s));
+                    JCHK(launch_vector_join(p, j.b, nruns, z.sol_cap, j.s));
+                    JCHK(hipEventRecord(j.ev[E_V1], j.s));
+                    j.verify_pending = true;
+                    j.st.verify_launches += 1;
+                } else if (nruns || niruns) {
                     if (nruns) {
                         JCHK(launch_tile_counts(p, j.b, nruns, p.exact ? 0 : 1, j.s));
                         JCHK(scan_u32(j.b.tiles, j.b.tiles, nruns, &j.b.scal[S_TOT_TILES],
@@ -621,6 +638,7 @@ void job_init_stats(Job &j) {
     j.st.exact_buckets = p.exact;
     j.st.words = p.W;
     j.st.record_bytes = rec_bytes(p.W);
+    j.st.vector_join = p.vjoin;
     j.st.complete = 1;
     j.st.windows_total = (j.P.z.ncells + j.P.z.kwin - 1) / std::max<uint64_t>(j.P.z.kwin, 1);
 }

@@ -26,6 +26,7 @@ struct Plan {
     int32_t exact;                   // 1: M > K_d, each bucket is one key value
     int32_t hsh;                     // qa + qb: shift of the key in Rec::hdr
     int32_t join_grouped;            // light join variant: 0 chains, 1 contiguous groups
+    int32_t vjoin;                   // exact runs decided by the vector hash join
     int64_t Kd;                      // target key
     int64_t slice_mod, slice_res;    // slice on the left key (0 = none)
     int64_t kstep, kfirst;           // cell k = kfirst + idx * kstep
@@ -77,6 +78,8 @@ struct DevBufs {
     uint32_t *idx;                   // record indices of large equal-key groups
     uint32_t *heavy;                 // buckets deferred to the heavy join
     uint64_t iruns_cap, idx_cap;     // capacities of iruns and idx
+    uint32_t *vtab;                  // vector join table: left record index or ~0
+    uint32_t vtab_mask;              // slots - 1 (a power of two, >= 2x the left records)
     uint64_t *sol;                   // solutions: (maskL, maskR) pairs
     uint64_t *scal;                  // scalars (see Scal)
     void *scan_tmp;                  // scratch of the device-wide scan
@@ -101,6 +104,9 @@ hipError_t launch_hash_join(const Plan &p, const DevBufs &b, int32_t K, uint64_t
 // mode 0: exact run pairs, 1: key-checked run pairs, 2: indexed run pairs.
 hipError_t launch_verify(const Plan &p, const DevBufs &b, uint32_t nruns, uint32_t ntiles,
                          uint64_t sol_cap, int mode, hipStream_t st);
+// Exact-bucket runs decided by a hash join on the packed non-key rows.
+hipError_t launch_vector_join(const Plan &p, const DevBufs &b, uint32_t nruns, uint64_t sol_cap,
+                              hipStream_t st);
 hipError_t launch_tile_counts(const Plan &p, const DevBufs &b, uint32_t nruns, int mode,
                               hipStream_t st);
 // Exclusive scan of n uint32 values (out[n] = total; out may equal in);

@@ -491,6 +491,82 @@ __device__ __forceinline__ uint32_t key_hash(int64_t k) {
     return (uint32_t)(((uint64_t)k * 0x9E3779B97F4A7C15ull) >> 40);
 }
 
+// ---------------------------------------------------------------------------
+// Vector join of exact-bucket runs.  Within a run every left and right record
+// has the same key, so a pair is a solution exactly when the packed non-key
+// rows agree word for word (the right side holds d' - rows, 0xFFFF where
+// negative, which no left sum reaches).  Algorithms 3-4 decide such pairs by
+// encoding the partial vectors, sorting and searching; here the encoding is
+// the exact packed vector and the search a hash table: the left records of
+// every run go into one open-addressing table keyed by (run, vector), and
+// each right record probes it once.  Cost O(|G_L| + |G_R|) per run instead of
+// |G_L| |G_R| compares; H is the sum of |G_L| |G_R| as before.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kVEmpty = 0xFFFFFFFFu;
+
+template <int W>
+__device__ __forceinline__ uint32_t vj_hash(uint32_t run, const uint32_t *v) {
+    uint32_t h = run * 0x9E3779B1u + 0x7F4A7C15u;
+#pragma unroll
+    for (int w = 0; w < (W > 0 ? W : 1); ++w) {
+        h = (h ^ v[w]) * 0x85EBCA77u;
+        h ^= h >> 13;
+    }
+    h *= 0xC2B2AE35u;
+    return h ^ (h >> 16);
+}
+
+template <int W>
+__global__ __launch_bounds__(256) void k_vjoin_insert(const RunPair *__restrict__ runs,
+                                                      uint32_t nruns,
+                                                      const Rec<W> *__restrict__ L,
+                                                      uint32_t *tab, uint32_t mask) {
+    constexpr int WV = W > 0 ? W : 1;
+    for (uint32_t ri = blockIdx.x; ri < nruns; ri += gridDim.x) {
+        const RunPair r = runs[ri];
+        for (uint32_t i = blockIdx.y * 256 + threadIdx.x; i < r.nl; i += 256 * gridDim.y) {
+            const uint32_t li = r.l0 + i;
+            uint32_t v[WV];
+#pragma unroll
+            for (int w = 0; w < WV; ++w) v[w] = L[li].vec[w];
+            uint32_t h = vj_hash<W>(ri, v) & mask;
+            // The table is at most half full: an empty slot is always reached.
+            while (atomicCAS(&tab[h], kVEmpty, li) != kVEmpty) h = (h + 1) & mask;
+        }
+    }
+}
+
+template <int W>
+__global__ __launch_bounds__(256) void k_vjoin_probe(Plan p, const RunPair *__restrict__ runs,
+                                                     uint32_t nruns,
+                                                     const Rec<W> *__restrict__ L,
+                                                     const Rec<W> *__restrict__ R,
+                                                     const uint32_t *__restrict__ tab,
+                                                     uint32_t mask, uint64_t *scal, uint64_t *sol,
+                                                     uint64_t cap, QPtrs<W> qs) {
+    constexpr int WV = W > 0 ? W : 1;
+    for (uint32_t ri = blockIdx.x; ri < nruns; ri += gridDim.x) {
+        const RunPair r = runs[ri];
+        for (uint32_t j = blockIdx.y * 256 + threadIdx.x; j < r.nr; j += 256 * gridDim.y) {
+            const uint32_t rj = r.r0 + j;
+            uint32_t v[WV];
+#pragma unroll
+            for (int w = 0; w < WV; ++w) v[w] = R[rj].vec[w];
+            for (uint32_t h = vj_hash<W>(ri, v) & mask;; h = (h + 1) & mask) {
+                const uint32_t e = tab[h];
+                if (e == kVEmpty) break;
+                if (e - r.l0 >= r.nl) continue;          // another run's record
+                bool ok = true;
+#pragma unroll
+                for (int w = 0; w < WV; ++w) ok = ok && (L[e].vec[w] == v[w]);
+                if (ok)
+                    emit_solution(sol, cap, &scal[S_NSOL], half_mask(p, qs, 0, L[e].hdr),
+                                  half_mask(p, qs, 1, R[rj].hdr));
+            }
+        }
+    }
+}
+
 // Light join of one bucket whose equal-key groups are small: left records
 // are pushed onto per-slot chains in LDS (one CAS per record, the slot word
 // packs chain head and length); each right record walks its slot's chain.
@@ -1522,6 +1598,31 @@ bool verify_cmpx() {
         return !(e && atoi(e) == 0);
     }();
     return on;
+}
+
+template <int W>
+static hipError_t vjoin_impl(const Plan &p, const DevBufs &b, uint32_t nruns, uint64_t cap,
+                             hipStream_t st) {
+    const uint64_t slots = (uint64_t)b.vtab_mask + 1;
+    hipError_t e = hipMemsetAsync(b.vtab, 0xFF, slots * 4, st);
+    if (e != hipSuccess) return e;
+    // Blocks stride over runs; the second grid dimension splits long runs.
+    const dim3 grid(std::min<uint32_t>(nruns, 4096), 16);
+    hipLaunchKernelGGL(k_vjoin_insert<W>, grid, dim3(256), 0, st, b.runs, nruns,
+                       (const Rec<W> *)b.rec[0], b.vtab, b.vtab_mask);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_vjoin_probe<W>, grid, dim3(256), 0, st, p, b.runs, nruns,
+                       (const Rec<W> *)b.rec[0], (const Rec<W> *)b.rec[1], b.vtab, b.vtab_mask,
+                       b.scal, b.sol, cap, sorted_quarters<W>(b));
+    return hipGetLastError();
+}
+
+hipError_t launch_vector_join(const Plan &p, const DevBufs &b, uint32_t nruns, uint64_t cap,
+                              hipStream_t st) {
+    if (nruns == 0) return hipSuccess;
+    MSP_DISPATCH_W(p.W, return vjoin_impl<WW>(p, b, nruns, cap, st));
+    return hipSuccess;
 }
 
 hipError_t launch_tile_counts(const Plan &, const DevBufs &b, uint32_t nruns, int mode,

@@ -66,9 +66,10 @@ def make_instance(m: int, n: int, seed: int, planted: bool = False, K: int = 100
     same generator so the result stays a function of ``seed``.
     """
     A = make_matrix(m, n, seed, K)
+    kk = "" if K == 100 else f"_K{K}"
     if not planted:
         d = (A.astype(np.int64).sum(axis=1) // 2).astype(np.int32)
-        return Instance(A, d, f"msp_{m}_{n}_s{seed}", seed, None, key_rows)
+        return Instance(A, d, f"msp_{m}_{n}{kk}_s{seed}", seed, None, key_rows)
     rng = np.random.default_rng(seed + PLANT_OFFSET)
     for _ in range(max_tries):
         x = rng.integers(0, 2, size=n).astype(np.uint8)
@@ -77,7 +78,7 @@ def make_instance(m: int, n: int, seed: int, planted: bool = False, K: int = 100
     else:
         raise RuntimeError("no planted vector satisfied the predicate")
     d = (A.astype(np.int64) @ x.astype(np.int64)).astype(np.int32)
-    return Instance(A, d, f"msp_{m}_{n}_s{seed}_planted", seed, x, key_rows)
+    return Instance(A, d, f"msp_{m}_{n}{kk}_s{seed}_planted", seed, x, key_rows)
 
 
 def stream_instances(count: int = 512, base_seed: int = 1000) -> List[Instance]:

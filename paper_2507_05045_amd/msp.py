@@ -36,7 +36,8 @@ class msp_opts(C.Structure):
                 ("parts", C.c_int32), ("slice_mod", C.c_int64), ("slice_res", C.c_int64),
                 ("max_solutions", C.c_uint64), ("window_records", C.c_uint64),
                 ("workspace", C.c_void_p), ("workspace_bytes", C.c_uint64),
-                ("stream", C.c_void_p), ("first_only", C.c_int32), ("join_variant", C.c_int32)]
+                ("stream", C.c_void_p), ("first_only", C.c_int32), ("join_variant", C.c_int32),
+                ("verify_join", C.c_int32)]
 
 
 class msp_stats_t(C.Structure):
@@ -47,7 +48,7 @@ class msp_stats_t(C.Structure):
                 ("verify_launches", C.c_uint64), ("verify_pairs", C.c_uint64),
                 ("record_bytes", C.c_uint64), ("log2_m", C.c_int32), ("log2_cells", C.c_int32),
                 ("parts", C.c_int32), ("key_rows", C.c_int32), ("exact_buckets", C.c_int32),
-                ("words", C.c_int32), ("complete", C.c_int32), ("reserved", C.c_int32),
+                ("words", C.c_int32), ("complete", C.c_int32), ("vector_join", C.c_int32),
                 ("windows_total", C.c_uint64)]
 
 

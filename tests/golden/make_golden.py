@@ -22,8 +22,8 @@ from paper_2507_05045_amd.inputs import make_instance  # noqa: E402
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_configs.json")
 
 
-def entry(inst, r, res, slice_mod=0, slice_res=0, routine=""):
-    return dict(name=inst.name, m=inst.m, n=inst.n, seed=inst.seed,
+def entry(inst, r, res, slice_mod=0, slice_res=0, routine="", K=100):
+    return dict(name=inst.name, m=inst.m, n=inst.n, K=K, seed=inst.seed,
                 planted=inst.planted is not None, key_rows=r, slice_mod=slice_mod,
                 slice_res=slice_res, H=str(res.H), nsol=res.nsol,
                 solutions=["".join(str(int(v)) for v in s) for s in res.solutions],
@@ -60,6 +60,24 @@ def main():
         rho = O.left_key(inst.A, inst.d, inst.planted, 4) % mod
         res = O.mitm(inst.A, inst.d, 4, lm, rho, rho + 1)
         out.append(entry(inst, 4, res, mod, rho, routine=f"mitm mod 2^{lm}"))
+        print(inst.name, rho, out[-1]["H"], out[-1]["nsol"], f"{time.time() - t0:.1f}s", flush=True)
+    # Coefficient-range sweep (Section 4 runs K = 50, 100, 200): the (6,50)
+    # pair solved whole, (8,70) seed 0 and its planted twin sampled.
+    for K in (50, 200):
+        for planted in (False, True):
+            inst = make_instance(6, 50, 0, planted=planted, K=K)
+            out.append(entry(inst, 1, O.ss_heap(inst.A, inst.d, 1), routine="ss_heap", K=K))
+            print(inst.name, out[-1]["H"], out[-1]["nsol"], f"{time.time() - t0:.1f}s", flush=True)
+        lm = 20
+        mod = 1 << lm
+        inst = make_instance(8, 70, 0, K=K)
+        res = O.mitm(inst.A, inst.d, 4, lm, 12345, 12346)
+        out.append(entry(inst, 4, res, mod, 12345, routine=f"mitm mod 2^{lm}", K=K))
+        print(inst.name, 12345, out[-1]["H"], out[-1]["nsol"], f"{time.time() - t0:.1f}s", flush=True)
+        inst = make_instance(8, 70, 0, planted=True, K=K)
+        rho = O.left_key(inst.A, inst.d, inst.planted, 4) % mod
+        res = O.mitm(inst.A, inst.d, 4, lm, rho, rho + 1)
+        out.append(entry(inst, 4, res, mod, rho, routine=f"mitm mod 2^{lm}", K=K))
         print(inst.name, rho, out[-1]["H"], out[-1]["nsol"], f"{time.time() - t0:.1f}s", flush=True)
     with open(OUT, "w") as f:
         json.dump(out, f, indent=1)

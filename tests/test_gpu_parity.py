@@ -61,6 +61,9 @@ def test_small_random_vs_brute_force(case):
         say("case", case, "seed", seed)
         ref = O.brute(inst.A, inst.d, key_rows=case["r"])
         same(gsolve(inst.A, inst.d, key_rows=case["r"]), ref, f"default {case} {seed}")
+        # exact buckets decided by the vector join (no effect in hash mode)
+        same(gsolve(inst.A, inst.d, key_rows=case["r"], verify_join=1), ref,
+             f"vector join {case} {seed}")
         # force hash buckets (modulus below K_d) and a few cell layouts
         for lm, lc, parts, jv in [(3, 1, 1, 0), (5, 2, 3, 1), (6, 6, 2, 0), (6, 3, 2, 1)]:
             g = gsolve(inst.A, inst.d, key_rows=case["r"], log2_m=lm, log2_cells=lc, parts=parts,
@@ -139,7 +142,8 @@ def _golden_instance(e):
     if e["planted"] and (e["m"], e["n"]) == (10, 90):
         probe = make_instance(10, 90, 0)
         acc = lambda x: O.left_key(probe.A, probe.d, x, 4) % 64 == 0  # noqa: E731
-    return make_instance(e["m"], e["n"], e["seed"], planted=e["planted"], accept=acc)
+    return make_instance(e["m"], e["n"], e["seed"], planted=e["planted"], accept=acc,
+                         K=e.get("K", 100))
 
 
 def _golden_result(e, n):
@@ -147,11 +151,12 @@ def _golden_result(e, n):
     return O.OracleResult(int(e["H"]), e["nsol"], sols)
 
 
-@pytest.mark.parametrize("cfg", ["4_30", "6_50"])
+@pytest.mark.parametrize("cfg", ["4_30", "6_50", "6_50_K50", "6_50_K200"])
 def test_full_configs_vs_oracle(cfg):
-    m, n = map(int, cfg.split("_"))
+    m, n = map(int, cfg.split("_")[:2])
+    K = int(cfg.split("_K")[1]) if "_K" in cfg else 100
     for e in _golden():
-        if (e["m"], e["n"]) != (m, n):
+        if (e["m"], e["n"], e.get("K", 100)) != (m, n, K):
             continue
         inst = _golden_instance(e)
         say("config", e["name"])
@@ -159,13 +164,16 @@ def test_full_configs_vs_oracle(cfg):
         same(g, _golden_result(e, n), e["name"])
         if inst.planted is not None:
             assert any(np.array_equal(s, inst.planted) for s in g.solutions)
+        v = gsolve(inst.A, inst.d, key_rows=e["key_rows"], verify_join=1)
+        same(v, _golden_result(e, n), e["name"] + " vector join")
 
 
-@pytest.mark.parametrize("cfg", ["8_70", "9_80", "10_90"])
+@pytest.mark.parametrize("cfg", ["8_70", "9_80", "10_90", "8_70_K50", "8_70_K200"])
 def test_large_configs_sampled_residue_classes(cfg):
-    m, n = map(int, cfg.split("_"))
+    m, n = map(int, cfg.split("_")[:2])
+    K = int(cfg.split("_K")[1]) if "_K" in cfg else 100
     for e in _golden():
-        if (e["m"], e["n"]) != (m, n):
+        if (e["m"], e["n"], e.get("K", 100)) != (m, n, K):
             continue
         inst = _golden_instance(e)
         say("sampled", e["name"], e["slice_mod"], e["slice_res"])
@@ -212,6 +220,24 @@ def test_grouped_join_right_chunks_vs_oracle(lm):
         for lc in (4, 6):
             same(gsolve(inst.A, inst.d, key_rows=2, log2_m=lm, log2_cells=lc, join_variant=1),
                  ref, f"{inst.name} M=2^{lm} T=2^{lc} grouped")
+
+
+def test_vector_join_ties_and_windows():
+    # Few distinct values: many left records per run share one packed vector,
+    # so a probe walks several equal entries; split windows reuse the table.
+    from paper_2507_05045_amd import msp
+    for seed in range(3):
+        inst = random_small(5, 22, 700 + seed, K=4, planted=True)
+        ref = O.brute(inst.A, inst.d, key_rows=1)
+        say("vector join ties", seed, ref.H, ref.nsol)
+        for wr in (0, 1 << 12):
+            ctx = msp.Context(inst.A, inst.d)
+            ctx.solve(key_rows=1, verify_join=1, window_records=wr)
+            st = ctx.stats()
+            assert st["exact_buckets"] == 1 and st["vector_join"] == 1
+            same(O.OracleResult(ctx.hits(), ctx.num_solutions(), ctx.solutions()), ref,
+                 f"seed {seed} window_records={wr}")
+            ctx.close()
 
 
 def test_first_solution_mode():
