@@ -699,11 +699,10 @@ __global__ __launch_bounds__(256) void k_join_light(Plan p, const uint32_t *__re
 
 // Light join variant for buckets whose equal-key groups hold a few to a
 // few hundred records: linear-probe table with one representative per
-// distinct key, counts scanned into contiguous groups.  The left rows are
-// then laid out in group order and the right records of a chunk are
-// counting-sorted by group, so that neighbouring lanes walk the same group:
-// the left words they compare are LDS broadcasts and the loop trip counts
-// agree across most of a wave.
+// distinct key, counts scanned into contiguous groups, and the left rows laid
+// out in group order.  Each right record then walks its group with eight
+// independent LDS loads of first words in flight per step; the other words
+// are read only where the first matches.
 template <int W>
 __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__restrict__ offL,
                                                    const uint32_t *__restrict__ offR,
@@ -715,17 +714,11 @@ __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__
     constexpr uint32_t kEmpty = 0xFFFF0000u;
     constexpr int WV = W > 0 ? W : 1;
     constexpr uint32_t kNone = 0xFFFFu;
-    constexpr uint32_t kRChunk = 1024;                   // right records sorted per pass
     __shared__ int64_t s_key[kJoinCap];
     __shared__ uint32_t s_vec[WV][kJoinCap + 8];         // left rows: by left index, then by group
     __shared__ uint32_t s_tab[kJoinSlots];
     __shared__ uint16_t s_slot[kJoinCap];
     __shared__ uint16_t s_grp[kJoinCap];                 // group order -> left index
-    __shared__ uint16_t s_rgs[kRChunk];                 // right chunk: group start, kNone if none
-    __shared__ uint16_t s_rge[kRChunk];                 // right chunk: group end
-    __shared__ uint16_t s_rrk[kRChunk];                 // right chunk: rank within its group
-    __shared__ uint16_t s_rperm[kRChunk];               // right chunk in group order
-    __shared__ uint32_t s_rcnt[kJoinCap];                // right records per group start
     __shared__ uint32_t s_w4[4];
     __shared__ uint64_t s_s4[4];
     __shared__ uint32_t s_gmax;
@@ -847,75 +840,52 @@ __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__
         }
     }
     uint64_t hits = 0;
-    for (uint32_t rc0 = 0; rc0 < nr; rc0 += kRChunk) {
-        const uint32_t n = min(kRChunk, nr - rc0);
-        for (uint32_t q = t; q < (uint32_t)kJoinCap; q += 256) s_rcnt[q] = 0;
-        __syncthreads();                                // also: s_vec reordered, last chunk done
-        for (uint32_t j = t; j < n; j += 256) {
-            const int64_t key = rkey(p, R[r0 + rc0 + j]);
-            // After the scan an empty slot keeps head 0xFFFF but its low half
-            // holds a running offset, so emptiness is read from the head half.
-            uint32_t h = key_hash(key) & smask;
-            uint32_t gs = kNone, ge = 0;
-            for (;;) {
-                const uint32_t w = s_tab[h];
-                if ((w >> 16) == 0xFFFFu) break;
-                if (s_key[w >> 16] == key) {
-                    ge = w & 0xFFFFu;
-                    gs = h ? (s_tab[h - 1] & 0xFFFFu) : 0u;
-                    break;
-                }
-                h = (h + 1) & smask;
+    __syncthreads();                                    // left rows reordered
+    for (uint32_t rj = t; rj < nr; rj += 256) {
+        const int64_t key = rkey(p, R[r0 + rj]);
+        // After the scan an empty slot keeps head 0xFFFF but its low half
+        // holds a running offset, so emptiness is read from the head half.
+        uint32_t h = key_hash(key) & smask;
+        uint32_t gs = kNone, ge = 0;
+        for (;;) {
+            const uint32_t w = s_tab[h];
+            if ((w >> 16) == 0xFFFFu) break;
+            if (s_key[w >> 16] == key) {
+                ge = w & 0xFFFFu;
+                gs = h ? (s_tab[h - 1] & 0xFFFFu) : 0u;
+                break;
             }
-            s_rgs[j] = (uint16_t)gs;
-            s_rge[j] = (uint16_t)ge;
-            if (gs != kNone) {
-                hits += ge - gs;
-                s_rrk[j] = (uint16_t)atomicAdd(&s_rcnt[gs], 1u);
-            }
+            h = (h + 1) & smask;
         }
-        __syncthreads();
-        const uint32_t nm = block_excl_scan_rt<uint32_t>(s_rcnt, kJoinCap, s_w4);
-        for (uint32_t j = t; j < n; j += 256)
-            if (s_rgs[j] != kNone) s_rperm[s_rcnt[s_rgs[j]] + s_rrk[j]] = (uint16_t)j;
-        __syncthreads();
-        for (uint32_t o = t; o < nm; o += 256) {
-            const uint32_t j = s_rperm[o];
-            const uint32_t gs = s_rgs[j], ge = s_rge[j];
-            const uint32_t rj = rc0 + j;
-            if (W == 0) {
-                atomicAdd((unsigned long long *)&scal[S_NSOL], (unsigned long long)(ge - gs));
-                for (uint32_t q = gs; q < ge; ++q) {
-                    if (scal[S_STORED] >= cap) break;
-                    emit_solution(sol, cap, &scal[S_STORED],
-                                  half_mask(p, qs, 0, L[l0 + s_grp[q]].hdr),
-                                  half_mask(p, qs, 1, R[r0 + rj].hdr));
-                }
-            } else {
-                uint32_t v[WV];
+        if (gs == kNone) continue;
+        hits += ge - gs;
+        if (W == 0) {
+            atomicAdd((unsigned long long *)&scal[S_NSOL], (unsigned long long)(ge - gs));
+            for (uint32_t q = gs; q < ge; ++q) {
+                if (scal[S_STORED] >= cap) break;
+                emit_solution(sol, cap, &scal[S_STORED], half_mask(p, qs, 0, L[l0 + s_grp[q]].hdr),
+                              half_mask(p, qs, 1, R[r0 + rj].hdr));
+            }
+        } else {
+            uint32_t v[WV];
 #pragma unroll
-                for (int w = 0; w < WV; ++w) v[w] = R[r0 + rj].vec[w];
-                // Eight first words in flight per step; the rest of a word
-                // vector is read only where the first word matches.
-                for (uint32_t q0 = gs; q0 < ge; q0 += 8) {
-                    uint32_t x[8];
+            for (int w = 0; w < WV; ++w) v[w] = R[r0 + rj].vec[w];
+            for (uint32_t q0 = gs; q0 < ge; q0 += 8) {
+                uint32_t x[8];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) x[u] = s_vec[0][q0 + u];   // padded past nl
-                    uint32_t m = 0;
+                for (int u = 0; u < 8; ++u) x[u] = s_vec[0][q0 + u];
+                uint32_t m = 0;
 #pragma unroll
-                    for (int u = 0; u < 8; ++u)
-                        m |= (uint32_t)(x[u] == v[0] && q0 + u < ge) << u;
-                    while (m) {
-                        const uint32_t q = q0 + __builtin_ctz(m);
-                        m &= m - 1;
-                        bool ok = true;
+                for (int u = 0; u < 8; ++u) m |= (uint32_t)(x[u] == v[0] && q0 + u < ge) << u;
+                while (m) {
+                    const uint32_t q = q0 + __builtin_ctz(m);
+                    m &= m - 1;
+                    bool ok = true;
 #pragma unroll
-                        for (int w = 1; w < WV; ++w) ok = ok && (s_vec[w][q] == v[w]);
-                        if (ok)
-                            emit_solution(sol, cap, &scal[S_NSOL],
-                                          half_mask(p, qs, 0, L[l0 + s_grp[q]].hdr),
-                                          half_mask(p, qs, 1, R[r0 + rj].hdr));
-                    }
+                    for (int w = 1; w < WV; ++w) ok = ok && (s_vec[w][q] == v[w]);
+                    if (ok)
+                        emit_solution(sol, cap, &scal[S_NSOL], half_mask(p, qs, 0, L[l0 + s_grp[q]].hdr),
+                                      half_mask(p, qs, 1, R[r0 + rj].hdr));
                 }
             }
         }

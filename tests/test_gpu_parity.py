@@ -209,14 +209,14 @@ def test_oversized_buckets_vs_oracle(lm):
 
 
 @pytest.mark.parametrize("lm", [9, 10])
-def test_grouped_join_right_chunks_vs_oracle(lm):
-    # Buckets of several hundred to over a thousand records per side: the
-    # grouped join sorts the right side by group in chunks of 1024, so these
-    # take one or two chunks (larger left sides go to the heavy kernel).
+def test_grouped_join_mid_buckets_vs_oracle(lm):
+    # Buckets of several hundred to over a thousand records per side, with
+    # groups of many equal keys: the grouped join walks its group-ordered
+    # left rows eight at a time (larger left sides go to the heavy kernel).
     for planted in (False, True):
         inst = make_instance(5, 40, 6, planted=planted)
         ref = O.ss_heap(inst.A, inst.d, key_rows=2)
-        say("grouped chunks", inst.name, lm)
+        say("grouped mid buckets", inst.name, lm)
         for lc in (4, 6):
             same(gsolve(inst.A, inst.d, key_rows=2, log2_m=lm, log2_cells=lc, join_variant=1),
                  ref, f"{inst.name} M=2^{lm} T=2^{lc} grouped")
