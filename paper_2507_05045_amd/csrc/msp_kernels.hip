@@ -1470,10 +1470,12 @@ hipError_t launch_count(const Plan &p, const DevBufs &b, int64_t idx0, int32_t K
 template <int W>
 static hipError_t staged_impl(const Plan &p, const DevBufs &b, int64_t idx0, int32_t K,
                               hipStream_t st) {
-    // Outer elements per chunk: enough pairs to fill about one batch.
+    // Outer elements per thread per chunk: enough pairs (about Q_inner / T
+    // per outer element) to fill about one batch.
     const uint64_t T = (uint64_t)1 << p.log2T;
-    const uint64_t avg = std::max<uint64_t>(1, std::min((uint64_t)p.Q[1], (uint64_t)p.Q[3]) / T);
-    const int per = avg >= 8 ? 1 : avg >= 4 ? 2 : 4;   // outer elements per thread per chunk
+    const uint64_t qin = std::min((uint64_t)p.Q[1], (uint64_t)p.Q[3]);
+    int per = 1;
+    while (per < 16 && (uint64_t)256 * (2 * per) * qin <= (uint64_t)kStageBatch * T) per *= 2;
     // LDS for the per-bucket cursors is sized to F: more work-groups per CU.
     const int F = 1 << p.log2F;
     dim3 grid((uint32_t)K * p.parts, 2);
@@ -1482,19 +1484,22 @@ static hipError_t staged_impl(const Plan &p, const DevBufs &b, int64_t idx0, int
                        (const QRec<W> *)b.qsrt[0], (const QRec<W> *)b.qsrt[1], b.qcnt[1],       \
                        (const QRec<W> *)b.qsrt[2], (const QRec<W> *)b.qsrt[3], b.qcnt[3],       \
                        b.off[0], b.off[1], (Rec<W> *)b.rec[0], (Rec<W> *)b.rec[1], idx0)
-    if (F <= 1024) {
-        if (per == 1) MSP_STAGED(1, 1024);
-        else if (per == 2) MSP_STAGED(2, 1024);
-        else MSP_STAGED(4, 1024);
-    } else if (F <= 2048) {
-        if (per == 1) MSP_STAGED(1, 2048);
-        else if (per == 2) MSP_STAGED(2, 2048);
-        else MSP_STAGED(4, 2048);
-    } else {
-        if (per == 1) MSP_STAGED(1, kMaxFine);
-        else if (per == 2) MSP_STAGED(2, kMaxFine);
-        else MSP_STAGED(4, kMaxFine);
+#define MSP_STAGED_PER(MF)                                                                      \
+    switch (per) {                                                                              \
+        case 1: MSP_STAGED(1, MF); break;                                                       \
+        case 2: MSP_STAGED(2, MF); break;                                                       \
+        case 4: MSP_STAGED(4, MF); break;                                                       \
+        case 8: MSP_STAGED(8, MF); break;                                                       \
+        default: MSP_STAGED(16, MF); break;                                                     \
     }
+    if (F <= 1024) {
+        MSP_STAGED_PER(1024)
+    } else if (F <= 2048) {
+        MSP_STAGED_PER(2048)
+    } else {
+        MSP_STAGED_PER(kMaxFine)
+    }
+#undef MSP_STAGED_PER
 #undef MSP_STAGED
     return hipGetLastError();
 }
