@@ -274,7 +274,7 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2507_05045_amd import msp
+    from paper_2507_05045_amd import autotune, msp
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     if args.workload == "stream":
@@ -285,11 +285,14 @@ def main():
     kw = dict(key_rows=w["key_rows"], slice_mod=w["slice_mod"], slice_res=0,
               first_only=1 if args.first_solution else 0,
               verify_join=1 if args.verify_join else 0)
+    # The plan (modulus, cells, parts, join variant) the autotuner picked for
+    # each instance class; the planner's defaults where it has no entry.
+    plans = [autotune.lookup(i.A, w["key_rows"]) or {} for i in insts]
 
     def step():
         stats = []
-        for c in ctxs:
-            c.solve(**kw)
+        for c, pl in zip(ctxs, plans):
+            c.solve(**kw, **pl)
             stats.append(c.stats())
         return stats
 
@@ -364,7 +367,7 @@ def main():
         "dtype": "u16x2/i64",
         "data": "synthetic",
         "config": {"workload": w["desc"], "m": w["m"], "n": w["n"], "key_rows": w["key_rows"],
-                   "instances": len(insts), "slice_mod": w["slice_mod"]},
+                   "instances": len(insts), "slice_mod": w["slice_mod"], "plan": plans[0]},
         "hits_per_step": hits,
         "solutions": nsol,
         "first_solution": bool(args.first_solution),

@@ -71,8 +71,10 @@ typedef struct {
     int32_t  first_only;      /* 1: stop after the first residue window that yields a
                                  solution (Algorithm 2 returns the first x); H, |S| and
                                  the solutions then cover the windows processed        */
-    int32_t  join_variant;    /* bucket join: 0 = per-slot chains (groups of ~1),
-                                 1 = contiguous key groups (groups of ~5-250)          */
+    int32_t  join_variant;    /* bucket join: 0 = planner's choice (from the expected
+                                 number of equal-key records per key), 1 = per-slot
+                                 chains (groups of ~1), 2 = contiguous key groups
+                                 (groups of ~5-250)                                     */
     int32_t  verify_join;     /* 1: with exact buckets (each bucket one key value),
                                  decide every equal-key run pair by an exact hash join
                                  on the packed non-key rows instead of checking its

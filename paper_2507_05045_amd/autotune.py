@@ -98,7 +98,7 @@ def tune(A, d, key_rows: int = 1, max_seconds: float = 20.0, slice_bits: Optiona
             if c2 < max(slice_bits, 0) or c2 > m2 or m2 - c2 > 12 or c2 > 23 or m2 < 1:
                 continue
             for p2 in sorted({parts, parts * 2, parts * 4}):
-                for jv in ((0,) if base["exact_buckets"] else (0, 1)):
+                for jv in ((0,) if base["exact_buckets"] else (1, 2)):
                     cands.append(dict(log2_m=m2, log2_cells=c2, parts=min(p2, 256),
                                       join_variant=jv))
     t_end = time.time() + max_seconds
@@ -124,7 +124,7 @@ def tune(A, d, key_rows: int = 1, max_seconds: float = 20.0, slice_bits: Optiona
             best, best_t = c, dt
     ctx.close()
     if best is None:
-        best = dict(log2_m=lm, log2_cells=lc, parts=parts, join_variant=0)
+        best = dict(log2_m=lm, log2_cells=lc, parts=parts, join_variant=0)   # planner's choice
     cache = _load()
     cache[key] = {"opts": best, "slice_bits": slice_bits, "ms_slice": best_t * 1e3,
                   "default": dict(log2_m=lm, log2_cells=lc, parts=parts)}

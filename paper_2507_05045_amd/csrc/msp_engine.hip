@@ -4,6 +4,7 @@
 #include "msp_internal.h"
 
 #include <algorithm>
+#include <cmath>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -178,8 +179,24 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
     p.log2M = log2M; p.log2T = log2T; p.log2F = log2M - log2T;
     p.slice_mod = o.slice_mod;
     p.slice_res = o.slice_res;
-    if (o.join_variant < 0 || o.join_variant > 1) return MSP_E_INVALID;
-    p.join_grouped = o.join_variant;
+    if (o.join_variant < 0 || o.join_variant > 2) return MSP_E_INVALID;
+    if (o.join_variant) {
+        p.join_grouped = o.join_variant == 2 ? 1 : 0;
+    } else {
+        // Expected equal-key records per side near K_d: 2^h_L spread over the
+        // key rows' half sums, each about normal with variance sum a_ij^2 / 4
+        // over the left columns.  Groups of a few dozen favour the grouped join.
+        double lg = p.hL;
+        for (int i = 0; i < r; ++i) {
+            double s2 = 0.0;
+            for (int j = 0; j < p.hL; ++j) {
+                const double a = c->A[(size_t)i * n + j];
+                s2 += a * a / 4.0;
+            }
+            if (s2 > 0.0) lg -= 0.5 * std::log2(2.0 * 3.141592653589793 * s2);
+        }
+        p.join_grouped = lg >= std::log2(18.0) ? 1 : 0;
+    }
     if (o.verify_join < 0 || o.verify_join > 1) return MSP_E_INVALID;
     p.vjoin = (o.verify_join && p.exact && p.W > 0) ? 1 : 0;
     const uint64_t T = (uint64_t)1 << log2T;

@@ -65,7 +65,7 @@ def test_small_random_vs_brute_force(case):
         same(gsolve(inst.A, inst.d, key_rows=case["r"], verify_join=1), ref,
              f"vector join {case} {seed}")
         # force hash buckets (modulus below K_d) and a few cell layouts
-        for lm, lc, parts, jv in [(3, 1, 1, 0), (5, 2, 3, 1), (6, 6, 2, 0), (6, 3, 2, 1)]:
+        for lm, lc, parts, jv in [(3, 1, 1, 1), (5, 2, 3, 2), (6, 6, 2, 0), (6, 3, 2, 2)]:
             g = gsolve(inst.A, inst.d, key_rows=case["r"], log2_m=lm, log2_cells=lc, parts=parts,
                        join_variant=jv)
             same(g, ref, f"M=2^{lm} T=2^{lc} P={parts} join={jv} {case} {seed}")
@@ -203,7 +203,7 @@ def test_oversized_buckets_vs_oracle(lm):
         inst = make_instance(5, 40, 5, planted=planted)
         ref = O.ss_heap(inst.A, inst.d, key_rows=2)
         say("oversized", inst.name, lm)
-        for jv in (0, 1):
+        for jv in (1, 2):
             same(gsolve(inst.A, inst.d, key_rows=2, log2_m=lm, log2_cells=min(lm, 4),
                         join_variant=jv), ref, f"{inst.name} M=2^{lm} join={jv}")
 
@@ -218,7 +218,7 @@ def test_grouped_join_mid_buckets_vs_oracle(lm):
         ref = O.ss_heap(inst.A, inst.d, key_rows=2)
         say("grouped mid buckets", inst.name, lm)
         for lc in (4, 6):
-            same(gsolve(inst.A, inst.d, key_rows=2, log2_m=lm, log2_cells=lc, join_variant=1),
+            same(gsolve(inst.A, inst.d, key_rows=2, log2_m=lm, log2_cells=lc, join_variant=2),
                  ref, f"{inst.name} M=2^{lm} T=2^{lc} grouped")
 
 
