@@ -248,12 +248,13 @@ __global__ __launch_bounds__(256) void k_bucket(Plan p, const QRec<W> *__restric
     }
 }
 
-// Exclusive scan of a[0 .. n) in LDS (n a multiple of 256, at most 2048) by
-// a 256-thread block; returns the total.
-template <typename T>
-__device__ uint32_t block_excl_scan_rt(T *a, int n, uint32_t *w4) {
+// Exclusive scan of a[0 .. n) in LDS by an NT-thread block (n a multiple of
+// NT, at most 16 NT); wv holds NT / 64 wave totals.  Returns the total.
+template <typename T, int NT = 256>
+__device__ uint32_t block_excl_scan_rt(T *a, int n, uint32_t *wv) {
+    constexpr int NW = NT / 64;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int E = n >> 8;
+    const int E = n / NT;
     uint32_t loc[16];
     uint32_t s = 0;
 #pragma unroll
@@ -262,12 +263,12 @@ __device__ uint32_t block_excl_scan_rt(T *a, int n, uint32_t *w4) {
         s += loc[e];
     }
     const uint32_t inc = wave_incl_scan(s);
-    if (lane == 63) w4[wave] = inc;
+    if (lane == 63) wv[wave] = inc;
     __syncthreads();
     uint32_t wbase = 0, total = 0;
 #pragma unroll
-    for (int w = 0; w < 4; ++w) {
-        const uint32_t x = w4[w];
+    for (int w = 0; w < NW; ++w) {
+        const uint32_t x = wv[w];
         if (w < wave) wbase += x;
         total += x;
     }
@@ -289,8 +290,8 @@ __device__ uint32_t block_excl_scan_rt(T *a, int n, uint32_t *w4) {
 // which costs two cached loads instead of a 16-24 byte LDS round trip.
 constexpr int kStageBatch = 3072;          // pairs per LDS batch
 
-template <int W, int PER, int MAXF>
-__global__ __launch_bounds__(256) void k_scatter_staged(Plan p, const QRec<W> *__restrict__ A,
+template <int W, int PER, int MAXF, int NT>
+__global__ __launch_bounds__(NT) void k_scatter_staged(Plan p, const QRec<W> *__restrict__ A,
                                                         const QRec<W> *__restrict__ B,
                                                         const uint32_t *__restrict__ offB,
                                                         const QRec<W> *__restrict__ Cq,
@@ -299,24 +300,25 @@ __global__ __launch_bounds__(256) void k_scatter_staged(Plan p, const QRec<W> *_
                                                         const uint32_t *__restrict__ offL,
                                                         const uint32_t *__restrict__ offR,
                                                         Rec<W> *recL, Rec<W> *recR, int64_t idx0) {
-    constexpr int BATCH = kStageBatch;
+    constexpr int BATCH = kStageBatch * (NT / 256);
+    constexpr int NW = NT / 64;
     constexpr int per = PER;                     // outer elements per thread per chunk
     constexpr int WV = W > 0 ? W : 1;
-    static_assert(256 * PER <= 65536, "chunk-relative outer index must fit 16 bits");
+    static_assert(NT * PER <= 65536, "chunk-relative outer index must fit 16 bits");
     __shared__ uint32_t s_cur[MAXF];
     __shared__ uint32_t s_cnt[MAXF];
     __shared__ uint32_t s_q[BATCH];              // inner element of the pair
     __shared__ uint16_t s_io[BATCH];             // outer element, relative to the chunk
     __shared__ uint16_t s_f[BATCH];              // fine bucket, 0xFFFF = filtered out
     __shared__ uint16_t s_perm[BATCH];
-    __shared__ uint32_t s_w4[4];
+    __shared__ uint32_t s_w4[NW];
     const int side = blockIdx.y;
     const int P = p.parts;
     const int cw = blockIdx.x / P, part = blockIdx.x % P;
     const int t = threadIdx.x;
     const uint32_t T = 1u << p.log2T;
     const int F = 1 << p.log2F;
-    const int Fs = F < 256 ? 256 : F;            // scan length (multiple of 256)
+    const int Fs = F < NT ? NT : F;              // scan length (multiple of NT)
     const int64_t M1 = ((int64_t)1 << p.log2M) - 1;
     const uint32_t k = (uint32_t)(p.kfirst + (idx0 + cw) * p.kstep) & (T - 1);
     const QRec<W> *outer = side ? Cq : A;
@@ -326,10 +328,10 @@ __global__ __launch_bounds__(256) void k_scatter_staged(Plan p, const QRec<W> *_
     const uint32_t *offs = side ? offR : offL;
     Rec<W> *rec = side ? recR : recL;
     const uint64_t base = ((uint64_t)cw * F) * P + part;
-    for (int f = t; f < F; f += 256) s_cur[f] = offs[base + (uint64_t)f * P];
+    for (int f = t; f < F; f += NT) s_cur[f] = offs[base + (uint64_t)f * P];
     const uint64_t lo = Qo * part / P, hi = Qo * (part + 1) / P;
     const int64_t smod1 = p.slice_mod - 1;
-    for (uint64_t c0 = lo; c0 < hi; c0 += (uint64_t)256 * per) {
+    for (uint64_t c0 = lo; c0 < hi; c0 += (uint64_t)NT * per) {
         // This thread's outer elements (per of them, consecutive) and the
         // chunk-relative offsets of their pairs.
         int64_t akey[PER];
@@ -355,13 +357,13 @@ __global__ __launch_bounds__(256) void k_scatter_staged(Plan p, const QRec<W> *_
         if ((t & 63) == 63) s_w4[t >> 6] = inc;
         __syncthreads();
         uint32_t myoff = inc - mysum, total = 0;
-        for (int w = 0; w < 4; ++w) {
+        for (int w = 0; w < NW; ++w) {
             if (w < (t >> 6)) myoff += s_w4[w];
             total += s_w4[w];
         }
         for (uint32_t P0 = 0; P0 < total; P0 += BATCH) {
             const uint32_t nb = min((uint32_t)BATCH, total - P0);
-            for (int f = t; f < Fs; f += 256) s_cnt[f] = 0;
+            for (int f = t; f < Fs; f += NT) s_cnt[f] = 0;
             // Stage my pairs whose index falls in [P0, P0 + nb).
             uint32_t off = myoff;
 #pragma unroll
@@ -391,17 +393,17 @@ __global__ __launch_bounds__(256) void k_scatter_staged(Plan p, const QRec<W> *_
                 off += n;
             }
             __syncthreads();
-            for (uint32_t o = t; o < nb; o += 256)
+            for (uint32_t o = t; o < nb; o += NT)
                 if (s_f[o] != 0xFFFF) atomicAdd(&s_cnt[s_f[o]], 1u);
             __syncthreads();
-            const uint32_t nvalid = block_excl_scan_rt<uint32_t>(s_cnt, Fs, s_w4);
+            const uint32_t nvalid = block_excl_scan_rt<uint32_t, NT>(s_cnt, Fs, s_w4);
             // Rank within the batch; afterwards s_cnt[f] = end of group f.
-            for (uint32_t o = t; o < nb; o += 256) {
+            for (uint32_t o = t; o < nb; o += NT) {
                 const uint32_t f = s_f[o];
                 if (f != 0xFFFF) s_perm[atomicAdd(&s_cnt[f], 1u)] = (uint16_t)o;
             }
             __syncthreads();
-            for (uint32_t o = t; o < nvalid; o += 256) {
+            for (uint32_t o = t; o < nvalid; o += NT) {
                 const uint32_t slot = s_perm[o];
                 const uint32_t f = s_f[slot];
                 const uint32_t start = f ? s_cnt[f - 1] : 0u;
@@ -418,7 +420,7 @@ __global__ __launch_bounds__(256) void k_scatter_staged(Plan p, const QRec<W> *_
                 rec[s_cur[f] + (o - start)] = r;
             }
             __syncthreads();
-            for (int f = t; f < F; f += 256) s_cur[f] += s_cnt[f] - (f ? s_cnt[f - 1] : 0u);
+            for (int f = t; f < F; f += NT) s_cur[f] += s_cnt[f] - (f ? s_cnt[f - 1] : 0u);
             __syncthreads();
         }
     }
@@ -1479,8 +1481,11 @@ static hipError_t staged_impl(const Plan &p, const DevBufs &b, int64_t idx0, int
     // LDS for the per-bucket cursors is sized to F: more work-groups per CU.
     const int F = 1 << p.log2F;
     dim3 grid((uint32_t)K * p.parts, 2);
+    // 512 threads (batches of 6144 pairs) while two work-groups still fit a
+    // CU's LDS; 256 threads for the 4096-bucket cursors.
 #define MSP_STAGED(PERV, MF)                                                                    \
-    hipLaunchKernelGGL((k_scatter_staged<W, PERV, MF>), grid, dim3(256), 0, st, p,              \
+    hipLaunchKernelGGL((k_scatter_staged<W, PERV, MF, (MF) <= 2048 ? 512 : 256>), grid,        \
+                       dim3((MF) <= 2048 ? 512 : 256), 0, st, p,                                \
                        (const QRec<W> *)b.qsrt[0], (const QRec<W> *)b.qsrt[1], b.qcnt[1],       \
                        (const QRec<W> *)b.qsrt[2], (const QRec<W> *)b.qsrt[3], b.qcnt[3],       \
                        b.off[0], b.off[1], (Rec<W> *)b.rec[0], (Rec<W> *)b.rec[1], idx0)
