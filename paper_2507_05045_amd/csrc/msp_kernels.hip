@@ -736,6 +736,19 @@ __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__
         return;
     }
     const int t = threadIdx.x;
+    // Right keys and rows are loaded first and consumed after the build.
+    constexpr int kPre = 4;                              // right records preloaded per lane
+    int64_t rk[kPre];
+    uint32_t rv[kPre][WV];
+#pragma unroll
+    for (int e = 0; e < kPre; ++e) {
+        const uint32_t j = t + 256 * e;
+        if (j < nr) {
+            rk[e] = rkey(p, R[r0 + j]);
+#pragma unroll
+            for (int w = 0; w < WV; ++w) rv[e][w] = R[r0 + j].vec[w];
+        }
+    }
     uint32_t slots = 256;
     while (slots < 2 * nl) slots <<= 1;
     const uint32_t smask = slots - 1;
@@ -843,8 +856,7 @@ __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__
     }
     uint64_t hits = 0;
     __syncthreads();                                    // left rows reordered
-    for (uint32_t rj = t; rj < nr; rj += 256) {
-        const int64_t key = rkey(p, R[r0 + rj]);
+    auto probe = [&](const int64_t key, const uint32_t *v, uint32_t rj) {
         // After the scan an empty slot keeps head 0xFFFF but its low half
         // holds a running offset, so emptiness is read from the head half.
         uint32_t h = key_hash(key) & smask;
@@ -859,7 +871,7 @@ __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__
             }
             h = (h + 1) & smask;
         }
-        if (gs == kNone) continue;
+        if (gs == kNone) return;
         hits += ge - gs;
         if (W == 0) {
             atomicAdd((unsigned long long *)&scal[S_NSOL], (unsigned long long)(ge - gs));
@@ -868,29 +880,39 @@ __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__
                 emit_solution(sol, cap, &scal[S_STORED], half_mask(p, qs, 0, L[l0 + s_grp[q]].hdr),
                               half_mask(p, qs, 1, R[r0 + rj].hdr));
             }
-        } else {
-            uint32_t v[WV];
+            return;
+        }
+        // Eight first words in flight per step; the rest of a word vector is
+        // read only where the first word matches.
+        for (uint32_t q0 = gs; q0 < ge; q0 += 8) {
+            uint32_t x[8];
 #pragma unroll
-            for (int w = 0; w < WV; ++w) v[w] = R[r0 + rj].vec[w];
-            for (uint32_t q0 = gs; q0 < ge; q0 += 8) {
-                uint32_t x[8];
+            for (int u = 0; u < 8; ++u) x[u] = s_vec[0][q0 + u];   // padded past nl
+            uint32_t m = 0;
 #pragma unroll
-                for (int u = 0; u < 8; ++u) x[u] = s_vec[0][q0 + u];
-                uint32_t m = 0;
+            for (int u = 0; u < 8; ++u) m |= (uint32_t)(x[u] == v[0] && q0 + u < ge) << u;
+            while (m) {
+                const uint32_t q = q0 + __builtin_ctz(m);
+                m &= m - 1;
+                bool ok = true;
 #pragma unroll
-                for (int u = 0; u < 8; ++u) m |= (uint32_t)(x[u] == v[0] && q0 + u < ge) << u;
-                while (m) {
-                    const uint32_t q = q0 + __builtin_ctz(m);
-                    m &= m - 1;
-                    bool ok = true;
-#pragma unroll
-                    for (int w = 1; w < WV; ++w) ok = ok && (s_vec[w][q] == v[w]);
-                    if (ok)
-                        emit_solution(sol, cap, &scal[S_NSOL], half_mask(p, qs, 0, L[l0 + s_grp[q]].hdr),
-                                      half_mask(p, qs, 1, R[r0 + rj].hdr));
-                }
+                for (int w = 1; w < WV; ++w) ok = ok && (s_vec[w][q] == v[w]);
+                if (ok)
+                    emit_solution(sol, cap, &scal[S_NSOL], half_mask(p, qs, 0, L[l0 + s_grp[q]].hdr),
+                                  half_mask(p, qs, 1, R[r0 + rj].hdr));
             }
         }
+    };
+#pragma unroll
+    for (int e = 0; e < kPre; ++e) {
+        const uint32_t j = t + 256 * e;
+        if (j < nr) probe(rk[e], rv[e], j);
+    }
+    for (uint32_t j = t + 256 * kPre; j < nr; j += 256) {
+        uint32_t v[WV];
+#pragma unroll
+        for (int w = 0; w < WV; ++w) v[w] = R[r0 + j].vec[w];
+        probe(rkey(p, R[r0 + j]), v, j);
     }
     const uint64_t tot = block_sum_u64(hits, s_s4);
     if (t == 0) add_u128(&scal[S_H_LO], &scal[S_H_HI], tot);
@@ -1481,11 +1503,13 @@ static hipError_t staged_impl(const Plan &p, const DevBufs &b, int64_t idx0, int
     // LDS for the per-bucket cursors is sized to F: more work-groups per CU.
     const int F = 1 << p.log2F;
     dim3 grid((uint32_t)K * p.parts, 2);
-    // 512 threads (batches of 6144 pairs) while two work-groups still fit a
-    // CU's LDS; 256 threads for the 4096-bucket cursors.
+    // Threads per work-group (batch = 12 pairs per thread), by the LDS that
+    // the bucket cursors leave: 512 for F <= 1024 (two groups per CU), 1024
+    // for F = 2048 (one group of 16 waves), 256 for F = 4096.
+#define MSP_NT(MF) ((MF) <= 1024 ? 512 : (MF) <= 2048 ? 1024 : 256)
 #define MSP_STAGED(PERV, MF)                                                                    \
-    hipLaunchKernelGGL((k_scatter_staged<W, PERV, MF, (MF) <= 2048 ? 512 : 256>), grid,        \
-                       dim3((MF) <= 2048 ? 512 : 256), 0, st, p,                                \
+    hipLaunchKernelGGL((k_scatter_staged<W, PERV, MF, MSP_NT(MF)>), grid, dim3(MSP_NT(MF)), 0, \
+                       st, p,                                                                   \
                        (const QRec<W> *)b.qsrt[0], (const QRec<W> *)b.qsrt[1], b.qcnt[1],       \
                        (const QRec<W> *)b.qsrt[2], (const QRec<W> *)b.qsrt[3], b.qcnt[3],       \
                        b.off[0], b.off[1], (Rec<W> *)b.rec[0], (Rec<W> *)b.rec[1], idx0)
@@ -1506,6 +1530,7 @@ static hipError_t staged_impl(const Plan &p, const DevBufs &b, int64_t idx0, int
     }
 #undef MSP_STAGED_PER
 #undef MSP_STAGED
+#undef MSP_NT
     return hipGetLastError();
 }
 
