@@ -40,8 +40,8 @@ struct Plan {
 template <int W>
 struct __attribute__((packed, aligned(4))) QRec {
     int64_t key;
+    uint32_t vec[W > 0 ? W : 1];     // key and rows adjacent: one wide load for both
     uint32_t mask;
-    uint32_t vec[W > 0 ? W : 1];
 };
 
 // A half record in a bucket: left (key k_a + k_b, packed row sums) or right

@@ -409,14 +409,20 @@ __global__ __launch_bounds__(NT) void k_scatter_staged(Plan p, const QRec<W> *__
                 const uint32_t start = f ? s_cnt[f - 1] : 0u;
                 const uint32_t q = s_q[slot];
                 const uint64_t ai = c0 + s_io[slot];
-                const QRec<W> a = outer[ai];
-                const QRec<W> bq = inner[q];
-                const int64_t key = side ? a.key - bq.key : a.key + bq.key;
+                // Key and rows only (adjacent in QRec): the mask is not needed.
+                const int64_t ak = outer[ai].key, bk = inner[q].key;
+                uint32_t av[WV], bv[WV];
+#pragma unroll
+                for (int w = 0; w < WV; ++w) {
+                    av[w] = outer[ai].vec[w];
+                    bv[w] = inner[q].vec[w];
+                }
+                const int64_t key = side ? ak - bk : ak + bk;
                 Rec<W> r;
                 r.hdr = ai | ((uint64_t)q << p.qa) | ((uint64_t)(key >> p.log2M) << p.hsh);
 #pragma unroll
                 for (int w = 0; w < WV; ++w)
-                    r.vec[w] = side ? resid_word(p.dpk[w], a.vec[w], bq.vec[w]) : a.vec[w] + bq.vec[w];
+                    r.vec[w] = side ? resid_word(p.dpk[w], av[w], bv[w]) : av[w] + bv[w];
                 rec[s_cur[f] + (o - start)] = r;
             }
             __syncthreads();
