@@ -332,14 +332,15 @@ __global__ __launch_bounds__(NT) void k_scatter_staged(Plan p, const QRec<W> *__
     const uint64_t lo = Qo * part / P, hi = Qo * (part + 1) / P;
     const int64_t smod1 = p.slice_mod - 1;
     for (uint64_t c0 = lo; c0 < hi; c0 += (uint64_t)NT * per) {
-        // This thread's outer elements (per of them, consecutive) and the
-        // chunk-relative offsets of their pairs.
+        // This thread's outer elements (per of them, NT apart so that a wave
+        // reads consecutive records) and the chunk-relative offsets of their
+        // pairs.
         int64_t akey[PER];
         uint32_t b0[PER], nn[PER];
         uint32_t mysum = 0;
 #pragma unroll
         for (int e = 0; e < per; ++e) {
-            const uint64_t i = c0 + (uint64_t)t * per + e;
+            const uint64_t i = c0 + (uint64_t)e * NT + t;
             nn[e] = 0;
             b0[e] = 0;
             akey[e] = 0;
@@ -386,7 +387,7 @@ __global__ __launch_bounds__(NT) void k_scatter_staged(Plan p, const QRec<W> *__
                         if (p.slice_mod) keep = keep && ((key & smod1) == p.slice_res);
                         const uint32_t o = off + q0 + u - P0;
                         s_q[o] = b0[e] + q0 + u;
-                        s_io[o] = (uint16_t)(t * per + e);
+                        s_io[o] = (uint16_t)(e * NT + t);
                         s_f[o] = keep ? (uint16_t)((key & M1) >> p.log2T) : (uint16_t)0xFFFF;
                     }
                 }
