@@ -177,6 +177,7 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
     if (log2M - log2T > 12) return MSP_E_INVALID;       // fine buckets per cell <= 4096
     if (log2T > 24) return MSP_E_UNSUPPORTED;
     p.log2M = log2M; p.log2T = log2T; p.log2F = log2M - log2T;
+    p.khb = std::max(0, lgKd - log2M);
     p.slice_mod = o.slice_mod;
     p.slice_res = o.slice_res;
     if (o.join_variant < 0 || o.join_variant > 2) return MSP_E_INVALID;

@@ -16,6 +16,8 @@ constexpr int kThreads = 256;
 constexpr int kBigPairs = 4096;     // equal-key groups with this many pairs go to the tiled verify
 constexpr int kMaxBig = 64;         // such groups exported per chunk pair (the rest verified in place)
 constexpr int kLightGroup = 256;    // largest left group the light join verifies per lane
+constexpr uint32_t kGroupCap = 1344;   // left records per bucket in the grouped join
+constexpr uint32_t kGroupSlots = 2048; // its LDS table (at most two-thirds full)
 
 // Everything the kernels need to know about one solve.
 struct Plan {
@@ -27,6 +29,7 @@ struct Plan {
     int32_t hsh;                     // qa + qb: shift of the key in Rec::hdr
     int32_t join_grouped;            // light join variant: 0 chains, 1 contiguous groups
     int32_t vjoin;                   // exact runs decided by the vector hash join
+    int32_t khb;                     // bits of key >> log2M (every stored key is in [0, K_d])
     int64_t Kd;                      // target key
     int64_t slice_mod, slice_res;    // slice on the left key (0 = none)
     int64_t kstep, kfirst;           // cell k = kfirst + idx * kstep

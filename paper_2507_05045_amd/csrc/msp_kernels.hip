@@ -15,6 +15,8 @@
 // low bits, cell(a + b) = cell(a) + cell(b) mod T exactly, so the left
 // records of output cell k are exactly the products A_i x B_{k-i}: every
 // enumerated pair lands in the cell being built.
+#include <type_traits>
+
 #include "msp_internal.h"
 
 #include <stdlib.h>
@@ -712,7 +714,7 @@ __global__ __launch_bounds__(256) void k_join_light(Plan p, const uint32_t *__re
 // out in group order.  Each right record then walks its group with eight
 // independent LDS loads of first words in flight per step; the other words
 // are read only where the first matches.
-template <int W>
+template <int W, bool K32>
 __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__restrict__ offL,
                                                    const uint32_t *__restrict__ offR,
                                                    const Rec<W> *__restrict__ L,
@@ -723,11 +725,15 @@ __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__
     constexpr uint32_t kEmpty = 0xFFFF0000u;
     constexpr int WV = W > 0 ? W : 1;
     constexpr uint32_t kNone = 0xFFFFu;
-    __shared__ int64_t s_key[kJoinCap];
-    __shared__ uint32_t s_vec[WV][kJoinCap + 8];         // left rows: by left index, then by group
-    __shared__ uint32_t s_tab[kJoinSlots];
-    __shared__ uint16_t s_slot[kJoinCap];
-    __shared__ uint16_t s_grp[kJoinCap];                 // group order -> left index
+    // Capacity and table sized for four work-groups per CU: keys held in 32
+    // bits when key >> log2M fits (K32), table at most two-thirds full.
+    using KT = typename std::conditional<K32, uint32_t, int64_t>::type;
+    constexpr uint32_t kCap = kGroupCap;
+    __shared__ KT s_key[kCap];
+    __shared__ uint32_t s_vec[WV][kCap + 8];             // left rows: by left index, then by group
+    __shared__ uint32_t s_tab[kGroupSlots];
+    __shared__ uint16_t s_slot[kCap];
+    __shared__ uint16_t s_grp[kCap];                     // group order -> left index
     __shared__ uint32_t s_w4[4];
     __shared__ uint64_t s_s4[4];
     __shared__ uint32_t s_gmax;
@@ -737,7 +743,7 @@ __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__
     const uint32_t r0 = offR[b * P], r1 = offR[(b + 1) * P];
     const uint32_t nl = l1 - l0, nr = r1 - r0;
     if (nl == 0 || nr == 0) return;                     // uniform across the block
-    if (nl > (uint32_t)kJoinCap) {                      // too big for LDS: heavy kernel
+    if (nl > kCap) {                                    // too big for LDS: heavy kernel
         if (threadIdx.x == 0)
             heavy[atomicAdd((unsigned long long *)&scal[S_NHEAVY], 1ull)] = b;
         return;
@@ -757,12 +763,12 @@ __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__
         }
     }
     uint32_t slots = 256;
-    while (slots < 2 * nl) slots <<= 1;
+    while (2 * slots < 3 * nl) slots <<= 1;             // <= kGroupSlots for nl <= kCap
     const uint32_t smask = slots - 1;
     for (uint32_t i = t; i < slots; i += 256) s_tab[i] = kEmpty;
     if (t == 0) s_gmax = 0;
     {   // all left loads of this lane issued together, then staged into LDS
-        constexpr int kLU = (kJoinCap + 255) / 256;
+        constexpr int kLU = (kCap + 255) / 256;
         int64_t lk[kLU];
         uint32_t lv[kLU][WV];
 #pragma unroll
@@ -778,7 +784,7 @@ __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__
         for (int u = 0; u < kLU; ++u) {
             const uint32_t i = t + 256 * u;
             if (i < nl) {
-                s_key[i] = lk[u];
+                s_key[i] = (KT)lk[u];
 #pragma unroll
                 for (int w = 0; w < WV; ++w) s_vec[w][i] = lv[u][w];
             }
@@ -787,8 +793,8 @@ __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__
     __syncthreads();
     // Build: one representative per distinct key, count per slot.
     for (uint32_t i = t; i < nl; i += 256) {
-        const int64_t k = s_key[i];
-        uint32_t h = key_hash(k) & smask;
+        const KT k = s_key[i];
+        uint32_t h = key_hash((int64_t)k) & smask;
         for (;;) {
             uint32_t w = s_tab[h];
             if (w == kEmpty) {
@@ -840,7 +846,7 @@ __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__
     }
     __syncthreads();
     {   // left rows into group order
-        constexpr int kLU = (kJoinCap + 255) / 256;
+        constexpr int kLU = (kCap + 255) / 256;
         uint32_t tmp[kLU][WV];
 #pragma unroll
         for (int u = 0; u < kLU; ++u) {
@@ -871,7 +877,7 @@ __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__
         for (;;) {
             const uint32_t w = s_tab[h];
             if ((w >> 16) == 0xFFFFu) break;
-            if (s_key[w >> 16] == key) {
+            if (s_key[w >> 16] == (KT)key) {
                 ge = w & 0xFFFFu;
                 gs = h ? (s_tab[h - 1] & 0xFFFFu) : 0u;
                 break;
@@ -1571,9 +1577,12 @@ static hipError_t join_impl(const Plan &p, const DevBufs &b, int32_t K, uint64_t
                             hipStream_t st) {
     const uint32_t nb = (uint32_t)K << p.log2F;
     const Rec<W> *L = (const Rec<W> *)b.rec[0], *R = (const Rec<W> *)b.rec[1];
-    if (p.join_grouped)
-        hipLaunchKernelGGL(k_join_grouped<W>, dim3(nb), dim3(256), 0, st, p, b.off[0], b.off[1], L,
-                           R, b.heavy, b.scal, b.sol, cap, sorted_quarters<W>(b));
+    if (p.join_grouped && p.khb <= 32)
+        hipLaunchKernelGGL((k_join_grouped<W, true>), dim3(nb), dim3(256), 0, st, p, b.off[0],
+                           b.off[1], L, R, b.heavy, b.scal, b.sol, cap, sorted_quarters<W>(b));
+    else if (p.join_grouped)
+        hipLaunchKernelGGL((k_join_grouped<W, false>), dim3(nb), dim3(256), 0, st, p, b.off[0],
+                           b.off[1], L, R, b.heavy, b.scal, b.sol, cap, sorted_quarters<W>(b));
     else
         hipLaunchKernelGGL(k_join_light<W>, dim3(nb), dim3(256), 0, st, p, b.off[0], b.off[1], L, R,
                            b.heavy, b.scal, b.sol, cap, sorted_quarters<W>(b));
