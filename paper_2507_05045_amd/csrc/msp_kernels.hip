@@ -583,7 +583,7 @@ __global__ __launch_bounds__(256) void k_vjoin_probe(Plan p, const RunPair *__re
 // packs chain head and length); each right record walks its slot's chain.
 // Buckets with more than kJoinCap left records, or a chain longer than
 // kLightGroup, are handed to k_join_heavy unprocessed.
-template <int W>
+template <int W, bool K32>
 __global__ __launch_bounds__(256) void k_join_light(Plan p, const uint32_t *__restrict__ offL,
                                                    const uint32_t *__restrict__ offR,
                                                    const Rec<W> *__restrict__ L,
@@ -594,7 +594,9 @@ __global__ __launch_bounds__(256) void k_join_light(Plan p, const uint32_t *__re
     constexpr uint32_t kEmpty = kEnd << 16;               // head = end of chain, length 0
     constexpr int kPre = 4;                              // right records preloaded per lane
     constexpr int WV = W > 0 ? W : 1;
-    __shared__ int64_t s_key[kJoinCap];
+    // Keys in 32 bits when key >> log2M fits (K32): more work-groups per CU.
+    using KT = typename std::conditional<K32, uint32_t, int64_t>::type;
+    __shared__ KT s_key[kJoinCap];
     __shared__ uint32_t s_vec[WV][kJoinCap];             // left packed rows, by left index
     constexpr uint32_t kLightSlots = 2048;               // load factor <= 3/4 at kJoinCap
     __shared__ uint32_t s_head[kLightSlots];             // (first left index << 16) | length
@@ -647,7 +649,7 @@ __global__ __launch_bounds__(256) void k_join_light(Plan p, const uint32_t *__re
         for (int u = 0; u < kLU; ++u) {
             const uint32_t i = t + 256 * u;
             if (i < nl) {
-                s_key[i] = lk[u];
+                s_key[i] = (KT)lk[u];
 #pragma unroll
                 for (int w = 0; w < WV; ++w) s_vec[w][i] = lv[u][w];
             }
@@ -655,7 +657,7 @@ __global__ __launch_bounds__(256) void k_join_light(Plan p, const uint32_t *__re
     }
     __syncthreads();
     for (uint32_t i = t; i < nl; i += 256) {
-        const uint32_t h = key_hash(s_key[i]) & smask;
+        const uint32_t h = key_hash((int64_t)s_key[i]) & smask;
         uint32_t old = s_head[h];
         for (;;) {
             const uint32_t got = atomicCAS(&s_head[h], old, (i << 16) | ((old & 0xFFFFu) + 1));
@@ -691,7 +693,7 @@ __global__ __launch_bounds__(256) void k_join_light(Plan p, const uint32_t *__re
     };
     auto probe = [&](const int64_t key, const uint32_t *v, uint32_t rj) {
         for (uint32_t i = s_head[key_hash(key) & smask] >> 16; i != kEnd; i = s_next[i])
-            if (s_key[i] == key) hit(i, v, rj);
+            if (s_key[i] == (KT)key) hit(i, v, rj);
     };
 #pragma unroll
     for (int e = 0; e < kPre; ++e) {
@@ -1583,9 +1585,12 @@ static hipError_t join_impl(const Plan &p, const DevBufs &b, int32_t K, uint64_t
     else if (p.join_grouped)
         hipLaunchKernelGGL((k_join_grouped<W, false>), dim3(nb), dim3(256), 0, st, p, b.off[0],
                            b.off[1], L, R, b.heavy, b.scal, b.sol, cap, sorted_quarters<W>(b));
+    else if (p.khb <= 32)
+        hipLaunchKernelGGL((k_join_light<W, true>), dim3(nb), dim3(256), 0, st, p, b.off[0],
+                           b.off[1], L, R, b.heavy, b.scal, b.sol, cap, sorted_quarters<W>(b));
     else
-        hipLaunchKernelGGL(k_join_light<W>, dim3(nb), dim3(256), 0, st, p, b.off[0], b.off[1], L, R,
-                           b.heavy, b.scal, b.sol, cap, sorted_quarters<W>(b));
+        hipLaunchKernelGGL((k_join_light<W, false>), dim3(nb), dim3(256), 0, st, p, b.off[0],
+                           b.off[1], L, R, b.heavy, b.scal, b.sol, cap, sorted_quarters<W>(b));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // Buckets deferred by the light join (count read on the device).
