@@ -589,10 +589,11 @@ __global__ __launch_bounds__(256) void k_join_light(Plan p, const uint32_t *__re
                                                    const Rec<W> *__restrict__ L,
                                                    const Rec<W> *__restrict__ R, uint32_t *heavy,
                                                    uint64_t *scal, uint64_t *sol, uint64_t cap,
-                                                   QPtrs<W> qs) {
+                                                   QPtrs<W> qs, uint32_t nb) {
     constexpr uint32_t kEnd = 0xFFFFu;
     constexpr uint32_t kEmpty = kEnd << 16;               // head = end of chain, length 0
     constexpr int kPre = 4;                              // right records preloaded per lane
+    constexpr int kLU = (kJoinCap + 255) / 256;           // left records per lane
     constexpr int WV = W > 0 ? W : 1;
     // Keys in 32 bits when key >> log2M fits (K32): more work-groups per CU.
     using KT = typename std::conditional<K32, uint32_t, int64_t>::type;
@@ -603,108 +604,128 @@ __global__ __launch_bounds__(256) void k_join_light(Plan p, const uint32_t *__re
     __shared__ uint16_t s_next[kJoinCap];
     __shared__ uint64_t s_s4[4];
     __shared__ uint32_t s_gmax;
-    const uint32_t b = blockIdx.x;
-    const uint64_t P = p.parts;
-    const uint32_t l0 = offL[b * P], l1 = offL[(b + 1) * P];
-    const uint32_t r0 = offR[b * P], r1 = offR[(b + 1) * P];
-    const uint32_t nl = l1 - l0, nr = r1 - r0;
-    if (nl == 0 || nr == 0) return;                     // uniform across the block
-    if (nl > (uint32_t)kJoinCap) {                      // too big for LDS: heavy kernel
-        if (threadIdx.x == 0)
-            heavy[atomicAdd((unsigned long long *)&scal[S_NHEAVY], 1ull)] = b;
-        return;
-    }
     const int t = threadIdx.x;
-    // Right keys and rows are loaded first and consumed after the build.
-    int64_t rk[kPre];
-    uint32_t rv[kPre][WV];
-#pragma unroll
-    for (int e = 0; e < kPre; ++e) {
-        const uint32_t j = t + 256 * e;
-        if (j < nr) {
-            rk[e] = rkey(p, R[r0 + j]);
-#pragma unroll
-            for (int w = 0; w < WV; ++w) rv[e][w] = R[r0 + j].vec[w];
-        }
-    }
-    uint32_t slots = 256;
-    while (3 * slots < 4 * nl) slots <<= 1;
-    const uint32_t smask = slots - 1;
-    for (uint32_t i = t; i < slots; i += 256) s_head[i] = kEmpty;
-    if (t == 0) s_gmax = 0;
-    {   // all left loads of this lane issued together, then staged into LDS
-        constexpr int kLU = (kJoinCap + 255) / 256;
-        int64_t lk[kLU];
+    const uint64_t P = p.parts;
+    // A bucket's ranges and this lane's share of its records, in registers.
+    // Headers are kept raw (the key shift is applied where they are used), so
+    // no instruction depends on a load inside its guard and all loads of a
+    // bucket stay in flight together.
+    struct Slot {
+        uint32_t l0, nl, r0, nr;
+        uint64_t lh[kLU];
         uint32_t lv[kLU][WV];
+        uint64_t rh[kPre];
+        uint32_t rv[kPre][WV];
+    };
+    // Every lane issues the same loads for every bucket (lanes past a range
+    // read record 0 and ignore it): a fixed number of loads per bucket lets
+    // the wait for the current bucket leave the next bucket's loads pending.
+    auto fetch = [&](uint32_t bb, Slot &f) {
+        f.l0 = offL[bb * P];
+        f.nl = offL[(bb + 1) * P] - f.l0;
+        f.r0 = offR[bb * P];
+        f.nr = offR[(bb + 1) * P] - f.r0;
 #pragma unroll
         for (int u = 0; u < kLU; ++u) {
             const uint32_t i = t + 256 * u;
-            if (i < nl) {
-                lk[u] = rkey(p, L[l0 + i]);
+            const uint32_t li = i < f.nl ? f.l0 + i : 0u;
+            f.lh[u] = L[li].hdr;
 #pragma unroll
-                for (int w = 0; w < WV; ++w) lv[u][w] = L[l0 + i].vec[w];
-            }
+            for (int w = 0; w < WV; ++w) f.lv[u][w] = L[li].vec[w];
         }
 #pragma unroll
-        for (int u = 0; u < kLU; ++u) {
-            const uint32_t i = t + 256 * u;
-            if (i < nl) {
-                s_key[i] = (KT)lk[u];
+        for (int e = 0; e < kPre; ++e) {
+            const uint32_t j = t + 256 * e;
+            const uint32_t rj = j < f.nr ? f.r0 + j : 0u;
+            f.rh[e] = R[rj].hdr;
 #pragma unroll
-                for (int w = 0; w < WV; ++w) s_vec[w][i] = lv[u][w];
-            }
+            for (int w = 0; w < WV; ++w) f.rv[e][w] = R[rj].vec[w];
         }
-    }
-    __syncthreads();
-    for (uint32_t i = t; i < nl; i += 256) {
-        const uint32_t h = key_hash((int64_t)s_key[i]) & smask;
-        uint32_t old = s_head[h];
-        for (;;) {
-            const uint32_t got = atomicCAS(&s_head[h], old, (i << 16) | ((old & 0xFFFFu) + 1));
-            if (got == old) break;
-            old = got;
-        }
-        s_next[i] = (uint16_t)(old >> 16);
-        const uint32_t len = (old & 0xFFFFu) + 1;
-        if (len > (uint32_t)kLightGroup) atomicMax(&s_gmax, len);   // rare: one shared word
-    }
-    __syncthreads();
-    const uint32_t gmax = s_gmax;
-    if (gmax > (uint32_t)kLightGroup) {                 // a large group: heavy kernel
-        if (t == 0) heavy[atomicAdd((unsigned long long *)&scal[S_NHEAVY], 1ull)] = b;
-        return;
-    }
+    };
     uint64_t hits = 0;
-    auto hit = [&](uint32_t i, const uint32_t *v, uint32_t rj) {
-        ++hits;
-        if (W == 0) {
-            atomicAdd((unsigned long long *)&scal[S_NSOL], 1ull);
-            if (scal[S_STORED] < cap)
-                emit_solution(sol, cap, &scal[S_STORED], half_mask(p, qs, 0, L[l0 + i].hdr),
-                              half_mask(p, qs, 1, R[r0 + rj].hdr));
-        } else {
-            bool ok = true;
+    // Work-groups stride over the buckets; the next bucket's records are
+    // loaded while the current one is joined, so their latency is hidden.
+    Slot cur, nxt;
+    uint32_t b = blockIdx.x;
+    fetch(min(b, nb - 1), cur);
+    while (b < nb) {
+        const uint32_t bn = b + gridDim.x;
+        fetch(min(bn, nb - 1), nxt);                    // past the end: a repeat, unused
+        const uint32_t l0 = cur.l0, nl = cur.nl, r0 = cur.r0, nr = cur.nr;
+        __syncthreads();                                // the previous bucket is done with LDS
+        const bool run = nl != 0 && nr != 0 && nl <= (uint32_t)kJoinCap;   // uniform
+        if (nl > (uint32_t)kJoinCap && nr != 0 && t == 0)           // too big for LDS
+            heavy[atomicAdd((unsigned long long *)&scal[S_NHEAVY], 1ull)] = b;
+        if (run) {
+            uint32_t slots = 256;
+            while (3 * slots < 4 * nl) slots <<= 1;
+            const uint32_t smask = slots - 1;
+            for (uint32_t i = t; i < slots; i += 256) s_head[i] = kEmpty;
+            if (t == 0) s_gmax = 0;
 #pragma unroll
-            for (int w = 0; w < WV; ++w) ok = ok && (s_vec[w][i] == v[w]);
-            if (ok)
-                emit_solution(sol, cap, &scal[S_NSOL], half_mask(p, qs, 0, L[l0 + i].hdr),
-                              half_mask(p, qs, 1, R[r0 + rj].hdr));
+            for (int u = 0; u < kLU; ++u) {
+                const uint32_t i = t + 256 * u;
+                if (i < nl) {
+                    s_key[i] = (KT)(cur.lh[u] >> p.hsh);
+#pragma unroll
+                    for (int w = 0; w < WV; ++w) s_vec[w][i] = cur.lv[u][w];
+                }
+            }
+            __syncthreads();
+            for (uint32_t i = t; i < nl; i += 256) {
+                const uint32_t h = key_hash((int64_t)s_key[i]) & smask;
+                uint32_t old = s_head[h];
+                for (;;) {
+                    const uint32_t got =
+                        atomicCAS(&s_head[h], old, (i << 16) | ((old & 0xFFFFu) + 1));
+                    if (got == old) break;
+                    old = got;
+                }
+                s_next[i] = (uint16_t)(old >> 16);
+                const uint32_t len = (old & 0xFFFFu) + 1;
+                if (len > (uint32_t)kLightGroup) atomicMax(&s_gmax, len);   // rare
+            }
+            __syncthreads();
+            if (s_gmax > (uint32_t)kLightGroup) {       // a large group: heavy kernel
+                if (t == 0) heavy[atomicAdd((unsigned long long *)&scal[S_NHEAVY], 1ull)] = b;
+            } else {
+                auto hit = [&](uint32_t i, const uint32_t *v, uint32_t rj) {
+                    ++hits;
+                    if (W == 0) {
+                        atomicAdd((unsigned long long *)&scal[S_NSOL], 1ull);
+                        if (scal[S_STORED] < cap)
+                            emit_solution(sol, cap, &scal[S_STORED],
+                                          half_mask(p, qs, 0, L[l0 + i].hdr),
+                                          half_mask(p, qs, 1, R[r0 + rj].hdr));
+                    } else {
+                        bool ok = true;
+#pragma unroll
+                        for (int w = 0; w < WV; ++w) ok = ok && (s_vec[w][i] == v[w]);
+                        if (ok)
+                            emit_solution(sol, cap, &scal[S_NSOL],
+                                          half_mask(p, qs, 0, L[l0 + i].hdr),
+                                          half_mask(p, qs, 1, R[r0 + rj].hdr));
+                    }
+                };
+                auto probe = [&](const int64_t key, const uint32_t *v, uint32_t rj) {
+                    for (uint32_t i = s_head[key_hash(key) & smask] >> 16; i != kEnd; i = s_next[i])
+                        if (s_key[i] == (KT)key) hit(i, v, rj);
+                };
+#pragma unroll
+                for (int e = 0; e < kPre; ++e) {
+                    const uint32_t j = t + 256 * e;
+                    if (j < nr) probe((int64_t)(cur.rh[e] >> p.hsh), cur.rv[e], j);
+                }
+                for (uint32_t j = t + 256 * kPre; j < nr; j += 256) {
+                    uint32_t v[WV];
+#pragma unroll
+                    for (int w = 0; w < WV; ++w) v[w] = R[r0 + j].vec[w];
+                    probe(rkey(p, R[r0 + j]), v, j);
+                }
+            }
         }
-    };
-    auto probe = [&](const int64_t key, const uint32_t *v, uint32_t rj) {
-        for (uint32_t i = s_head[key_hash(key) & smask] >> 16; i != kEnd; i = s_next[i])
-            if (s_key[i] == (KT)key) hit(i, v, rj);
-    };
-#pragma unroll
-    for (int e = 0; e < kPre; ++e) {
-        const uint32_t j = t + 256 * e;
-        if (j < nr) probe(rk[e], rv[e], j);
-    }
-    for (uint32_t j = t + 256 * kPre; j < nr; j += 256) {
-        uint32_t v[WV];
-#pragma unroll
-        for (int w = 0; w < WV; ++w) v[w] = R[r0 + j].vec[w];
-        probe(rkey(p, R[r0 + j]), v, j);
+        cur = nxt;
+        b = bn;
     }
     const uint64_t tot = block_sum_u64(hits, s_s4);
     if (t == 0) add_u128(&scal[S_H_LO], &scal[S_H_HI], tot);
@@ -1585,12 +1606,14 @@ static hipError_t join_impl(const Plan &p, const DevBufs &b, int32_t K, uint64_t
     else if (p.join_grouped)
         hipLaunchKernelGGL((k_join_grouped<W, false>), dim3(nb), dim3(256), 0, st, p, b.off[0],
                            b.off[1], L, R, b.heavy, b.scal, b.sol, cap, sorted_quarters<W>(b));
-    else if (p.khb <= 32)
-        hipLaunchKernelGGL((k_join_light<W, true>), dim3(nb), dim3(256), 0, st, p, b.off[0],
-                           b.off[1], L, R, b.heavy, b.scal, b.sol, cap, sorted_quarters<W>(b));
+    else if (p.khb <= 32)       // persistent: work-groups stride over the buckets
+        hipLaunchKernelGGL((k_join_light<W, true>), dim3(std::min<uint32_t>(nb, 4096)), dim3(256),
+                           0, st, p, b.off[0], b.off[1], L, R, b.heavy, b.scal, b.sol, cap,
+                           sorted_quarters<W>(b), nb);
     else
-        hipLaunchKernelGGL((k_join_light<W, false>), dim3(nb), dim3(256), 0, st, p, b.off[0],
-                           b.off[1], L, R, b.heavy, b.scal, b.sol, cap, sorted_quarters<W>(b));
+        hipLaunchKernelGGL((k_join_light<W, false>), dim3(std::min<uint32_t>(nb, 4096)), dim3(256),
+                           0, st, p, b.off[0], b.off[1], L, R, b.heavy, b.scal, b.sol, cap,
+                           sorted_quarters<W>(b), nb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // Buckets deferred by the light join (count read on the device).
