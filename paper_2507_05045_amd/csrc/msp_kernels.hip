@@ -1600,20 +1600,19 @@ static hipError_t join_impl(const Plan &p, const DevBufs &b, int32_t K, uint64_t
                             hipStream_t st) {
     const uint32_t nb = (uint32_t)K << p.log2F;
     const Rec<W> *L = (const Rec<W> *)b.rec[0], *R = (const Rec<W> *)b.rec[1];
+    const dim3 pg(std::min<uint32_t>(nb, 4096));         // persistent chain join
     if (p.join_grouped && p.khb <= 32)
         hipLaunchKernelGGL((k_join_grouped<W, true>), dim3(nb), dim3(256), 0, st, p, b.off[0],
                            b.off[1], L, R, b.heavy, b.scal, b.sol, cap, sorted_quarters<W>(b));
     else if (p.join_grouped)
         hipLaunchKernelGGL((k_join_grouped<W, false>), dim3(nb), dim3(256), 0, st, p, b.off[0],
                            b.off[1], L, R, b.heavy, b.scal, b.sol, cap, sorted_quarters<W>(b));
-    else if (p.khb <= 32)       // persistent: work-groups stride over the buckets
-        hipLaunchKernelGGL((k_join_light<W, true>), dim3(std::min<uint32_t>(nb, 4096)), dim3(256),
-                           0, st, p, b.off[0], b.off[1], L, R, b.heavy, b.scal, b.sol, cap,
-                           sorted_quarters<W>(b), nb);
+    else if (p.khb <= 32)
+        hipLaunchKernelGGL((k_join_light<W, true>), pg, dim3(256), 0, st, p, b.off[0], b.off[1], L,
+                           R, b.heavy, b.scal, b.sol, cap, sorted_quarters<W>(b), nb);
     else
-        hipLaunchKernelGGL((k_join_light<W, false>), dim3(std::min<uint32_t>(nb, 4096)), dim3(256),
-                           0, st, p, b.off[0], b.off[1], L, R, b.heavy, b.scal, b.sol, cap,
-                           sorted_quarters<W>(b), nb);
+        hipLaunchKernelGGL((k_join_light<W, false>), pg, dim3(256), 0, st, p, b.off[0], b.off[1],
+                           L, R, b.heavy, b.scal, b.sol, cap, sorted_quarters<W>(b), nb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // Buckets deferred by the light join (count read on the device).
