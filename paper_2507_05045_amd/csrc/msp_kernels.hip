@@ -250,6 +250,78 @@ __global__ __launch_bounds__(256) void k_bucket(Plan p, const QRec<W> *__restric
     }
 }
 
+// Count pass (the enumeration of k_bucket without records).  Each thread
+// takes PER outer elements at a time, NT apart so that a wave reads
+// consecutive records, and loads eight inner keys together: the chains of
+// dependent loads (outer key -> cell offsets -> inner keys) of several
+// elements are in flight at once.  Out-of-range lanes load a valid record and
+// ignore it, so every step issues the same loads.
+template <int W, int PER>
+__global__ __launch_bounds__(256) void k_count(Plan p, const QRec<W> *__restrict__ A,
+                                               const QRec<W> *__restrict__ B,
+                                               const uint32_t *__restrict__ offB,
+                                               const QRec<W> *__restrict__ Cq,
+                                               const QRec<W> *__restrict__ Dq,
+                                               const uint32_t *__restrict__ offD,
+                                               uint32_t *cntL, uint32_t *cntR, int64_t idx0) {
+    __shared__ uint32_t s_f[kMaxFine];
+    const int side = blockIdx.y;
+    const int P = p.parts;
+    const int cw = blockIdx.x / P, part = blockIdx.x % P;
+    const int t = threadIdx.x;
+    const uint32_t T = 1u << p.log2T;
+    const int F = 1 << p.log2F;
+    const int64_t M1 = ((int64_t)1 << p.log2M) - 1;
+    const uint32_t k = (uint32_t)(p.kfirst + (idx0 + cw) * p.kstep) & (T - 1);
+    const QRec<W> *outer = side ? Cq : A;
+    const QRec<W> *inner = side ? Dq : B;
+    const uint32_t *ioff = side ? offD : offB;
+    const uint64_t Qo = side ? p.Q[2] : p.Q[0];
+    uint32_t *cnt = side ? cntR : cntL;
+    const uint64_t base = ((uint64_t)cw * F) * P + part;
+    for (int f = t; f < F; f += 256) s_f[f] = 0u;
+    __syncthreads();
+    const uint64_t lo = Qo * part / P, hi = Qo * (part + 1) / P;
+    const int64_t smod1 = p.slice_mod - 1;
+    if (hi > lo) {
+        for (uint64_t c0 = lo; c0 < hi; c0 += (uint64_t)256 * PER) {
+            int64_t ak[PER];
+            uint32_t b0[PER], b1[PER];
+#pragma unroll
+            for (int e = 0; e < PER; ++e) {
+                const uint64_t i = c0 + (uint64_t)e * 256 + t;
+                ak[e] = outer[i < hi ? i : lo].key;
+            }
+#pragma unroll
+            for (int e = 0; e < PER; ++e) {
+                const uint32_t ca = (uint32_t)ak[e] & (T - 1);
+                const uint32_t j = side ? ((ca - k) & (T - 1)) : ((k - ca) & (T - 1));
+                b0[e] = ioff[j];
+                b1[e] = ioff[j + 1];
+            }
+#pragma unroll
+            for (int e = 0; e < PER; ++e) {
+                if (c0 + (uint64_t)e * 256 + t >= hi) b1[e] = b0[e];
+                for (uint32_t q0 = b0[e]; q0 < b1[e]; q0 += 8) {
+                    int64_t bk[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) bk[u] = inner[min(q0 + u, b1[e] - 1)].key;
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        if (q0 + u >= b1[e]) break;
+                        const int64_t key = side ? ak[e] - bk[u] : ak[e] + bk[u];
+                        bool keep = side ? key >= 0 : key <= p.Kd;   // only these can meet
+                        if (p.slice_mod) keep = keep && ((key & smod1) == p.slice_res);
+                        if (keep) atomicAdd(&s_f[(uint32_t)((key & M1) >> p.log2T)], 1u);
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int f = t; f < F; f += 256) cnt[base + (uint64_t)f * P] = s_f[f];
+}
+
 // Exclusive scan of a[0 .. n) in LDS by an NT-thread block (n a multiple of
 // NT, at most 16 NT); wv holds NT / 64 wave totals.  Returns the total.
 template <typename T, int NT = 256>
@@ -1522,8 +1594,25 @@ static hipError_t bucket_impl(const Plan &p, const DevBufs &b, int64_t idx0, int
     return hipGetLastError();
 }
 
+template <int W>
+static hipError_t count_impl(const Plan &p, const DevBufs &b, int64_t idx0, int32_t K,
+                             hipStream_t st) {
+    // Four outer elements per thread while cells hold few inner elements.
+    const uint64_t T = (uint64_t)1 << p.log2T;
+    const uint64_t qin = std::min((uint64_t)p.Q[1], (uint64_t)p.Q[3]);
+    dim3 grid((uint32_t)K * p.parts, 2);
+#define MSP_COUNT(PERV)                                                                         \
+    hipLaunchKernelGGL((k_count<W, PERV>), grid, dim3(256), 0, st, p, (const QRec<W> *)b.qsrt[0], \
+                       (const QRec<W> *)b.qsrt[1], b.qcnt[1], (const QRec<W> *)b.qsrt[2],       \
+                       (const QRec<W> *)b.qsrt[3], b.qcnt[3], b.cnt[0], b.cnt[1], idx0)
+    if (qin >= 16 * T) MSP_COUNT(1);
+    else MSP_COUNT(4);
+#undef MSP_COUNT
+    return hipGetLastError();
+}
+
 hipError_t launch_count(const Plan &p, const DevBufs &b, int64_t idx0, int32_t K, hipStream_t st) {
-    MSP_DISPATCH_W(p.W, return (bucket_impl<WW, false>(p, b, idx0, K, st)));
+    MSP_DISPATCH_W(p.W, return count_impl<WW>(p, b, idx0, K, st));
     return hipSuccess;
 }
 
