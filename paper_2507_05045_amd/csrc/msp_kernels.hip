@@ -409,22 +409,27 @@ __global__ __launch_bounds__(NT) void k_scatter_staged(Plan p, const QRec<W> *__
         // This thread's outer elements (per of them, NT apart so that a wave
         // reads consecutive records) and the chunk-relative offsets of their
         // pairs.
+        // Every lane issues the same loads (past the end it reads element lo
+        // and ignores it), so the keys, then the cell ranges, of all its
+        // elements are in flight together.
         int64_t akey[PER];
-        uint32_t b0[PER], nn[PER];
+        uint32_t b0[PER], nn[PER], c1[PER];
         uint32_t mysum = 0;
 #pragma unroll
         for (int e = 0; e < per; ++e) {
             const uint64_t i = c0 + (uint64_t)e * NT + t;
-            nn[e] = 0;
-            b0[e] = 0;
-            akey[e] = 0;
-            if (i < hi) {
-                akey[e] = outer[i].key;
-                const uint32_t ca = (uint32_t)akey[e] & (T - 1);
-                const uint32_t j = side ? ((ca - k) & (T - 1)) : ((k - ca) & (T - 1));
-                b0[e] = ioff[j];
-                nn[e] = ioff[j + 1] - b0[e];
-            }
+            akey[e] = outer[i < hi ? i : lo].key;
+        }
+#pragma unroll
+        for (int e = 0; e < per; ++e) {
+            const uint32_t ca = (uint32_t)akey[e] & (T - 1);
+            const uint32_t j = side ? ((ca - k) & (T - 1)) : ((k - ca) & (T - 1));
+            b0[e] = ioff[j];
+            c1[e] = ioff[j + 1];
+        }
+#pragma unroll
+        for (int e = 0; e < per; ++e) {
+            nn[e] = (c0 + (uint64_t)e * NT + t < hi) ? c1[e] - b0[e] : 0u;
             mysum += nn[e];
         }
         const uint32_t inc = wave_incl_scan(mysum);
