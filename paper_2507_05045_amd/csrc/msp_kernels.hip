@@ -849,18 +849,20 @@ __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__
         return;
     }
     const int t = threadIdx.x;
-    // Right keys and rows are loaded first and consumed after the build.
+    // Right records are loaded first and consumed after the build.  Every
+    // lane issues the same loads (lanes past a range read record 0 and
+    // ignore it) and headers stay raw until used, so no load waits inside
+    // its guard and all of them are in flight together.
     constexpr int kPre = 4;                              // right records preloaded per lane
-    int64_t rk[kPre];
+    uint64_t rh[kPre];
     uint32_t rv[kPre][WV];
 #pragma unroll
     for (int e = 0; e < kPre; ++e) {
         const uint32_t j = t + 256 * e;
-        if (j < nr) {
-            rk[e] = rkey(p, R[r0 + j]);
+        const uint32_t rj = j < nr ? r0 + j : 0u;
+        rh[e] = R[rj].hdr;
 #pragma unroll
-            for (int w = 0; w < WV; ++w) rv[e][w] = R[r0 + j].vec[w];
-        }
+        for (int w = 0; w < WV; ++w) rv[e][w] = R[rj].vec[w];
     }
     uint32_t slots = 256;
     while (2 * slots < 3 * nl) slots <<= 1;             // <= kGroupSlots for nl <= kCap
@@ -869,22 +871,21 @@ __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__
     if (t == 0) s_gmax = 0;
     {   // all left loads of this lane issued together, then staged into LDS
         constexpr int kLU = (kCap + 255) / 256;
-        int64_t lk[kLU];
+        uint64_t lh[kLU];
         uint32_t lv[kLU][WV];
 #pragma unroll
         for (int u = 0; u < kLU; ++u) {
             const uint32_t i = t + 256 * u;
-            if (i < nl) {
-                lk[u] = rkey(p, L[l0 + i]);
+            const uint32_t li = i < nl ? l0 + i : 0u;
+            lh[u] = L[li].hdr;
 #pragma unroll
-                for (int w = 0; w < WV; ++w) lv[u][w] = L[l0 + i].vec[w];
-            }
+            for (int w = 0; w < WV; ++w) lv[u][w] = L[li].vec[w];
         }
 #pragma unroll
         for (int u = 0; u < kLU; ++u) {
             const uint32_t i = t + 256 * u;
             if (i < nl) {
-                s_key[i] = (KT)lk[u];
+                s_key[i] = (KT)(lh[u] >> p.hsh);
 #pragma unroll
                 for (int w = 0; w < WV; ++w) s_vec[w][i] = lv[u][w];
             }
@@ -1019,7 +1020,7 @@ __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__
 #pragma unroll
     for (int e = 0; e < kPre; ++e) {
         const uint32_t j = t + 256 * e;
-        if (j < nr) probe(rk[e], rv[e], j);
+        if (j < nr) probe((int64_t)(rh[e] >> p.hsh), rv[e], j);
     }
     for (uint32_t j = t + 256 * kPre; j < nr; j += 256) {
         uint32_t v[WV];
