@@ -75,13 +75,14 @@ typedef struct {
                                  number of equal-key records per key), 1 = per-slot
                                  chains (groups of ~1), 2 = contiguous key groups
                                  (groups of ~5-250)                                     */
-    int32_t  verify_join;     /* 1: with exact buckets (each bucket one key value),
-                                 decide every equal-key run pair by an exact hash join
-                                 on the packed non-key rows instead of checking its
-                                 |G_L||G_R| pairs one by one (the sort/search check of
-                                 Algorithms 3-4 with an exact key in place of a
-                                 hash).  Same H, |S| and solutions; no effect with
-                                 hash buckets or when every row is a key row       */
+    int32_t  verify_join;     /* 1: decide every equal-key run pair by an exact hash
+                                 join on (key, packed non-key rows) instead of checking
+                                 its |G_L||G_R| pairs one by one (the sort/search check
+                                 of Algorithms 3-4 with an exact key in place of a
+                                 hash): a device-wide table for exact buckets, an LDS
+                                 table per bucket for hash buckets (buckets too large
+                                 for LDS keep the pairwise check).  Same H, |S| and
+                                 solutions; no effect when every row is a key row   */
 } msp_opts;
 
 /* Per-solve statistics; phase times are measured with HIP events on the

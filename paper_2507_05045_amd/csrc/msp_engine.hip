@@ -200,7 +200,7 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
         p.join_grouped = lg >= std::log2(6.0) ? 1 : 0;
     }
     if (o.verify_join < 0 || o.verify_join > 1) return MSP_E_INVALID;
-    p.vjoin = (o.verify_join && p.exact && p.W > 0) ? 1 : 0;
+    p.vjoin = (o.verify_join && p.W > 0) ? 1 : 0;
     const uint64_t T = (uint64_t)1 << log2T;
     if (o.slice_mod > 0) {
         p.kstep = (int64_t)std::min<uint64_t>((uint64_t)o.slice_mod, T);
@@ -271,7 +271,7 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
         z.o_heavy = take(p.exact ? 4 : kw * F * 4);
         // Vector join table: at most half full, so every probe ends.
         z.vtab_slots = 1;
-        if (p.vjoin)
+        if (p.vjoin && p.exact)
             while (z.vtab_slots < 2 * cap_rec) z.vtab_slots <<= 1;
         z.o_vtab = take(z.vtab_slots * 4);
         z.o_sol = take(z.sol_cap * 16);
@@ -537,7 +537,7 @@ int job_step(Job &j) {
             if (j.next == A_JOINED) {
                 j.st.ms_scatter += ev_ms(j.ev[E_S0], j.ev[E_S1]);
                 j.st.ms_join += ev_ms(j.ev[E_S1], j.ev[E_S2]);
-                if (p.vjoin && nruns) {
+                if (p.vjoin && p.exact && nruns) {
                     // Exact runs: one hash join on the packed rows decides them all.
                     JCHK(hipEventRecord(j.ev[E_V0], j.s));
                     JCHK(launch_vector_join(p, j.b, nruns, z.sol_cap, j.s));

@@ -808,13 +808,22 @@ __global__ __launch_bounds__(256) void k_join_light(Plan p, const uint32_t *__re
     if (t == 0) add_u128(&scal[S_H_LO], &scal[S_H_HI], tot);
 }
 
+// Hash of a (key, packed rows) pair for the vector join table.
+template <int W>
+__device__ __forceinline__ uint32_t kv_hash(int64_t key, const uint32_t *v) {
+    uint64_t h = (uint64_t)key * 0x9E3779B97F4A7C15ull;
+#pragma unroll
+    for (int w = 0; w < (W > 0 ? W : 1); ++w) h = (h ^ v[w]) * 0xC2B2AE3D27D4EB4Full;
+    return (uint32_t)(h >> 32);
+}
+
 // Light join variant for buckets whose equal-key groups hold a few to a
 // few hundred records: linear-probe table with one representative per
 // distinct key, counts scanned into contiguous groups, and the left rows laid
 // out in group order.  Each right record then walks its group with eight
 // independent LDS loads of first words in flight per step; the other words
 // are read only where the first matches.
-template <int W, bool K32>
+template <int W, bool K32, bool VJ>
 __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__restrict__ offL,
                                                    const uint32_t *__restrict__ offR,
                                                    const Rec<W> *__restrict__ L,
@@ -834,6 +843,7 @@ __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__
     __shared__ uint32_t s_tab[kGroupSlots];
     __shared__ uint16_t s_slot[kCap];
     __shared__ uint16_t s_grp[kCap];                     // group order -> left index
+    __shared__ uint32_t s_vt[VJ ? kGroupSlots : 1];      // VJ: (key, rows) -> left index
     __shared__ uint32_t s_w4[4];
     __shared__ uint64_t s_s4[4];
     __shared__ uint32_t s_gmax;
@@ -867,7 +877,10 @@ __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__
     uint32_t slots = 256;
     while (2 * slots < 3 * nl) slots <<= 1;             // <= kGroupSlots for nl <= kCap
     const uint32_t smask = slots - 1;
-    for (uint32_t i = t; i < slots; i += 256) s_tab[i] = kEmpty;
+    for (uint32_t i = t; i < slots; i += 256) {
+        s_tab[i] = kEmpty;
+        if (VJ) s_vt[i] = 0xFFFFFFFFu;
+    }
     if (t == 0) s_gmax = 0;
     {   // all left loads of this lane issued together, then staged into LDS
         constexpr int kLU = (kCap + 255) / 256;
@@ -908,8 +921,54 @@ __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__
         }
         s_slot[i] = (uint16_t)h;
         atomicAdd(&s_tab[h], 1u);
+        if (VJ) {
+            uint32_t lvv[WV];
+#pragma unroll
+            for (int w = 0; w < WV; ++w) lvv[w] = s_vec[w][i];
+            // At most two-thirds full: an empty slot is always reached.
+            uint32_t g = kv_hash<W>((int64_t)k, lvv) & smask;
+            while (atomicCAS(&s_vt[g], 0xFFFFFFFFu, i) != 0xFFFFFFFFu) g = (g + 1) & smask;
+        }
     }
     __syncthreads();
+    if (VJ) {
+        uint64_t hits = 0;
+        auto probe_vj = [&](const int64_t key, const uint32_t *v, uint32_t rj) {
+            uint32_t h = key_hash(key) & smask;
+            for (;;) {
+                const uint32_t w = s_tab[h];
+                if (w == kEmpty) return;                 // no left record has this key
+                if (s_key[w >> 16] == (KT)key) break;
+                h = (h + 1) & smask;
+            }
+            hits += s_tab[h] & 0xFFFFu;                  // |G_L| pairs for this right record
+            for (uint32_t g = kv_hash<W>(key, v) & smask;; g = (g + 1) & smask) {
+                const uint32_t li = s_vt[g];
+                if (li == 0xFFFFFFFFu) break;
+                if (s_key[li] != (KT)key) continue;
+                bool ok = true;
+#pragma unroll
+                for (int w = 0; w < WV; ++w) ok = ok && (s_vec[w][li] == v[w]);
+                if (ok)
+                    emit_solution(sol, cap, &scal[S_NSOL], half_mask(p, qs, 0, L[l0 + li].hdr),
+                                  half_mask(p, qs, 1, R[r0 + rj].hdr));
+            }
+        };
+#pragma unroll
+        for (int q = 0; q < kPre; ++q) {
+            const uint32_t j = t + 256 * q;
+            if (j < nr) probe_vj((int64_t)(rh[q] >> p.hsh), rv[q], j);
+        }
+        for (uint32_t j = t + 256 * kPre; j < nr; j += 256) {
+            uint32_t v[WV];
+#pragma unroll
+            for (int w = 0; w < WV; ++w) v[w] = R[r0 + j].vec[w];
+            probe_vj(rkey(p, R[r0 + j]), v, j);
+        }
+        const uint64_t tot = block_sum_u64(hits, s_s4);
+        if (t == 0) add_u128(&scal[S_H_LO], &scal[S_H_HI], tot);
+        return;
+    }
     {   // exclusive scan of the counts (low halves), heads kept
         const int E = (int)(slots >> 8), lane = t & 63, wave = t >> 6;
         uint32_t loc[16], sum = 0, gm = 0;
@@ -1696,18 +1755,24 @@ static hipError_t join_impl(const Plan &p, const DevBufs &b, int32_t K, uint64_t
     const uint32_t nb = (uint32_t)K << p.log2F;
     const Rec<W> *L = (const Rec<W> *)b.rec[0], *R = (const Rec<W> *)b.rec[1];
     const dim3 pg(std::min<uint32_t>(nb, 4096));         // persistent chain join
-    if (p.join_grouped && p.khb <= 32)
-        hipLaunchKernelGGL((k_join_grouped<W, true>), dim3(nb), dim3(256), 0, st, p, b.off[0],
-                           b.off[1], L, R, b.heavy, b.scal, b.sol, cap, sorted_quarters<W>(b));
+#define MSP_GROUPED(K32V, VJV)                                                                  \
+    hipLaunchKernelGGL((k_join_grouped<W, K32V, VJV>), dim3(nb), dim3(256), 0, st, p, b.off[0], \
+                       b.off[1], L, R, b.heavy, b.scal, b.sol, cap, sorted_quarters<W>(b))
+    if (p.vjoin && p.khb <= 32)            // vector join: the grouped kernel decides every run
+        MSP_GROUPED(true, true);
+    else if (p.vjoin)
+        MSP_GROUPED(false, true);
+    else if (p.join_grouped && p.khb <= 32)
+        MSP_GROUPED(true, false);
     else if (p.join_grouped)
-        hipLaunchKernelGGL((k_join_grouped<W, false>), dim3(nb), dim3(256), 0, st, p, b.off[0],
-                           b.off[1], L, R, b.heavy, b.scal, b.sol, cap, sorted_quarters<W>(b));
+        MSP_GROUPED(false, false);
     else if (p.khb <= 32)
         hipLaunchKernelGGL((k_join_light<W, true>), pg, dim3(256), 0, st, p, b.off[0], b.off[1], L,
                            R, b.heavy, b.scal, b.sol, cap, sorted_quarters<W>(b), nb);
     else
         hipLaunchKernelGGL((k_join_light<W, false>), pg, dim3(256), 0, st, p, b.off[0], b.off[1],
                            L, R, b.heavy, b.scal, b.sol, cap, sorted_quarters<W>(b), nb);
+#undef MSP_GROUPED
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // Buckets deferred by the light join (count read on the device).

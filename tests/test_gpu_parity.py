@@ -69,6 +69,10 @@ def test_small_random_vs_brute_force(case):
             g = gsolve(inst.A, inst.d, key_rows=case["r"], log2_m=lm, log2_cells=lc, parts=parts,
                        join_variant=jv)
             same(g, ref, f"M=2^{lm} T=2^{lc} P={parts} join={jv} {case} {seed}")
+            # hash buckets decided by the vector join inside the grouped kernel
+            g = gsolve(inst.A, inst.d, key_rows=case["r"], log2_m=lm, log2_cells=lc, parts=parts,
+                       verify_join=1)
+            same(g, ref, f"M=2^{lm} T=2^{lc} P={parts} vector join {case} {seed}")
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 7])
@@ -181,6 +185,9 @@ def test_large_configs_sampled_residue_classes(cfg):
         same(g, _golden_result(e, n), f"{e['name']} rho={e['slice_res']}")
         if inst.planted is not None:
             assert any(np.array_equal(s, inst.planted) for s in g.solutions)
+        v = gsolve(inst.A, inst.d, key_rows=4, slice_mod=e["slice_mod"], slice_res=e["slice_res"],
+                   verify_join=1)
+        same(v, _golden_result(e, n), f"{e['name']} rho={e['slice_res']} vector join")
 
 
 def test_8_70_full_solve_properties():
@@ -220,6 +227,8 @@ def test_grouped_join_mid_buckets_vs_oracle(lm):
         for lc in (4, 6):
             same(gsolve(inst.A, inst.d, key_rows=2, log2_m=lm, log2_cells=lc, join_variant=2),
                  ref, f"{inst.name} M=2^{lm} T=2^{lc} grouped")
+            same(gsolve(inst.A, inst.d, key_rows=2, log2_m=lm, log2_cells=lc, verify_join=1),
+                 ref, f"{inst.name} M=2^{lm} T=2^{lc} vector join")
 
 
 def test_vector_join_ties_and_windows():
