@@ -1091,6 +1091,122 @@ __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__
     if (t == 0) add_u128(&scal[S_H_LO], &scal[S_H_HI], tot);
 }
 
+// Vector join of the buckets too large for k_join_grouped's LDS: left
+// chunks of kGroupCap records, each against the whole right side of the
+// bucket, with the same two LDS tables (key -> count for H, (key, rows) ->
+// left index for the solutions).  Every (left, right) pair of the bucket is
+// met once; nothing is compared pair by pair.
+template <int W, bool K32>
+__global__ __launch_bounds__(256) void k_join_heavy_vj(Plan p, const uint32_t *__restrict__ offL,
+                                                      const uint32_t *__restrict__ offR,
+                                                      const Rec<W> *__restrict__ L,
+                                                      const Rec<W> *__restrict__ R,
+                                                      const uint32_t *__restrict__ heavy,
+                                                      uint64_t *scal, uint64_t *sol, uint64_t cap,
+                                                      QPtrs<W> qs) {
+    constexpr uint32_t kEmpty = 0xFFFF0000u;
+    constexpr int WV = W > 0 ? W : 1;
+    using KT = typename std::conditional<K32, uint32_t, int64_t>::type;
+    constexpr uint32_t kCap = kGroupCap;
+    constexpr int kLU = (kCap + 255) / 256;
+    __shared__ KT s_key[kCap];
+    __shared__ uint32_t s_vec[WV][kCap];
+    __shared__ uint32_t s_tab[kGroupSlots];              // (representative << 16) | count
+    __shared__ uint32_t s_vt[kGroupSlots];               // (key, rows) -> left index
+    __shared__ uint64_t s_s4[4];
+    const int t = threadIdx.x;
+    const uint32_t nheavy = (uint32_t)scal[S_NHEAVY];
+    const uint64_t P = p.parts;
+    uint64_t hits = 0;
+    for (uint32_t hb = blockIdx.x; hb < nheavy; hb += gridDim.x) {
+        const uint32_t b = heavy[hb];
+        const uint32_t L0 = offL[b * P], L1 = offL[(b + 1) * P];
+        const uint32_t r0 = offR[b * P], nr = offR[(b + 1) * P] - r0;
+        for (uint32_t l0 = L0; l0 < L1; l0 += kCap) {
+            const uint32_t nl = min(kCap, L1 - l0);
+            __syncthreads();                            // previous chunk done with LDS
+            uint32_t slots = 256;
+            while (2 * slots < 3 * nl) slots <<= 1;     // <= kGroupSlots
+            const uint32_t smask = slots - 1;
+            for (uint32_t i = t; i < slots; i += 256) {
+                s_tab[i] = kEmpty;
+                s_vt[i] = 0xFFFFFFFFu;
+            }
+            uint64_t lh[kLU];
+            uint32_t lv[kLU][WV];
+#pragma unroll
+            for (int u = 0; u < kLU; ++u) {
+                const uint32_t i = t + 256 * u;
+                const uint32_t li = i < nl ? l0 + i : 0u;
+                lh[u] = L[li].hdr;
+#pragma unroll
+                for (int w = 0; w < WV; ++w) lv[u][w] = L[li].vec[w];
+            }
+#pragma unroll
+            for (int u = 0; u < kLU; ++u) {
+                const uint32_t i = t + 256 * u;
+                if (i < nl) {
+                    s_key[i] = (KT)(lh[u] >> p.hsh);
+#pragma unroll
+                    for (int w = 0; w < WV; ++w) s_vec[w][i] = lv[u][w];
+                }
+            }
+            __syncthreads();
+            for (uint32_t i = t; i < nl; i += 256) {
+                const KT k = s_key[i];
+                uint32_t h = key_hash((int64_t)k) & smask;
+                for (;;) {
+                    uint32_t w = s_tab[h];
+                    if (w == kEmpty) {
+                        const uint32_t old = atomicCAS(&s_tab[h], kEmpty, i << 16);
+                        if (old == kEmpty) break;
+                        w = old;
+                    }
+                    if (s_key[w >> 16] == k) break;
+                    h = (h + 1) & smask;
+                }
+                atomicAdd(&s_tab[h], 1u);
+                uint32_t lvv[WV];
+#pragma unroll
+                for (int w = 0; w < WV; ++w) lvv[w] = s_vec[w][i];
+                uint32_t g = kv_hash<W>((int64_t)k, lvv) & smask;
+                while (atomicCAS(&s_vt[g], 0xFFFFFFFFu, i) != 0xFFFFFFFFu) g = (g + 1) & smask;
+            }
+            __syncthreads();
+            for (uint32_t j = t; j < nr; j += 256) {
+                const uint64_t rhdr = R[r0 + j].hdr;
+                uint32_t v[WV];
+#pragma unroll
+                for (int w = 0; w < WV; ++w) v[w] = R[r0 + j].vec[w];
+                const int64_t key = (int64_t)(rhdr >> p.hsh);
+                uint32_t h = key_hash(key) & smask;
+                bool found = false;
+                for (;;) {
+                    const uint32_t w = s_tab[h];
+                    if (w == kEmpty) break;
+                    if (s_key[w >> 16] == (KT)key) { found = true; break; }
+                    h = (h + 1) & smask;
+                }
+                if (!found) continue;
+                hits += s_tab[h] & 0xFFFFu;
+                for (uint32_t g = kv_hash<W>(key, v) & smask;; g = (g + 1) & smask) {
+                    const uint32_t li = s_vt[g];
+                    if (li == 0xFFFFFFFFu) break;
+                    if (s_key[li] != (KT)key) continue;
+                    bool ok = true;
+#pragma unroll
+                    for (int w = 0; w < WV; ++w) ok = ok && (s_vec[w][li] == v[w]);
+                    if (ok)
+                        emit_solution(sol, cap, &scal[S_NSOL], half_mask(p, qs, 0, L[l0 + li].hdr),
+                                      half_mask(p, qs, 1, rhdr));
+                }
+            }
+        }
+    }
+    const uint64_t tot = block_sum_u64(hits, s_s4);
+    if (t == 0) add_u128(&scal[S_H_LO], &scal[S_H_HI], tot);
+}
+
 template <int W>
 __global__ __launch_bounds__(256) void k_join_heavy(Plan p, const uint32_t *__restrict__ offL,
                                                    const uint32_t *__restrict__ offR,
@@ -1776,9 +1892,18 @@ static hipError_t join_impl(const Plan &p, const DevBufs &b, int32_t K, uint64_t
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // Buckets deferred by the light join (count read on the device).
-    hipLaunchKernelGGL(k_join_heavy<W>, dim3(std::min<uint32_t>(nb, 2048)), dim3(256), 0, st, p,
-                       b.off[0], b.off[1], L, R, b.heavy, b.iruns, b.idx, b.scal, b.sol, cap,
-                       b.iruns_cap, b.idx_cap, sorted_quarters<W>(b));
+    if (p.vjoin && p.khb <= 32)
+        hipLaunchKernelGGL((k_join_heavy_vj<W, true>), dim3(std::min<uint32_t>(nb, 2048)), dim3(256),
+                           0, st, p, b.off[0], b.off[1], L, R, b.heavy, b.scal, b.sol, cap,
+                           sorted_quarters<W>(b));
+    else if (p.vjoin)
+        hipLaunchKernelGGL((k_join_heavy_vj<W, false>), dim3(std::min<uint32_t>(nb, 2048)),
+                           dim3(256), 0, st, p, b.off[0], b.off[1], L, R, b.heavy, b.scal, b.sol,
+                           cap, sorted_quarters<W>(b));
+    else
+        hipLaunchKernelGGL(k_join_heavy<W>, dim3(std::min<uint32_t>(nb, 2048)), dim3(256), 0, st,
+                           p, b.off[0], b.off[1], L, R, b.heavy, b.iruns, b.idx, b.scal, b.sol, cap,
+                           b.iruns_cap, b.idx_cap, sorted_quarters<W>(b));
     return hipGetLastError();
 }
 

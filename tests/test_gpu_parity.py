@@ -213,6 +213,9 @@ def test_oversized_buckets_vs_oracle(lm):
         for jv in (1, 2):
             same(gsolve(inst.A, inst.d, key_rows=2, log2_m=lm, log2_cells=min(lm, 4),
                         join_variant=jv), ref, f"{inst.name} M=2^{lm} join={jv}")
+        # the vector join takes these buckets in left chunks (heavy kernel)
+        same(gsolve(inst.A, inst.d, key_rows=2, log2_m=lm, log2_cells=min(lm, 4), verify_join=1),
+             ref, f"{inst.name} M=2^{lm} vector join")
 
 
 @pytest.mark.parametrize("lm", [9, 10])
