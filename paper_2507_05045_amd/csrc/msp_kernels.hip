@@ -177,6 +177,23 @@ __global__ __launch_bounds__(256) void k_quarter_sort(Plan p, QPtrs<W> raw, QPtr
     srt.q[x][pos] = r;
 }
 
+// Work-group -> (cell in window, part).  Work-groups are dealt to the 8 XCDs
+// round robin, so with P a multiple of 8 each XCD gets parts x, x + 8, ...
+// and takes every cell of one part before the next.  A part is a contiguous
+// slice of the (cell-sorted) outer list, whose inner partners are then a
+// contiguous slice of the inner list as well: each XCD keeps about 8/P of
+// the inner list hot in its own L2 instead of all of it.
+__device__ __forceinline__ void cell_part(uint32_t b, uint32_t K, uint32_t P, int &cw, int &part) {
+    if ((P & 7u) == 0) {
+        const uint32_t x = b & 7u, sq = b >> 3;
+        part = (int)(x + 8u * (sq / K));
+        cw = (int)(sq % K);
+    } else {
+        cw = (int)(b / P);
+        part = (int)(b % P);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Bucket count / scatter (one enumeration, two modes)
 // ---------------------------------------------------------------------------
@@ -200,7 +217,8 @@ __global__ __launch_bounds__(256) void k_bucket(Plan p, const QRec<W> *__restric
     __shared__ uint32_t s_f[kMaxFine];
     const int side = blockIdx.y;
     const int P = p.parts;
-    const int cw = blockIdx.x / P, part = blockIdx.x % P;
+    int cw, part;
+    cell_part(blockIdx.x, gridDim.x / P, P, cw, part);
     const uint32_t T = 1u << p.log2T;
     const int F = 1 << p.log2F;
     const int64_t M1 = ((int64_t)1 << p.log2M) - 1;
@@ -267,7 +285,8 @@ __global__ __launch_bounds__(256) void k_count(Plan p, const QRec<W> *__restrict
     __shared__ uint32_t s_f[kMaxFine];
     const int side = blockIdx.y;
     const int P = p.parts;
-    const int cw = blockIdx.x / P, part = blockIdx.x % P;
+    int cw, part;
+    cell_part(blockIdx.x, gridDim.x / P, P, cw, part);
     const int t = threadIdx.x;
     const uint32_t T = 1u << p.log2T;
     const int F = 1 << p.log2F;
@@ -388,7 +407,8 @@ __global__ __launch_bounds__(NT) void k_scatter_staged(Plan p, const QRec<W> *__
     __shared__ uint32_t s_w4[NW];
     const int side = blockIdx.y;
     const int P = p.parts;
-    const int cw = blockIdx.x / P, part = blockIdx.x % P;
+    int cw, part;
+    cell_part(blockIdx.x, gridDim.x / P, P, cw, part);
     const int t = threadIdx.x;
     const uint32_t T = 1u << p.log2T;
     const int F = 1 << p.log2F;
