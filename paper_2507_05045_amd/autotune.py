@@ -97,7 +97,8 @@ def tune(A, d, key_rows: int = 1, max_seconds: float = 20.0, slice_bits: Optiona
             m2, c2 = lm + dm, lc + dc
             if c2 < max(slice_bits, 0) or c2 > m2 or m2 - c2 > 12 or c2 > 23 or m2 < 1:
                 continue
-            for p2 in sorted({parts, parts * 2, parts * 4}):
+            # multiples of 8 let the kernels map whole parts to each XCD
+            for p2 in sorted({parts, parts * 2, parts * 4, 16, 32, 64}):
                 for jv in ((0,) if base["exact_buckets"] else (1, 2)):
                     cands.append(dict(log2_m=m2, log2_cells=c2, parts=min(p2, 256),
                                       join_variant=jv))

@@ -241,6 +241,11 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
         parts = (int)std::min<uint64_t>(parts, std::max<uint64_t>(1, p.Q[0] / 256));
         parts = (int)std::min<uint64_t>(parts, std::max<uint64_t>(1, p.Q[2] / 256));
     }
+    // When the inner quarter lists outgrow one XCD's L2 (4 MB), parts come in
+    // multiples of 8: the count and scatter kernels then give each XCD whole
+    // parts, whose inner partners are a contiguous slice of the list.
+    if (!o.parts && (uint64_t)std::max(p.Q[1], p.Q[3]) * qb > ((uint64_t)4 << 20))
+        parts = std::max(8, (parts + 7) & ~7);
     p.parts = parts;
     auto layout = [&](uint64_t cap_rec, uint64_t kw) -> uint64_t {
         uint64_t off = 0;
