@@ -22,6 +22,13 @@
  * A,B,C,D of size ~n/4"): contiguous columns, h_L = ceil(n/2),
  * q_A = ceil(h_L/2), q_B = floor(h_L/2), q_C = ceil((n-h_L)/2), q_D the rest.
  *
+ * Pins (tests/test_oracle.py): orc_brute, orc_dp_count_row,
+ * orc_dp_count_2rows and orc_ss_heap are pinned by closed forms, brute force
+ * and the paper's expected number of solutions; orc_mitm_residues is pinned
+ * against brute force (n <= 30) and against orc_ss_heap (n <= 50).  Its
+ * results for the n = 70..90 classes are parity unpinned beyond that: they
+ * rest on the same code being right at larger n.
+ *
  * Every entry point returns 0 on success or a negative code:
  *   -1 invalid argument, -2 row sum exceeds 65534, -3 key overflows int64,
  *   -4 problem too large for this routine, -5 out of memory.
