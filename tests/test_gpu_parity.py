@@ -65,7 +65,9 @@ def test_small_random_vs_brute_force(case):
         same(gsolve(inst.A, inst.d, key_rows=case["r"], verify_join=1), ref,
              f"vector join {case} {seed}")
         # force hash buckets (modulus below K_d) and a few cell layouts
-        for lm, lc, parts, jv in [(3, 1, 1, 1), (5, 2, 3, 2), (6, 6, 2, 0), (6, 3, 2, 2)]:
+        # parts 8 and 16 take the XCD-aware work-group mapping
+        for lm, lc, parts, jv in [(3, 1, 1, 1), (5, 2, 3, 2), (6, 6, 2, 0), (6, 3, 2, 2),
+                                  (5, 2, 8, 1), (6, 3, 16, 2)]:
             g = gsolve(inst.A, inst.d, key_rows=case["r"], log2_m=lm, log2_cells=lc, parts=parts,
                        join_variant=jv)
             same(g, ref, f"M=2^{lm} T=2^{lc} P={parts} join={jv} {case} {seed}")
