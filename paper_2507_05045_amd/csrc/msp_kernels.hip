@@ -1275,22 +1275,23 @@ __global__ __launch_bounds__(256) void k_join_heavy(Plan p, const uint32_t *__re
     }
     {   // all left loads of this lane issued together, then staged into LDS
         constexpr int kLU = (kJoinCap + 255) / 256;
-        int64_t lk[kLU];
+        // Fixed loads per lane (past the chunk: record l0, ignored), raw
+        // headers: all in flight together.
+        uint64_t lh[kLU];
         uint32_t lv[kLU][WV];
 #pragma unroll
         for (int u = 0; u < kLU; ++u) {
             const uint32_t i = t + 256 * u;
-            if (i < nl) {
-                lk[u] = rkey(p, L[l0 + i]);
+            const uint32_t li = l0 + (i < nl ? i : 0u);
+            lh[u] = L[li].hdr;
 #pragma unroll
-                for (int w = 0; w < WV; ++w) lv[u][w] = L[l0 + i].vec[w];
-            }
+            for (int w = 0; w < WV; ++w) lv[u][w] = L[li].vec[w];
         }
 #pragma unroll
         for (int u = 0; u < kLU; ++u) {
             const uint32_t i = t + 256 * u;
             if (i < nl) {
-                s_key[i] = lk[u];
+                s_key[i] = (int64_t)(lh[u] >> p.hsh);
 #pragma unroll
                 for (int w = 0; w < WV; ++w) s_vec[w][i] = lv[u][w];
             }
@@ -1369,14 +1370,23 @@ __global__ __launch_bounds__(256) void k_join_heavy(Plan p, const uint32_t *__re
     }
     if (t == 0) s_nbig = 0;
     __syncthreads();
-    for (uint32_t j = t; j < nr; j += 256) {
-        const uint32_t h = find(rkey(p, R[r0 + j]));
-        if (h != 0xFFFFu) {
-            const uint32_t g = (s_tab[h] & 0xFFFFu) - gstart(h);
-            hits += g;
-            atomicAdd(&s_rcnt[h], 1u);
-            if (W == 0)
-                atomicAdd((unsigned long long *)&scal[S_NSOL], (unsigned long long)g);
+    // Right headers four per lane at a time (clamped into the bucket).
+    constexpr int kRU = 4;
+    for (uint32_t j0 = t; j0 < nr; j0 += 256 * kRU) {
+        uint64_t rh[kRU];
+#pragma unroll
+        for (int u = 0; u < kRU; ++u) rh[u] = R[r0 + min(j0 + 256u * u, nr - 1)].hdr;
+#pragma unroll
+        for (int u = 0; u < kRU; ++u) {
+            if (j0 + 256u * u >= nr) break;
+            const uint32_t h = find((int64_t)(rh[u] >> p.hsh));
+            if (h != 0xFFFFu) {
+                const uint32_t g = (s_tab[h] & 0xFFFFu) - gstart(h);
+                hits += g;
+                atomicAdd(&s_rcnt[h], 1u);
+                if (W == 0)
+                    atomicAdd((unsigned long long *)&scal[S_NSOL], (unsigned long long)g);
+            }
         }
     }
     __syncthreads();
@@ -1406,8 +1416,14 @@ __global__ __launch_bounds__(256) void k_join_heavy(Plan p, const uint32_t *__re
         const uint32_t h = s_slot[i], bi = s_bigidx[h];
         if (bi != 0xFFu) idx[s_bbase[bi] + (s_lpos[i] - gstart(h))] = l0 + i;
     }
-    for (uint32_t j = t; j < nr; j += 256) {
-        const uint32_t h = find(rkey(p, R[r0 + j]));
+    for (uint32_t j0 = t; j0 < nr; j0 += 256 * kRU) {
+    uint64_t rh[kRU];
+#pragma unroll
+    for (int u = 0; u < kRU; ++u) rh[u] = R[r0 + min(j0 + 256u * u, nr - 1)].hdr;
+    for (int u = 0; u < kRU; ++u) {
+        const uint32_t j = j0 + 256u * u;
+        if (j >= nr) break;
+        const uint32_t h = find((int64_t)(rh[u] >> p.hsh));
         if (h == 0xFFFFu) continue;
         const uint32_t bi = s_bigidx[h];
         if (bi != 0xFFu) {
@@ -1437,6 +1453,7 @@ __global__ __launch_bounds__(256) void k_join_heavy(Plan p, const uint32_t *__re
             }
         }
     }
+    }   // right steps
     }   // left chunks
     }   // heavy buckets
     const uint64_t tot = block_sum_u64(hits, s_s4);
