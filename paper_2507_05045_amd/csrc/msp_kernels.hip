@@ -1193,11 +1193,23 @@ __global__ __launch_bounds__(256) void k_join_heavy_vj(Plan p, const uint32_t *_
                 while (atomicCAS(&s_vt[g], 0xFFFFFFFFu, i) != 0xFFFFFFFFu) g = (g + 1) & smask;
             }
             __syncthreads();
-            for (uint32_t j = t; j < nr; j += 256) {
-                const uint64_t rhdr = R[r0 + j].hdr;
-                uint32_t v[WV];
+            // Right records four per lane at a time (clamped into the bucket),
+            // all loads in flight together.
+            constexpr int kRU = 4;
+            for (uint32_t j0 = t; j0 < nr; j0 += 256 * kRU) {
+            uint64_t rhs[kRU];
+            uint32_t rvs[kRU][WV];
 #pragma unroll
-                for (int w = 0; w < WV; ++w) v[w] = R[r0 + j].vec[w];
+            for (int u = 0; u < kRU; ++u) {
+                const uint32_t rj = r0 + min(j0 + 256u * u, nr - 1);
+                rhs[u] = R[rj].hdr;
+#pragma unroll
+                for (int w = 0; w < WV; ++w) rvs[u][w] = R[rj].vec[w];
+            }
+            for (int u = 0; u < kRU; ++u) {
+                if (j0 + 256u * u >= nr) break;
+                const uint64_t rhdr = rhs[u];
+                const uint32_t *v = rvs[u];
                 const int64_t key = (int64_t)(rhdr >> p.hsh);
                 uint32_t h = key_hash(key) & smask;
                 bool found = false;
@@ -1221,6 +1233,7 @@ __global__ __launch_bounds__(256) void k_join_heavy_vj(Plan p, const uint32_t *_
                                       half_mask(p, qs, 1, rhdr));
                 }
             }
+            }   // right steps
         }
     }
     const uint64_t tot = block_sum_u64(hits, s_s4);
