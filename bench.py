@@ -268,8 +268,8 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on exactly one GPU; multi-GPU runs are not part of this build "
-              "(the residue classes would shard across GPUs with one all-reduce at the end)",
+        print("bench.py runs on exactly one GPU: --gpus must be 1 (the residue classes would "
+              "shard across GPUs with one all-reduce at the end; that path is not provided)",
               file=sys.stderr)
         sys.exit(2)
 

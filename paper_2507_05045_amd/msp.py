@@ -73,7 +73,7 @@ except ImportError:  # the library also runs without torch
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with "
-                      "`python -c 'import __graft_entry__ as g; g.build()'` (no CPU fallback)")
+                      "`python paper_2507_05045_amd/build.py` (no CPU fallback)")
 lib = C.CDLL(LIB_PATH)
 _p = C.POINTER
 lib.msp_create.argtypes = [_p(C.c_int32), _p(C.c_int32), C.c_int32, C.c_int32, _p(C.c_void_p)]
