@@ -83,6 +83,13 @@ typedef struct {
                                  table per bucket for hash buckets (buckets too large
                                  for LDS keep the pairwise check).  Same H, |S| and
                                  solutions; no effect when every row is a key row   */
+    int32_t  key_base;        /* radix of the surrogate key (Section 1, eq. surrogate):
+                                 0 = B = n*D for every key row (D = max(100, max a_ij
+                                 + 1)); 1 = mixed radix rowsum_i + 1 per key row, the
+                                 smallest radix that keeps the key exact, so int64
+                                 holds more rows.  Both give the same H, |S| and
+                                 solutions on a whole solve; a slice keeps
+                                 k_L mod slice_mod of the key in use             */
 } msp_opts;
 
 /* Per-solve statistics; phase times are measured with HIP events on the

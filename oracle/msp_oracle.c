@@ -25,7 +25,7 @@ typedef unsigned __int128 u128;
 
 static int validate(const int32_t *A, const int32_t *d, int m, int n, int key_rows)
 {
-    if (!A || !d || m < 1 || n < 1 || n > 96 || key_rows < 1 || key_rows > m)
+    if (!A || !d || m < 1 || n < 1 || n > 96 || key_rows < 1 || key_rows > m || key_rows > 96)
         return ORC_EINVAL;
     for (int i = 0; i < m; ++i) {
         int64_t s = 0;
@@ -40,42 +40,44 @@ static int validate(const int32_t *A, const int32_t *d, int m, int n, int key_ro
 }
 
 int orc_key_setup(const int32_t *A, const int32_t *d, int m, int n, int key_rows,
-                  int64_t *base, int64_t *kd, int64_t *w, int *infeasible)
+                  int key_base, int64_t *base, int64_t *kd, int64_t *w, int *infeasible)
 {
     int rc = validate(A, d, m, n, key_rows);
     if (rc) return rc;
+    if (key_base != 0 && key_base != 1) return ORC_EINVAL;
     int32_t amax = 0;
     for (size_t k = 0; k < (size_t)m * n; ++k)
         if (A[k] > amax) amax = A[k];
     /* D > a_ij for every coefficient; D = 100 for the paper's [0,99] family. */
     int64_t D = amax + 1 > 100 ? (int64_t)amax + 1 : 100;
     int64_t B = (int64_t)n * D;
-    /* Largest key = sum_i B^i rowsum_i must stay below 2^63. */
+    /* Digit i (the row sum a_i.x, 0..rowsum_i) has radix B (key_base 0) or
+     * rowsum_i + 1 (key_base 1, mixed radix); radix[i] > every digit value
+     * is what makes the key exact.  Place values: the product of the radices
+     * of the rows below.  The largest key, sum_i place_i rowsum_i, must
+     * stay below 2^63. */
+    int64_t rowsum[96], place[96];
     __int128 kmax = 0, p = 1;
     *infeasible = 0;
     for (int i = 0; i < key_rows; ++i) {
-        int64_t rs = 0;
-        for (int j = 0; j < n; ++j) rs += A[(size_t)i * n + j];
-        if (d[i] > rs) *infeasible = 1;     /* row i can never hold */
-        kmax += p * rs;
+        rowsum[i] = 0;
+        for (int j = 0; j < n; ++j) rowsum[i] += A[(size_t)i * n + j];
+        if (d[i] > rowsum[i]) *infeasible = 1;     /* row i can never hold */
+        place[i] = (int64_t)p;
+        kmax += p * rowsum[i];
         if (kmax >= ((__int128)1 << 63)) return ORC_EKEY;
-        p *= B;
+        p *= key_base ? rowsum[i] + 1 : B;
         if (i + 1 < key_rows && p >= ((__int128)1 << 63)) return ORC_EKEY;
     }
-    int64_t k = 0, pw = 1;
-    for (int i = 0; i < key_rows; ++i) {
-        if (!*infeasible) k += pw * (int64_t)d[i];
-        pw = (i + 1 < key_rows) ? pw * B : pw;
-    }
+    int64_t k = 0;
+    for (int i = 0; i < key_rows; ++i)
+        if (!*infeasible) k += place[i] * (int64_t)d[i];
     for (int j = 0; j < n; ++j) {
-        int64_t s = 0, q = 1;
-        for (int i = 0; i < key_rows; ++i) {
-            s += q * (int64_t)A[(size_t)i * n + j];
-            if (i + 1 < key_rows) q *= B;
-        }
+        int64_t s = 0;
+        for (int i = 0; i < key_rows; ++i) s += place[i] * (int64_t)A[(size_t)i * n + j];
         w[j] = s;
     }
-    *base = B;
+    *base = key_base ? rowsum[0] + 1 : B;
     *kd = *infeasible ? -1 : k;
     return 0;
 }
@@ -116,13 +118,13 @@ static void add_h(orc_result *res, u128 v)
 /* O1: brute force -- the definition of S and H written out.                 */
 /* ------------------------------------------------------------------------ */
 
-int orc_brute(const int32_t *A, const int32_t *d, int m, int n, int key_rows,
+int orc_brute(const int32_t *A, const int32_t *d, int m, int n, int key_rows, int key_base,
               int64_t slice_mod, int64_t slice_res, uint64_t *hr,
               uint8_t *sol, uint64_t capacity, orc_result *res)
 {
     int64_t base, kd, w[96];
     int infeasible;
-    int rc = orc_key_setup(A, d, m, n, key_rows, &base, &kd, w, &infeasible);
+    int rc = orc_key_setup(A, d, m, n, key_rows, key_base, &base, &kd, w, &infeasible);
     if (rc) return rc;
     if (n > 30) return ORC_ESIZE;
     if (slice_mod < 0 || (slice_mod > 0 && (slice_res < 0 || slice_res >= slice_mod)))
@@ -417,13 +419,13 @@ static int grow(half_rec **buf, uint64_t *cap, uint64_t need)
     return 0;
 }
 
-int orc_ss_heap(const int32_t *A, const int32_t *d, int m, int n, int key_rows,
+int orc_ss_heap(const int32_t *A, const int32_t *d, int m, int n, int key_rows, int key_base,
                 int64_t slice_mod, int64_t slice_res,
                 uint8_t *sol, uint64_t capacity, orc_result *res)
 {
     int64_t base, kd, w[96];
     int infeasible;
-    int rc = orc_key_setup(A, d, m, n, key_rows, &base, &kd, w, &infeasible);
+    int rc = orc_key_setup(A, d, m, n, key_rows, key_base, &base, &kd, w, &infeasible);
     if (rc) return rc;
     if (m > 16) return ORC_ESIZE;
     if (slice_mod < 0 || (slice_mod > 0 && (slice_res < 0 || slice_res >= slice_mod)))
@@ -562,13 +564,13 @@ static uint64_t lower_res(const int64_t *r, uint64_t n, int64_t t)
 }
 
 int orc_mitm_residues(const int32_t *A, const int32_t *d, int m, int n,
-                      int key_rows, int log2_m, int64_t rho_lo, int64_t rho_hi,
+                      int key_rows, int key_base, int log2_m, int64_t rho_lo, int64_t rho_hi,
                       int64_t slice_mod, int64_t slice_res,
                       uint8_t *sol, uint64_t capacity, orc_result *res)
 {
     int64_t base, kd, w[96];
     int infeasible;
-    int rc = orc_key_setup(A, d, m, n, key_rows, &base, &kd, w, &infeasible);
+    int rc = orc_key_setup(A, d, m, n, key_rows, key_base, &base, &kd, w, &infeasible);
     if (rc) return rc;
     if (m > 16 || log2_m < 0 || log2_m > 40) return ORC_EINVAL;
     const int64_t M = (int64_t)1 << log2_m;

@@ -11,7 +11,11 @@
  * The 1-D key of Section 1, eq. surrogate: with D = max(100, max a_ij + 1)
  * and base B = n*D, key(x) = sum_{i<r} B^i (a_i . x) over the first r rows
  * (row 1 least significant).  Because every partial row sum is < B, key(x) = K_d
- * (= sum_{i<r} B^i d_i) holds exactly when rows 1..r hold.
+ * (= sum_{i<r} B^i d_i) holds exactly when rows 1..r hold.  key_base = 1
+ * (every routine takes it after key_rows) swaps B for the mixed radix
+ * rowsum_i + 1 of each key row: the digits a_i . x still stay below their
+ * radix, so the key stays exact with a smaller K_d; key_base = 0 is the
+ * paper's choice.
  *
  * H ("1-D hits") = #{x : key(x) = K_d} = #{x : rows 1..r hold}.
  * S = the full solution set.  Slice (optional): only x whose left-half key
@@ -50,7 +54,7 @@ typedef struct {
 /* Brute force over all 2^n vectors (the definition written out), n <= 30.
  * hr[k] (k = 0..m-1) receives #{x : rows 1..k+1 hold} (inside the slice,
  * which is defined with `key_rows` rows).  sol: capacity*n bytes of 0/1. */
-int orc_brute(const int32_t *A, const int32_t *d, int m, int n, int key_rows,
+int orc_brute(const int32_t *A, const int32_t *d, int m, int n, int key_rows, int key_base,
               int64_t slice_mod, int64_t slice_res, uint64_t *hr,
               uint8_t *sol, uint64_t capacity, orc_result *res);
 
@@ -67,7 +71,7 @@ int orc_dp_count_2rows(const int32_t *a1, const int32_t *a2, int n,
  * 2^C x 2^D (Algorithm 1) on the 1-D key, every equal-key group verified
  * against all m rows by an exact sort-and-search join of the partial vectors
  * (Algorithms 2 and 3; exact vectors instead of hashes). */
-int orc_ss_heap(const int32_t *A, const int32_t *d, int m, int n, int key_rows,
+int orc_ss_heap(const int32_t *A, const int32_t *d, int m, int n, int key_rows, int key_base,
                 int64_t slice_mod, int64_t slice_res,
                 uint8_t *sol, uint64_t capacity, orc_result *res);
 
@@ -78,15 +82,15 @@ int orc_ss_heap(const int32_t *A, const int32_t *d, int m, int n, int key_rows,
  * vectors.  Summed over all classes this is the whole solve.
  * The slice must satisfy slice_mod | M. */
 int orc_mitm_residues(const int32_t *A, const int32_t *d, int m, int n,
-                      int key_rows, int log2_m, int64_t rho_lo, int64_t rho_hi,
+                      int key_rows, int key_base, int log2_m, int64_t rho_lo, int64_t rho_hi,
                       int64_t slice_mod, int64_t slice_res,
                       uint8_t *sol, uint64_t capacity, orc_result *res);
 
-/* The key setup shared by the routines above, exposed for tests: base B,
- * K_d and the per-column key weights w_j (n entries).  *infeasible is set
- * when some key row has d_i > row sum (then H = 0). */
+/* The key setup shared by the routines above, exposed for tests: the radix
+ * of row 1 (*base), K_d and the per-column key weights w_j (n entries).
+ * *infeasible is set when some key row has d_i > row sum (then H = 0). */
 int orc_key_setup(const int32_t *A, const int32_t *d, int m, int n, int key_rows,
-                  int64_t *base, int64_t *kd, int64_t *w, int *infeasible);
+                  int key_base, int64_t *base, int64_t *kd, int64_t *w, int *infeasible);
 
 #ifdef __cplusplus
 }

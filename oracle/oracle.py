@@ -64,16 +64,16 @@ def _load():
         u8p = C.POINTER(C.c_uint8)
         u64p = C.POINTER(C.c_uint64)
         i64p = C.POINTER(C.c_int64)
-        lib.orc_brute.argtypes = [i32p, i32p, C.c_int, C.c_int, C.c_int, C.c_int64,
+        lib.orc_brute.argtypes = [i32p, i32p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int64,
                                   C.c_int64, u64p, u8p, C.c_uint64, C.POINTER(_Res)]
         lib.orc_dp_count_row.argtypes = [i32p, C.c_int, C.c_int64, u64p, u64p]
         lib.orc_dp_count_2rows.argtypes = [i32p, i32p, C.c_int, C.c_int64, C.c_int64, u64p]
-        lib.orc_ss_heap.argtypes = [i32p, i32p, C.c_int, C.c_int, C.c_int, C.c_int64,
+        lib.orc_ss_heap.argtypes = [i32p, i32p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int64,
                                     C.c_int64, u8p, C.c_uint64, C.POINTER(_Res)]
-        lib.orc_mitm_residues.argtypes = [i32p, i32p, C.c_int, C.c_int, C.c_int, C.c_int,
+        lib.orc_mitm_residues.argtypes = [i32p, i32p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                           C.c_int64, C.c_int64, C.c_int64, C.c_int64,
                                           u8p, C.c_uint64, C.POINTER(_Res)]
-        lib.orc_key_setup.argtypes = [i32p, i32p, C.c_int, C.c_int, C.c_int, i64p, i64p,
+        lib.orc_key_setup.argtypes = [i32p, i32p, C.c_int, C.c_int, C.c_int, C.c_int, i64p, i64p,
                                       i64p, C.POINTER(C.c_int)]
         for f in (lib.orc_brute, lib.orc_dp_count_row, lib.orc_dp_count_2rows,
                   lib.orc_ss_heap, lib.orc_mitm_residues, lib.orc_key_setup):
@@ -124,14 +124,15 @@ def _finish(res, buf, n, hr=None):
     return OracleResult((int(res.h_hi) << 64) | int(res.h_lo), int(res.nsol), sol, hr)
 
 
-def brute(A, d, key_rows=1, slice_mod=0, slice_res=0, capacity=1 << 16) -> OracleResult:
+def brute(A, d, key_rows=1, slice_mod=0, slice_res=0, capacity=1 << 16,
+          key_base=0) -> OracleResult:
     A, d = _prep(A, d)
     m, n = A.shape
     hr = np.zeros(m, dtype=np.uint64)
     buf = np.zeros(capacity * n, dtype=np.uint8)
     res = _Res()
     _check(_load().orc_brute(_ptr(A, C.c_int32), _ptr(d, C.c_int32), m, n, key_rows,
-                             slice_mod, slice_res, _ptr(hr, C.c_uint64),
+                             key_base, slice_mod, slice_res, _ptr(hr, C.c_uint64),
                              _ptr(buf, C.c_uint8), capacity, C.byref(res)))
     return _finish(res, buf, n, hr.astype(object))
 
@@ -153,19 +154,20 @@ def dp_count2(a1, a2, t1, t2) -> int:
     return out.value
 
 
-def ss_heap(A, d, key_rows=1, slice_mod=0, slice_res=0, capacity=1 << 16) -> OracleResult:
+def ss_heap(A, d, key_rows=1, slice_mod=0, slice_res=0, capacity=1 << 16,
+            key_base=0) -> OracleResult:
     A, d = _prep(A, d)
     m, n = A.shape
     buf = np.zeros(capacity * n, dtype=np.uint8)
     res = _Res()
     _check(_load().orc_ss_heap(_ptr(A, C.c_int32), _ptr(d, C.c_int32), m, n, key_rows,
-                               slice_mod, slice_res, _ptr(buf, C.c_uint8), capacity,
+                               key_base, slice_mod, slice_res, _ptr(buf, C.c_uint8), capacity,
                                C.byref(res)))
     return _finish(res, buf, n)
 
 
 def mitm(A, d, key_rows=1, log2_m=12, rho_lo=0, rho_hi=None, slice_mod=0, slice_res=0,
-         capacity=1 << 16) -> OracleResult:
+         capacity=1 << 16, key_base=0) -> OracleResult:
     A, d = _prep(A, d)
     m, n = A.shape
     if rho_hi is None:
@@ -173,26 +175,26 @@ def mitm(A, d, key_rows=1, log2_m=12, rho_lo=0, rho_hi=None, slice_mod=0, slice_
     buf = np.zeros(capacity * n, dtype=np.uint8)
     res = _Res()
     _check(_load().orc_mitm_residues(_ptr(A, C.c_int32), _ptr(d, C.c_int32), m, n, key_rows,
-                                     log2_m, rho_lo, rho_hi, slice_mod, slice_res,
+                                     key_base, log2_m, rho_lo, rho_hi, slice_mod, slice_res,
                                      _ptr(buf, C.c_uint8), capacity, C.byref(res)))
     return _finish(res, buf, n)
 
 
-def key_setup(A, d, key_rows=1):
-    """(base B, K_d, per-column key weights, infeasible flag)."""
+def key_setup(A, d, key_rows=1, key_base=0):
+    """(radix of row 1, K_d, per-column key weights, infeasible flag)."""
     A, d = _prep(A, d)
     m, n = A.shape
     base, kd = C.c_int64(), C.c_int64()
     w = np.zeros(n, dtype=np.int64)
     inf = C.c_int()
     _check(_load().orc_key_setup(_ptr(A, C.c_int32), _ptr(d, C.c_int32), m, n, key_rows,
-                                 C.byref(base), C.byref(kd), _ptr(w, C.c_int64), C.byref(inf)))
+                                 key_base, C.byref(base), C.byref(kd), _ptr(w, C.c_int64), C.byref(inf)))
     return base.value, kd.value, w, bool(inf.value)
 
 
-def left_key(A, d, x, key_rows=1) -> int:
+def left_key(A, d, x, key_rows=1, key_base=0) -> int:
     """k_L(x): the 1-D key of x restricted to the left half of the columns."""
-    _, _, w, _ = key_setup(A, d, key_rows)
+    _, _, w, _ = key_setup(A, d, key_rows, key_base)
     n = len(w)
     hl = (n + 1) // 2
     return int(sum(int(w[j]) for j in range(hl) if x[j]))

@@ -101,35 +101,36 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
     p.qc = (n - p.hL + 1) / 2; p.qd = (n - p.hL) / 2;
     p.Q[0] = 1u << p.qa; p.Q[1] = 1u << p.qb; p.Q[2] = 1u << p.qc; p.Q[3] = 1u << p.qd;
 
-    // Key: D > every a_ij (D = 100 for the [0,99] family), base B = n*D.
+    // Key (Section 1, eq. surrogate): digit i is the row sum a_i.x, radix
+    // rad_i.  key_base 0 takes the paper's B = n*D for every row (D > every
+    // a_ij, D = 100 for the [0,99] family); key_base 1 the mixed radix
+    // rowsum_i + 1, the smallest that still bounds every digit, so the same
+    // int64 holds more rows.  Either way 0 <= a_i.x <= rowsum_i < rad_i, so
+    // key(x) = K_d exactly when rows 1..r hold.
+    if (o.key_base < 0 || o.key_base > 1) return MSP_E_INVALID;
     int32_t amax = 0;
     for (int32_t a : c->A) amax = std::max(amax, a);
     const int64_t D = std::max<int64_t>(100, (int64_t)amax + 1);
-    const int64_t B = (int64_t)n * D;
-    __int128 kmax = 0, pw = 1;
+    std::vector<int64_t> pw(r, 1);                  // place value of digit i
+    __int128 kmax = 0, place = 1;
     P.infeasible = false;
     for (int i = 0; i < r; ++i) {
         int64_t rs = 0;
         for (int j = 0; j < n; ++j) rs += c->A[(size_t)i * n + j];
         if (c->d[i] > rs) P.infeasible = true;      // row i can never hold: H = 0
-        kmax += pw * rs;
+        pw[i] = (int64_t)place;
+        kmax += place * rs;
         if (kmax >= ((__int128)1 << 63)) return MSP_E_KEY_OVERFLOW;
-        pw *= B;
-        if (i + 1 < r && pw >= ((__int128)1 << 63)) return MSP_E_KEY_OVERFLOW;
+        place *= o.key_base ? rs + 1 : (int64_t)n * D;
+        if (i + 1 < r && place >= ((__int128)1 << 63)) return MSP_E_KEY_OVERFLOW;
     }
-    int64_t kd = 0, q = 1;
-    for (int i = 0; i < r; ++i) {
-        kd += q * (int64_t)c->d[i];
-        if (i + 1 < r) q *= B;
-    }
+    int64_t kd = 0;
+    for (int i = 0; i < r; ++i) kd += pw[i] * (int64_t)c->d[i];
     p.Kd = P.infeasible ? 0 : kd;
     P.colw.assign(n, 0);
     for (int j = 0; j < n; ++j) {
-        int64_t s = 0, qq = 1;
-        for (int i = 0; i < r; ++i) {
-            s += qq * (int64_t)c->A[(size_t)i * n + j];
-            if (i + 1 < r) qq *= B;
-        }
+        int64_t s = 0;
+        for (int i = 0; i < r; ++i) s += pw[i] * (int64_t)c->A[(size_t)i * n + j];
         P.colw[j] = s;
     }
     P.rows.assign((size_t)std::max(p.nv, 1) * n, 0);

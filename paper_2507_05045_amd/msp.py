@@ -37,7 +37,7 @@ class msp_opts(C.Structure):
                 ("max_solutions", C.c_uint64), ("window_records", C.c_uint64),
                 ("workspace", C.c_void_p), ("workspace_bytes", C.c_uint64),
                 ("stream", C.c_void_p), ("first_only", C.c_int32), ("join_variant", C.c_int32),
-                ("verify_join", C.c_int32)]
+                ("verify_join", C.c_int32), ("key_base", C.c_int32)]
 
 
 class msp_stats_t(C.Structure):

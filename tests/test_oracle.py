@@ -273,3 +273,81 @@ def test_errors():
         O.ss_heap(np.full((1, 3), 30000, dtype=np.int32), [1])     # row sum > 65534
     with pytest.raises(O.OracleError):
         O.ss_heap(np.full((9, 90), 99, dtype=np.int32), [1] * 9, key_rows=5)  # key overflow
+
+
+# --------------------------------------------------------------------------
+# Mixed-radix key (key_base = 1): radix rowsum_i + 1 per key row instead of
+# n*D.  Exactness and the bound on the largest key are mathematical facts,
+# pinned here against brute force, a closed form and the row counts.
+# --------------------------------------------------------------------------
+
+def test_mixed_radix_carry_instance_closed_form():
+    # Row 1 = x1 + x2 (row sum 2), row 2 = x3 + .. + x6, d = (0, 2).  The
+    # hits are x1 = x2 = 0 with two of x3..x6 set: C(4, 2) = 6.  A radix of
+    # rowsum_1 = 2 (one too small) would let s1 = 2, s2 = 1 collide with
+    # s1 = 0, s2 = 2 and add C(4, 1) = 4 false hits.
+    A = np.array([[1, 1, 0, 0, 0, 0], [0, 0, 1, 1, 1, 1]], dtype=np.int32)
+    d = np.array([0, 2], dtype=np.int32)
+    base, kd, w, inf = O.key_setup(A, d, 2, key_base=1)
+    assert base == 3 and not inf
+    for f in (lambda: O.ss_heap(A, d, 2, key_base=1),
+              lambda: O.mitm(A, d, 2, log2_m=2, key_base=1),
+              lambda: O.brute(A, d, 2, key_base=1)):
+        r = f()
+        assert r.H == math.comb(4, 2) and r.nsol == 6
+        assert all(t[0] == 0 and t[1] == 0 and sum(t) == 2 for t in sol_tuples(r))
+
+
+def test_mixed_radix_largest_key_is_radix_product_minus_one():
+    # Mixed radix: the all-ones vector has every digit at its maximum, and
+    # the largest number with digits below radices rad_i is prod rad_i - 1.
+    for seed in range(4):
+        inst = random_small(4, 20, 700 + seed, K=9, zero_cols=2)
+        rows = inst.A.astype(np.int64).sum(axis=1)
+        for r in range(1, 5):
+            _, kd, w, _ = O.key_setup(inst.A, inst.d, r, key_base=1)
+            assert int(w.sum()) == math.prod(int(v) + 1 for v in rows[:r]) - 1
+            _, _, w0, _ = O.key_setup(inst.A, inst.d, r, key_base=0)
+            B = inst.n * 100
+            assert int(w0.sum()) == sum(int(rows[i]) * B ** i for i in range(r))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_mixed_radix_key_matches_row_counts(seed):
+    # Small coefficients and zero columns make full digits (s_i = rowsum_i)
+    # common, where a wrong radix would carry into the next row.
+    inst = random_small(4, 18, 720 + seed, K=3, zero_cols=3, planted=True)
+    for r in range(1, 5):
+        b = O.brute(inst.A, inst.d, key_rows=r, key_base=1)
+        s = O.ss_heap(inst.A, inst.d, key_rows=r, key_base=1)
+        mm = O.mitm(inst.A, inst.d, key_rows=r, log2_m=4, key_base=1)
+        assert s.H == mm.H == b.hr[r - 1] == b.H
+        assert sol_tuples(s) == sol_tuples(mm) == sol_tuples(b)
+        assert O.ss_heap(inst.A, inst.d, key_rows=r).H == s.H
+
+
+def test_mixed_radix_slices_partition_the_solve():
+    inst = random_small(3, 18, 740, K=8, planted=True)
+    full = O.brute(inst.A, inst.d, key_rows=3)
+    tot_h, sols = 0, []
+    for s in range(8):
+        b = O.brute(inst.A, inst.d, key_rows=3, slice_mod=8, slice_res=s, key_base=1)
+        h = O.ss_heap(inst.A, inst.d, key_rows=3, slice_mod=8, slice_res=s, key_base=1)
+        mm = O.mitm(inst.A, inst.d, key_rows=3, log2_m=5, slice_mod=8, slice_res=s, key_base=1)
+        assert b.H == h.H == mm.H
+        assert sol_tuples(b) == sol_tuples(h) == sol_tuples(mm)
+        tot_h += b.H
+        sols += sol_tuples(b)
+    assert tot_h == full.H and sorted(sols) == sol_tuples(full)
+
+
+def test_mixed_radix_fits_a_fifth_row_where_n_times_d_does_not():
+    # (9,80), rows ~ 80 * 49.5: five digits in radix 8000 need ~65 bits,
+    # in radix rowsum + 1 ~ 60.
+    inst = make_instance(9, 80, 0)
+    with pytest.raises(O.OracleError):
+        O.key_setup(inst.A, inst.d, 5, key_base=0)
+    _, kd, w, _ = O.key_setup(inst.A, inst.d, 5, key_base=1)
+    assert 0 < kd < int(w.sum()) < 2 ** 63
+    with pytest.raises(O.OracleError):
+        O.key_setup(inst.A, inst.d, 1, key_base=2)
