@@ -83,6 +83,12 @@ WORKLOADS = {
                   slice_mod=0, desc="(8,70) planted twins of seeds 0-4, key rows 1-4"),
     "9_80p": dict(m=9, n=80, key_rows=4, seeds=[0], planted=True, planted_only=True,
                   slice_mod=0, desc="(9,80) planted twin of seed 0, key rows 1-4"),
+    # Five key rows in the mixed radix rowsum_i + 1 per row: H shrinks by
+    # about the spread of row 5, the residue tables grow (more cells).
+    "8_70_r5": dict(m=8, n=70, key_rows=5, key_base=1, seeds=[0, 1, 2, 3, 4], planted=False,
+                    slice_mod=0, desc="(8,70) seeds 0-4, key rows 1-5 in mixed radix rowsum+1"),
+    "6_50_r5": dict(m=6, n=50, key_rows=5, key_base=1, seeds=[0], planted=True, slice_mod=0,
+                    desc="(6,50) seed 0 + planted twin, key rows 1-5 in mixed radix rowsum+1"),
 }
 
 
@@ -106,7 +112,7 @@ def cpu_baseline(w, insts, budget_s=30.0):
     if w["n"] <= 50:
         inst = insts[-1]
         t = time.perf_counter()
-        r = O.ss_heap(inst.A, inst.d, w["key_rows"])
+        r = O.ss_heap(inst.A, inst.d, w["key_rows"], key_base=w.get("key_base", 0))
         dt = time.perf_counter() - t
         return {"value": r.H / dt, "unit": "hits/s", "cores": 1, "kind": "oracle",
                 "sample": f"{inst.name}: whole solve by the heap Schroeppel-Shamir oracle, "
@@ -117,7 +123,8 @@ def cpu_baseline(w, insts, budget_s=30.0):
     H, k = 0, 0
     while time.perf_counter() - t < budget_s and k < 64:
         rho = (12345 + 64 * k) % (1 << lm)     # classes inside the k_L mod 64 = 0 slice family
-        H += O.mitm(inst.A, inst.d, w["key_rows"], lm, rho, rho + 1).H
+        H += O.mitm(inst.A, inst.d, w["key_rows"], lm, rho, rho + 1,
+                    key_base=w.get("key_base", 0)).H
         k += 1
     dt = time.perf_counter() - t
     return {"value": H / dt, "unit": "hits/s", "cores": 1, "kind": "oracle",
@@ -282,12 +289,13 @@ def main():
     w = WORKLOADS[args.workload]
     insts = build_instances(w)
     ctxs = [msp.Context(i.A, i.d) for i in insts]
-    kw = dict(key_rows=w["key_rows"], slice_mod=w["slice_mod"], slice_res=0,
+    kw = dict(key_rows=w["key_rows"], key_base=w.get("key_base", 0), slice_mod=w["slice_mod"],
+              slice_res=0,
               first_only=1 if args.first_solution else 0,
               verify_join=1 if args.verify_join else 0)
     # The plan (modulus, cells, parts, join variant) the autotuner picked for
     # each instance class; the planner's defaults where it has no entry.
-    plans = [autotune.lookup(i.A, w["key_rows"]) or {} for i in insts]
+    plans = [autotune.lookup(i.A, w["key_rows"], w.get("key_base", 0)) or {} for i in insts]
 
     def step():
         stats = []

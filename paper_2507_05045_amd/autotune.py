@@ -35,10 +35,11 @@ def _arch() -> str:
         return "gfx950"
 
 
-def class_key(A, key_rows: int) -> str:
+def class_key(A, key_rows: int, key_base: int = 0) -> str:
     import numpy as np
     A = np.asarray(A)
-    return f"{_arch()}:m{A.shape[0]}:n{A.shape[1]}:r{key_rows}:amax{int(A.max())}"
+    kb = ":kb1" if key_base else ""
+    return f"{_arch()}:m{A.shape[0]}:n{A.shape[1]}:r{key_rows}{kb}:amax{int(A.max())}"
 
 
 def _load() -> Dict[str, dict]:
@@ -57,8 +58,8 @@ def _save(cache: Dict[str, dict]):
     os.replace(tmp, CACHE)
 
 
-def lookup(A, key_rows: int) -> Optional[dict]:
-    key = class_key(A, key_rows)
+def lookup(A, key_rows: int, key_base: int = 0) -> Optional[dict]:
+    key = class_key(A, key_rows, key_base)
     hit = _load().get(key)
     if hit is None:
         try:
@@ -70,17 +71,17 @@ def lookup(A, key_rows: int) -> Optional[dict]:
 
 
 def tune(A, d, key_rows: int = 1, max_seconds: float = 20.0, slice_bits: Optional[int] = None,
-         force: bool = False, verbose: bool = False) -> dict:
+         force: bool = False, verbose: bool = False, key_base: int = 0) -> dict:
     """Return the fastest plan options for this instance's class (cached)."""
-    key = class_key(A, key_rows)
+    key = class_key(A, key_rows, key_base)
     cache = _load()
     if key in cache and not force:
         return cache[key]["opts"]
     ctx = msp.Context(A, d)
     # With a slice given, the planner's default is read off a sliced solve:
     # a whole solve of a large class can take minutes.
-    ctx.solve(key_rows=key_rows, **(dict(slice_mod=1 << slice_bits, slice_res=0)
-                                    if slice_bits else {}))
+    ctx.solve(key_rows=key_rows, key_base=key_base,
+              **(dict(slice_mod=1 << slice_bits, slice_res=0) if slice_bits else {}))
     base = ctx.stats()
     full_ms = base["ms_total"]
     lm, lc, parts = base["log2_m"], base["log2_cells"], base["parts"]
@@ -108,7 +109,7 @@ def tune(A, d, key_rows: int = 1, max_seconds: float = 20.0, slice_bits: Optiona
         if time.time() > t_end:
             break
         try:
-            ctx.solve(key_rows=key_rows, **c, **sl)
+            ctx.solve(key_rows=key_rows, key_base=key_base, **c, **sl)
         except msp.MspError:
             continue
         h = ctx.hits()
@@ -117,7 +118,7 @@ def tune(A, d, key_rows: int = 1, max_seconds: float = 20.0, slice_bits: Optiona
         if h != ref_h:
             raise RuntimeError(f"plan {c} changed the hit count: {h} != {ref_h}")
         t0 = time.perf_counter()
-        ctx.solve(key_rows=key_rows, **c, **sl)
+        ctx.solve(key_rows=key_rows, key_base=key_base, **c, **sl)
         dt = time.perf_counter() - t0
         if verbose:
             print(f"  {c} {dt * 1e3:.1f} ms", flush=True)

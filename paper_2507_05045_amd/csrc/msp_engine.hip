@@ -172,6 +172,11 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
         // per cell (the staged scatter's LDS budget).
         log2T = std::max(p.qb - 3, 0);
         log2T = std::max(log2T, log2M - 10);
+        // A large M forced by the key room (many key rows) would give more
+        // cells than inner elements; every cell re-reads the outer quarter,
+        // so take the most fine buckets per cell instead (measured at
+        // (8,70) with five key rows: 2^18 cells 4.7 s, 2^20 cells 8.8 s).
+        if (log2T > p.qb + 1) log2T = std::max(p.qb + 1, log2M - 12);
         if (log2T > 23) log2T = std::max(23, log2M - 12);   // cell tables <= 2^23
     }
     log2T = std::min(log2T, log2M);

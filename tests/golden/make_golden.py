@@ -22,9 +22,10 @@ from paper_2507_05045_amd.inputs import make_instance  # noqa: E402
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_configs.json")
 
 
-def entry(inst, r, res, slice_mod=0, slice_res=0, routine="", K=100):
+def entry(inst, r, res, slice_mod=0, slice_res=0, routine="", K=100, key_base=0):
     return dict(name=inst.name, m=inst.m, n=inst.n, K=K, seed=inst.seed,
-                planted=inst.planted is not None, key_rows=r, slice_mod=slice_mod,
+                planted=inst.planted is not None, key_rows=r, key_base=key_base,
+                slice_mod=slice_mod,
                 slice_res=slice_res, H=str(res.H), nsol=res.nsol,
                 solutions=["".join(str(int(v)) for v in s) for s in res.solutions],
                 routine=routine)
@@ -79,6 +80,25 @@ def main():
         res = O.mitm(inst.A, inst.d, 4, lm, rho, rho + 1)
         out.append(entry(inst, 4, res, mod, rho, routine=f"mitm mod 2^{lm}", K=K))
         print(inst.name, rho, out[-1]["H"], out[-1]["nsol"], f"{time.time() - t0:.1f}s", flush=True)
+    # Five key rows in the mixed radix rowsum_i + 1 (the paper's n*D radix
+    # overflows int64 at (9,80)): (6,50) solved whole, (8,70) and (9,80)
+    # sampled by residue class of the mixed-radix left key.
+    for planted in (False, True):
+        inst = make_instance(6, 50, 0, planted=planted)
+        out.append(entry(inst, 5, O.ss_heap(inst.A, inst.d, 5, key_base=1), routine="ss_heap",
+                         key_base=1))
+        print(inst.name, "r5", out[-1]["H"], out[-1]["nsol"], f"{time.time() - t0:.1f}s",
+              flush=True)
+    for (m, n), lm in [((8, 70), 20), ((9, 80), 24)]:
+        mod = 1 << lm
+        for planted in (False, True):
+            inst = make_instance(m, n, 0, planted=planted)
+            rho = (O.left_key(inst.A, inst.d, inst.planted, 5, key_base=1) % mod
+                   if planted else 12345)
+            res = O.mitm(inst.A, inst.d, 5, lm, rho, rho + 1, key_base=1)
+            out.append(entry(inst, 5, res, mod, rho, routine=f"mitm mod 2^{lm}", key_base=1))
+            print(inst.name, "r5", rho, out[-1]["H"], out[-1]["nsol"],
+                  f"{time.time() - t0:.1f}s", flush=True)
     with open(OUT, "w") as f:
         json.dump(out, f, indent=1)
     print("wrote", OUT)

@@ -77,6 +77,51 @@ def test_small_random_vs_brute_force(case):
             same(g, ref, f"M=2^{lm} T=2^{lc} P={parts} vector join {case} {seed}")
 
 
+WIDE = [
+    dict(m=4, n=18, K=3, zero=3, r=4),      # full digits (s_i = rowsum_i) are common
+    dict(m=5, n=22, K=8, zero=0, r=3),
+    dict(m=6, n=24, K=100, zero=0, r=5),
+]
+
+
+@pytest.mark.parametrize("case", WIDE, ids=lambda c: "m{m}n{n}K{K}z{zero}r{r}".format(**c))
+def test_mixed_radix_key_vs_brute_force(case):
+    """key_base = 1: radix rowsum_i + 1 per key row.  Slices select on the
+    mixed-radix left key, so the oracle takes the same key_base."""
+    r = case["r"]
+    for seed in range(2):
+        inst = random_small(case["m"], case["n"], 760 + seed, K=case["K"],
+                            zero_cols=case["zero"], planted=True)
+        say("mixed radix", case, "seed", seed)
+        ref = O.brute(inst.A, inst.d, key_rows=r, key_base=1)
+        assert ref.H == O.brute(inst.A, inst.d, key_rows=r).H      # same hits, other key
+        same(gsolve(inst.A, inst.d, key_rows=r, key_base=1), ref, f"default {case} {seed}")
+        same(gsolve(inst.A, inst.d, key_rows=r, key_base=1, verify_join=1), ref,
+             f"vector join {case} {seed}")
+        for lm, lc, parts, jv in [(5, 2, 3, 2), (6, 3, 16, 1)]:
+            g = gsolve(inst.A, inst.d, key_rows=r, key_base=1, log2_m=lm, log2_cells=lc,
+                       parts=parts, join_variant=jv)
+            same(g, ref, f"M=2^{lm} T=2^{lc} P={parts} join={jv} {case} {seed}")
+        for s in (0, 5):
+            o = O.brute(inst.A, inst.d, key_rows=r, slice_mod=8, slice_res=s, key_base=1)
+            g = gsolve(inst.A, inst.d, key_rows=r, key_base=1, slice_mod=8, slice_res=s)
+            same(g, o, f"slice 8/{s} {case} {seed}")
+
+
+def test_mixed_radix_carry_instance_and_bad_radix():
+    from paper_2507_05045_amd import msp
+    # Row 1 = x1 + x2, row 2 = x3 + .. + x6, d = (0, 2): C(4, 2) = 6 hits; a
+    # radix one too small would add 4 carries from s1 = 2.
+    A = np.array([[1, 1, 0, 0, 0, 0], [0, 0, 1, 1, 1, 1]], dtype=np.int32)
+    d = np.array([0, 2], dtype=np.int32)
+    ref = O.brute(A, d, key_rows=2, key_base=1)
+    assert ref.H == 6 and ref.nsol == 6
+    same(gsolve(A, d, key_rows=2, key_base=1), ref, "carry instance")
+    same(gsolve(A, d, key_rows=2, key_base=1, log2_m=2, log2_cells=1), ref, "carry, hash")
+    with pytest.raises(msp.MspError):
+        gsolve(A, d, key_rows=2, key_base=2)
+
+
 @pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 7])
 def test_tiny_and_empty_quarters(n):
     A = np.array([[2] * n, [1] * n, [3] * n], dtype=np.int32)
@@ -166,11 +211,12 @@ def test_full_configs_vs_oracle(cfg):
             continue
         inst = _golden_instance(e)
         say("config", e["name"])
-        g = gsolve(inst.A, inst.d, key_rows=e["key_rows"])
+        kb = e.get("key_base", 0)
+        g = gsolve(inst.A, inst.d, key_rows=e["key_rows"], key_base=kb)
         same(g, _golden_result(e, n), e["name"])
         if inst.planted is not None:
             assert any(np.array_equal(s, inst.planted) for s in g.solutions)
-        v = gsolve(inst.A, inst.d, key_rows=e["key_rows"], verify_join=1)
+        v = gsolve(inst.A, inst.d, key_rows=e["key_rows"], key_base=kb, verify_join=1)
         same(v, _golden_result(e, n), e["name"] + " vector join")
 
 
@@ -182,13 +228,15 @@ def test_large_configs_sampled_residue_classes(cfg):
         if (e["m"], e["n"], e.get("K", 100)) != (m, n, K):
             continue
         inst = _golden_instance(e)
-        say("sampled", e["name"], e["slice_mod"], e["slice_res"])
-        g = gsolve(inst.A, inst.d, key_rows=4, slice_mod=e["slice_mod"], slice_res=e["slice_res"])
+        r, kb = e["key_rows"], e.get("key_base", 0)
+        say("sampled", e["name"], "r", r, "key_base", kb, e["slice_mod"], e["slice_res"])
+        g = gsolve(inst.A, inst.d, key_rows=r, key_base=kb, slice_mod=e["slice_mod"],
+                   slice_res=e["slice_res"])
         same(g, _golden_result(e, n), f"{e['name']} rho={e['slice_res']}")
         if inst.planted is not None:
             assert any(np.array_equal(s, inst.planted) for s in g.solutions)
-        v = gsolve(inst.A, inst.d, key_rows=4, slice_mod=e["slice_mod"], slice_res=e["slice_res"],
-                   verify_join=1)
+        v = gsolve(inst.A, inst.d, key_rows=r, key_base=kb, slice_mod=e["slice_mod"],
+                   slice_res=e["slice_res"], verify_join=1)
         same(v, _golden_result(e, n), f"{e['name']} rho={e['slice_res']} vector join")
 
 
