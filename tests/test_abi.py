@@ -72,3 +72,41 @@ def test_solve_without_gpu_fails_loudly():
         ctx.solve(use_torch=False)
     assert e.value.code == -10
     ctx.close()
+
+
+def _c_layout(tmp_path, struct, fields):
+    """sizeof and offsetof of a header struct, from a C program built by gcc."""
+    import subprocess
+    src = tmp_path / "layout.c"
+    body = "".join(f'    printf("%zu\\n", offsetof({struct}, {f}));\n' for f in fields)
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "msp.h"\n'
+                   f'int main(void) {{\n    printf("%zu\\n", sizeof({struct}));\n{body}'
+                   '    return 0;\n}\n')
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src),
+                           "-o", str(exe)])
+    out = subprocess.check_output([str(exe)], text=True).split()
+    return int(out[0]), [int(v) for v in out[1:]]
+
+
+@pytest.mark.parametrize("struct", ["msp_opts", "msp_stats_t", "msp_batch_opts"])
+def test_binding_structs_match_the_header(tmp_path, struct):
+    from paper_2507_05045_amd import msp
+    cls = getattr(msp, struct)
+    names = [f for f, _ in cls._fields_]
+    size, offs = _c_layout(tmp_path, struct, names)
+    assert C.sizeof(cls) == size, struct
+    assert [getattr(cls, f).offset for f in names] == offs, struct
+
+
+def test_mixed_radix_key_fits_a_fifth_row():
+    """key_base = 1 (radix rowsum_i + 1) holds five key rows at (9,80) where
+    the radix n*D overflows int64; an unknown key_base is rejected."""
+    from paper_2507_05045_amd import msp
+    from paper_2507_05045_amd.inputs import make_instance
+    inst = make_instance(9, 80, 0)
+    ctx = msp.Context(inst.A, inst.d)
+    assert ctx.workspace_bytes(msp.msp_default_opts(key_rows=5)) == 0
+    assert ctx.workspace_bytes(msp.msp_default_opts(key_rows=5, key_base=1)) > 0
+    assert ctx.workspace_bytes(msp.msp_default_opts(key_rows=4, key_base=2)) == 0
+    ctx.close()
