@@ -366,8 +366,9 @@ def main():
                 "avg_launch_ms": avg_s * 1e3,
                 "algorithmic": "1 int32 compare per 1-D hit"}
     else:
-        key = {"ms_scatter": "k_scatter_staged", "ms_join": "k_join_light",
-               "ms_count": "k_bucket", "ms_quarters": "k_quarter_gen"}.get(dom, dom)
+        join_k = "k_join_grouped" if flat[0]["join_grouped"] else "k_join_light"
+        key = {"ms_scatter": "k_scatter_staged", "ms_join": join_k,
+               "ms_count": "k_count", "ms_quarters": "k_quarter_gen"}.get(dom, dom)
         bytes_per_launch = records * rec_bytes / max(windows, 1)
         avg_s = tot[dom] / 1e3 / max(windows, 1)
         achieved = bytes_per_launch / avg_s / 1e9

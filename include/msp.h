@@ -114,6 +114,8 @@ typedef struct {
     int32_t  complete;        /* 1: every residue window was processed               */
     int32_t  vector_join;     /* 1: equal-key runs were decided by the vector join   */
     uint64_t windows_total;   /* residue windows of the whole (sliced) solve         */
+    int32_t  join_grouped;    /* hash buckets: 1 = contiguous key groups, 0 = chains */
+    int32_t  key_base;        /* the key radix used (msp_opts.key_base)              */
 } msp_stats_t;
 
 /* Copies A (row-major m*n int32) and d (m int32); the caller may free both

@@ -669,6 +669,8 @@ void job_init_stats(Job &j) {
     j.st.words = p.W;
     j.st.record_bytes = rec_bytes(p.W);
     j.st.vector_join = p.vjoin;
+    j.st.join_grouped = p.exact ? 0 : p.join_grouped;
+    j.st.key_base = j.o.key_base;
     j.st.complete = 1;
     j.st.windows_total = (j.P.z.ncells + j.P.z.kwin - 1) / std::max<uint64_t>(j.P.z.kwin, 1);
 }

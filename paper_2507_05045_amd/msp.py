@@ -49,7 +49,8 @@ class msp_stats_t(C.Structure):
                 ("record_bytes", C.c_uint64), ("log2_m", C.c_int32), ("log2_cells", C.c_int32),
                 ("parts", C.c_int32), ("key_rows", C.c_int32), ("exact_buckets", C.c_int32),
                 ("words", C.c_int32), ("complete", C.c_int32), ("vector_join", C.c_int32),
-                ("windows_total", C.c_uint64)]
+                ("windows_total", C.c_uint64), ("join_grouped", C.c_int32),
+                ("key_base", C.c_int32)]
 
 
 class msp_batch_opts(C.Structure):
