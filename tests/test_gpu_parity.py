@@ -120,6 +120,13 @@ def test_mixed_radix_carry_instance_and_bad_radix():
     same(gsolve(A, d, key_rows=2, key_base=1, log2_m=2, log2_cells=1), ref, "carry, hash")
     with pytest.raises(msp.MspError):
         gsolve(A, d, key_rows=2, key_base=2)
+    ctx = msp.Context(A, d)
+    for jv in (1, 2):
+        ctx.solve(key_rows=2, key_base=1, log2_m=2, log2_cells=1, join_variant=jv)
+        st = ctx.stats()
+        assert (st["key_base"], st["join_grouped"], st["exact_buckets"]) == (1, jv - 1, 0)
+        assert ctx.hits() == 6
+    ctx.close()
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 7])
