@@ -124,9 +124,11 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
         place *= o.key_base ? rs + 1 : (int64_t)n * D;
         if (i + 1 < r && place >= ((__int128)1 << 63)) return MSP_E_KEY_OVERFLOW;
     }
+    // d_i <= rowsum_i on every key row keeps K_d below the largest key.
     int64_t kd = 0;
-    for (int i = 0; i < r; ++i) kd += pw[i] * (int64_t)c->d[i];
-    p.Kd = P.infeasible ? 0 : kd;
+    if (!P.infeasible)
+        for (int i = 0; i < r; ++i) kd += pw[i] * (int64_t)c->d[i];
+    p.Kd = kd;
     P.colw.assign(n, 0);
     for (int j = 0; j < n; ++j) {
         int64_t s = 0;

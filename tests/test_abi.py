@@ -110,3 +110,14 @@ def test_mixed_radix_key_fits_a_fifth_row():
     assert ctx.workspace_bytes(msp.msp_default_opts(key_rows=5, key_base=1)) > 0
     assert ctx.workspace_bytes(msp.msp_default_opts(key_rows=4, key_base=2)) == 0
     ctx.close()
+
+
+def test_target_far_above_a_key_row_sum_is_planned_as_empty():
+    """d_i > rowsum_i on a key row: no x can hit, the plan needs no key
+    arithmetic on d (a d_i near 2^31 would overflow it)."""
+    from paper_2507_05045_amd import msp
+    A = np.full((5, 40), 99)
+    ctx = msp.Context(A, [2 ** 31 - 1] * 5)
+    for kb in (0, 1):
+        assert ctx.workspace_bytes(msp.msp_default_opts(key_rows=4, key_base=kb)) > 0
+    ctx.close()
