@@ -366,7 +366,7 @@ def main():
                 "avg_launch_ms": avg_s * 1e3,
                 "algorithmic": "1 int32 compare per 1-D hit"}
     else:
-        join_k = "k_join_grouped" if flat[0]["join_grouped"] else "k_join_light"
+        join_k = ("k_join_light", "k_join_grouped", "k_join_pairs")[flat[0]["join_grouped"]]
         key = {"ms_scatter": "k_scatter_staged", "ms_join": join_k,
                "ms_count": "k_count", "ms_quarters": "k_quarter_gen"}.get(dom, dom)
         bytes_per_launch = records * rec_bytes / max(windows, 1)

@@ -74,7 +74,9 @@ typedef struct {
     int32_t  join_variant;    /* bucket join: 0 = planner's choice (from the expected
                                  number of equal-key records per key), 1 = per-slot
                                  chains (groups of ~1), 2 = contiguous key groups
-                                 (groups of ~5-250)                                     */
+                                 (groups of ~5-250), 3 = one wavefront per bucket
+                                 comparing keys directly (buckets of a few dozen
+                                 records)                                           */
     int32_t  verify_join;     /* 1: decide every equal-key run pair by an exact hash
                                  join on (key, packed non-key rows) instead of checking
                                  its |G_L||G_R| pairs one by one (the sort/search check
@@ -114,7 +116,8 @@ typedef struct {
     int32_t  complete;        /* 1: every residue window was processed               */
     int32_t  vector_join;     /* 1: equal-key runs were decided by the vector join   */
     uint64_t windows_total;   /* residue windows of the whole (sliced) solve         */
-    int32_t  join_grouped;    /* hash buckets: 1 = contiguous key groups, 0 = chains */
+    int32_t  join_grouped;    /* hash buckets: 0 = chains, 1 = contiguous key groups,
+                                 2 = one wavefront per bucket                        */
     int32_t  key_base;        /* the key radix used (msp_opts.key_base)              */
 } msp_stats_t;
 

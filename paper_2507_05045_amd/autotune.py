@@ -100,7 +100,7 @@ def tune(A, d, key_rows: int = 1, max_seconds: float = 20.0, slice_bits: Optiona
                 continue
             # multiples of 8 let the kernels map whole parts to each XCD
             for p2 in sorted({parts, parts * 2, parts * 4, 16, 32, 64}):
-                for jv in ((0,) if base["exact_buckets"] else (1, 2)):
+                for jv in ((0,) if base["exact_buckets"] else (1, 2, 3)):
                     cands.append(dict(log2_m=m2, log2_cells=c2, parts=min(p2, 256),
                                       join_variant=jv))
     t_end = time.time() + max_seconds

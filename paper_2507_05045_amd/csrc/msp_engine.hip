@@ -188,9 +188,9 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
     p.khb = std::max(0, lgKd - log2M);
     p.slice_mod = o.slice_mod;
     p.slice_res = o.slice_res;
-    if (o.join_variant < 0 || o.join_variant > 2) return MSP_E_INVALID;
+    if (o.join_variant < 0 || o.join_variant > 3) return MSP_E_INVALID;
     if (o.join_variant) {
-        p.join_grouped = o.join_variant == 2 ? 1 : 0;
+        p.join_grouped = o.join_variant == 3 ? 2 : o.join_variant == 2 ? 1 : 0;
     } else {
         // Expected equal-key records per side near K_d: 2^h_L spread over the
         // key rows' half sums, each about normal with variance sum a_ij^2 / 4
@@ -206,6 +206,11 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
             if (s2 > 0.0) lg -= 0.5 * std::log2(2.0 * 3.141592653589793 * s2);
         }
         p.join_grouped = lg >= std::log2(6.0) ? 1 : 0;
+        // A few dozen records per bucket and side (a modulus forced up by the
+        // key room): one wavefront per bucket.
+        const uint64_t per_bucket =
+            std::max((uint64_t)p.Q[0] * p.Q[1], (uint64_t)p.Q[2] * p.Q[3]) >> std::min(log2M, 62);
+        if (!p.exact && per_bucket <= 48) p.join_grouped = 2;
     }
     if (o.verify_join < 0 || o.verify_join > 1) return MSP_E_INVALID;
     p.vjoin = (o.verify_join && p.W > 0) ? 1 : 0;

@@ -27,7 +27,7 @@ struct Plan {
     int32_t parts;                   // work-groups per cell in count/scatter
     int32_t exact;                   // 1: M > K_d, each bucket is one key value
     int32_t hsh;                     // qa + qb: shift of the key in Rec::hdr
-    int32_t join_grouped;            // light join variant: 0 chains, 1 contiguous groups
+    int32_t join_grouped;            // join variant: 0 chains, 1 contiguous groups, 2 pairs
     int32_t vjoin;                   // exact runs decided by the vector hash join
     int32_t khb;                     // bits of key >> log2M (every stored key is in [0, K_d])
     int64_t Kd;                      // target key

@@ -828,6 +828,86 @@ __global__ __launch_bounds__(256) void k_join_light(Plan p, const uint32_t *__re
     if (t == 0) add_u128(&scal[S_H_LO], &scal[S_H_HI], tot);
 }
 
+// Join of buckets that hold a few dozen records per side (a large modulus,
+// as many key rows force): one wavefront per bucket and no LDS.  The lanes
+// hold 64 left keys at a time; right records follow 64 at a time, one per
+// lane, and each left key is broadcast to the wavefront in turn.  A key match
+// is a 1-D hit, whose rows are then read and compared.  Buckets with more
+// than kPairsCap left records are handed to k_join_heavy.
+constexpr uint32_t kPairsCap = 256;
+
+template <typename KT>
+__device__ __forceinline__ KT wave_bcast(KT v, uint32_t lane) {
+    if constexpr (sizeof(KT) == 4) {
+        return (KT)__builtin_amdgcn_readlane((int)v, (int)lane);
+    } else {
+        const uint64_t u = (uint64_t)v;
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, (int)lane);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), (int)lane);
+        return (KT)(((uint64_t)hi << 32) | lo);
+    }
+}
+
+template <int W, bool K32>
+__global__ __launch_bounds__(256) void k_join_pairs(Plan p, const uint32_t *__restrict__ offL,
+                                                   const uint32_t *__restrict__ offR,
+                                                   const Rec<W> *__restrict__ L,
+                                                   const Rec<W> *__restrict__ R, uint32_t *heavy,
+                                                   uint64_t *scal, uint64_t *sol, uint64_t cap,
+                                                   QPtrs<W> qs, uint32_t nb) {
+    constexpr int WV = W > 0 ? W : 1;
+    using KT = typename std::conditional<K32, uint32_t, int64_t>::type;
+    __shared__ uint64_t s_s4[4];
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t P = p.parts;
+    uint64_t hits = 0;
+    // Bucket ranges are read by the whole wavefront, so every branch below
+    // is uniform per wavefront.
+    for (uint32_t b = blockIdx.x * 4u + (threadIdx.x >> 6); b < nb; b += gridDim.x * 4u) {
+        const uint32_t l0 = offL[b * P], nl = offL[(b + 1) * P] - l0;
+        const uint32_t r0 = offR[b * P], nr = offR[(b + 1) * P] - r0;
+        if (nl == 0 || nr == 0) continue;
+        if (nl > kPairsCap) {
+            if (lane == 0) heavy[atomicAdd((unsigned long long *)&scal[S_NHEAVY], 1ull)] = b;
+            continue;
+        }
+        for (uint32_t i0 = 0; i0 < nl; i0 += 64) {
+            const uint32_t ni = min(64u, nl - i0);
+            const KT lk = (KT)(L[l0 + i0 + min(lane, ni - 1)].hdr >> p.hsh);
+            for (uint32_t j0 = 0; j0 < nr; j0 += 64) {
+                const bool rin = j0 + lane < nr;
+                const uint32_t rj = r0 + j0 + min(lane, nr - j0 - 1);
+                const uint64_t rh = R[rj].hdr;
+                const KT rk = (KT)(rh >> p.hsh);
+                for (uint32_t i = 0; i < ni; ++i) {
+                    const KT k = wave_bcast(lk, i);
+                    if (rin && k == rk) {
+                        ++hits;
+                        const uint32_t li = l0 + i0 + i;
+                        if (W == 0) {
+                            atomicAdd((unsigned long long *)&scal[S_NSOL], 1ull);
+                            if (scal[S_STORED] < cap)
+                                emit_solution(sol, cap, &scal[S_STORED],
+                                              half_mask(p, qs, 0, L[li].hdr),
+                                              half_mask(p, qs, 1, rh));
+                        } else {
+                            bool ok = true;
+#pragma unroll
+                            for (int w = 0; w < WV; ++w) ok = ok && (L[li].vec[w] == R[rj].vec[w]);
+                            if (ok)
+                                emit_solution(sol, cap, &scal[S_NSOL],
+                                              half_mask(p, qs, 0, L[li].hdr),
+                                              half_mask(p, qs, 1, rh));
+                        }
+                    }
+                }
+            }
+        }
+    }
+    const uint64_t tot = block_sum_u64(hits, s_s4);
+    if (threadIdx.x == 0) add_u128(&scal[S_H_LO], &scal[S_H_HI], tot);
+}
+
 // Hash of a (key, packed rows) pair for the vector join table.
 template <int W>
 __device__ __forceinline__ uint32_t kv_hash(int64_t key, const uint32_t *v) {
@@ -1928,6 +2008,14 @@ static hipError_t join_impl(const Plan &p, const DevBufs &b, int32_t K, uint64_t
         MSP_GROUPED(true, true);
     else if (p.vjoin)
         MSP_GROUPED(false, true);
+    else if (p.join_grouped == 2 && p.khb <= 32)
+        hipLaunchKernelGGL((k_join_pairs<W, true>), dim3(std::min<uint32_t>((nb + 3) / 4, 8192)),
+                           dim3(256), 0, st, p, b.off[0], b.off[1], L, R, b.heavy, b.scal, b.sol,
+                           cap, sorted_quarters<W>(b), nb);
+    else if (p.join_grouped == 2)
+        hipLaunchKernelGGL((k_join_pairs<W, false>), dim3(std::min<uint32_t>((nb + 3) / 4, 8192)),
+                           dim3(256), 0, st, p, b.off[0], b.off[1], L, R, b.heavy, b.scal, b.sol,
+                           cap, sorted_quarters<W>(b), nb);
     else if (p.join_grouped && p.khb <= 32)
         MSP_GROUPED(true, false);
     else if (p.join_grouped)

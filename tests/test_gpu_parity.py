@@ -67,7 +67,7 @@ def test_small_random_vs_brute_force(case):
         # force hash buckets (modulus below K_d) and a few cell layouts
         # parts 8 and 16 take the XCD-aware work-group mapping
         for lm, lc, parts, jv in [(3, 1, 1, 1), (5, 2, 3, 2), (6, 6, 2, 0), (6, 3, 2, 2),
-                                  (5, 2, 8, 1), (6, 3, 16, 2)]:
+                                  (5, 2, 8, 1), (6, 3, 16, 2), (3, 1, 2, 3), (8, 3, 8, 3)]:
             g = gsolve(inst.A, inst.d, key_rows=case["r"], log2_m=lm, log2_cells=lc, parts=parts,
                        join_variant=jv)
             same(g, ref, f"M=2^{lm} T=2^{lc} P={parts} join={jv} {case} {seed}")
@@ -98,7 +98,7 @@ def test_mixed_radix_key_vs_brute_force(case):
         same(gsolve(inst.A, inst.d, key_rows=r, key_base=1), ref, f"default {case} {seed}")
         same(gsolve(inst.A, inst.d, key_rows=r, key_base=1, verify_join=1), ref,
              f"vector join {case} {seed}")
-        for lm, lc, parts, jv in [(5, 2, 3, 2), (6, 3, 16, 1)]:
+        for lm, lc, parts, jv in [(5, 2, 3, 2), (6, 3, 16, 1), (7, 3, 8, 3)]:
             g = gsolve(inst.A, inst.d, key_rows=r, key_base=1, log2_m=lm, log2_cells=lc,
                        parts=parts, join_variant=jv)
             same(g, ref, f"M=2^{lm} T=2^{lc} P={parts} join={jv} {case} {seed}")
@@ -121,7 +121,7 @@ def test_mixed_radix_carry_instance_and_bad_radix():
     with pytest.raises(msp.MspError):
         gsolve(A, d, key_rows=2, key_base=2)
     ctx = msp.Context(A, d)
-    for jv in (1, 2):
+    for jv in (1, 2, 3):
         ctx.solve(key_rows=2, key_base=1, log2_m=2, log2_cells=1, join_variant=jv)
         st = ctx.stats()
         assert (st["key_base"], st["join_grouped"], st["exact_buckets"]) == (1, jv - 1, 0)
