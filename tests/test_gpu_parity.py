@@ -225,6 +225,12 @@ def test_full_configs_vs_oracle(cfg):
             assert any(np.array_equal(s, inst.planted) for s in g.solutions)
         v = gsolve(inst.A, inst.d, key_rows=e["key_rows"], key_base=kb, verify_join=1)
         same(v, _golden_result(e, n), e["name"] + " vector join")
+        if e["key_rows"] >= 4:
+            # ~256 records per bucket and side: the wavefront-per-bucket join
+            # in several 64-record chunks, and the heavy join past 256.
+            for jv in (1, 3):
+                g = gsolve(inst.A, inst.d, key_rows=e["key_rows"], key_base=kb, join_variant=jv)
+                same(g, _golden_result(e, n), e["name"] + f" join variant {jv}")
 
 
 @pytest.mark.parametrize("cfg", ["8_70", "9_80", "10_90", "8_70_K50", "8_70_K200"])
