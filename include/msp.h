@@ -9,6 +9,8 @@
  * surrogate constraint of Section 1 (eq. surrogate): with D = max(100,
  * max a_ij + 1) and base B = n*D, key(x) = sum_{i<r} B^i (a_i . x) and
  * K_d = sum_{i<r} B^i d_i; key(x) = K_d holds exactly when rows 1..r hold.
+ * msp_opts.key_base = 1 gives row i the mixed radix rowsum_i + 1 instead of
+ * B (the same exactness with a smaller key, so more rows fit in int64).
  * Every solution of that 1-D subset-sum problem (a "1-D hit") is enumerated
  * with a Schroeppel-Shamir style four-list meet in the middle (Algorithm 1,
  * with the heaps replaced by residue classes of the key), and every hit is
@@ -44,8 +46,8 @@ extern "C" {
 #define MSP_OK               0
 #define MSP_E_INVALID      (-1)  /* null pointer, m<1, n<1, a_ij<0, d_i<0, bad option */
 #define MSP_E_RANGE        (-2)  /* some row sum exceeds 65534 (uint16 row packing)    */
-#define MSP_E_KEY_OVERFLOW (-3)  /* sum_{i<r} B^i rowsum_i >= 2^63                      */
-#define MSP_E_UNSUPPORTED  (-4)  /* m > 10 or n > 92 or m - r > 10                      */
+#define MSP_E_KEY_OVERFLOW (-3)  /* largest key (all rows at their row sums) >= 2^63   */
+#define MSP_E_UNSUPPORTED  (-4)  /* m > 16, n > 92, m - r > 10, or > 2^24 cells needed */
 #define MSP_E_NOMEM        (-5)  /* device workspace does not fit the budget            */
 #define MSP_E_DEVICE       (-6)  /* HIP runtime error; the context is poisoned          */
 #define MSP_E_CANCELLED    (-7)  /* solve cancelled                                     */
