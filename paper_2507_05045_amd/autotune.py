@@ -110,7 +110,10 @@ def tune(A, d, key_rows: int = 1, max_seconds: float = 20.0, slice_bits: Optiona
             break
         try:
             ctx.solve(key_rows=key_rows, key_base=key_base, **c, **sl)
-        except msp.MspError:
+        except msp.MspError as e:
+            if e.code == msp.MSP_E_DEVICE:        # the context is poisoned: start afresh
+                ctx.close()
+                ctx = msp.Context(A, d)
             continue
         h = ctx.hits()
         if ref_h is None:

@@ -247,6 +247,10 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
     } else {
         kwin = std::max<uint64_t>(1, std::min<uint64_t>(z.ncells, want / per_cell));
     }
+    // At most 2^23 buckets per window: the grouped join launches one
+    // work-group of 256 lanes per bucket, and a HIP grid holds fewer than
+    // 2^32 lanes.  Only a large modulus (many key rows) reaches this.
+    kwin = std::min<uint64_t>(kwin, std::max<uint64_t>(1, ((uint64_t)1 << 23) >> p.log2F));
     int parts = o.parts;
     if (!parts) {
         const uint64_t target = 8192;            // work-groups per launch (tuned: 4x fill)

@@ -129,6 +129,20 @@ def test_mixed_radix_carry_instance_and_bad_radix():
     ctx.close()
 
 
+def test_many_buckets_per_window_every_join():
+    """Five mixed-radix key rows at (8,70) force M = 2^30: windows would hold
+    2^24+ buckets, beyond one work-group per bucket in a HIP grid.  Every join
+    variant and the vector join must run and agree on a 1/64 slice."""
+    inst = make_instance(8, 70, 0, planted=True)
+    kw = dict(key_rows=5, key_base=1, slice_mod=64, slice_res=0)
+    ref = gsolve(inst.A, inst.d, **kw)
+    assert ref.H > 0
+    for extra in (dict(join_variant=1), dict(join_variant=2), dict(join_variant=3),
+                  dict(verify_join=1), dict(log2_cells=19, join_variant=2)):
+        say("many buckets", extra)
+        same(gsolve(inst.A, inst.d, **kw, **extra), ref, f"{extra}")
+
+
 @pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 7])
 def test_tiny_and_empty_quarters(n):
     A = np.array([[2] * n, [1] * n, [3] * n], dtype=np.int32)
