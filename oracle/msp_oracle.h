@@ -26,10 +26,15 @@
  * A,B,C,D of size ~n/4"): contiguous columns, h_L = ceil(n/2),
  * q_A = ceil(h_L/2), q_B = floor(h_L/2), q_C = ceil((n-h_L)/2), q_D the rest.
  *
- * Pins (tests/test_oracle.py): orc_brute, orc_dp_count_row,
- * orc_dp_count_2rows and orc_ss_heap are pinned by closed forms, brute force
- * and the paper's expected number of solutions; orc_mitm_residues is pinned
- * against brute force (n <= 30) and against orc_ss_heap (n <= 50).  Its
+ * Pins (tests/test_oracle.py, tests/test_oracle_mitm_pins.py): orc_brute,
+ * orc_dp_count_row, orc_dp_count_2rows and orc_ss_heap are pinned by closed
+ * forms, brute force and the paper's expected number of solutions.
+ * orc_mitm_residues is pinned against brute force (n <= 22, r = 1..3), and
+ * against orc_ss_heap on whole solves of (4,30) (r = 1), of the (6,50) seed-0
+ * instance and its planted twin (r = 1, 2, 3; moduli 2^9..2^12 and a split
+ * class range; also r = 1 against the row-1 counting DP), of the (6,50)
+ * planted twin with five key rows in the mixed radix, and of the (5,40) pair
+ * with r = 2 (two moduli, a split range, and the 2-row counting DP).  Its
  * results for the n = 70..90 classes are parity unpinned beyond that: they
  * rest on the same code being right at larger n.
  *
