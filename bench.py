@@ -2,9 +2,11 @@
 
 One step = one pass of the whole hot path (quarter lists, residue-cell
 sort, bucket count/scatter, join, verify) over one batch of synthetic
-instances.  The default workload is the (m, n) = (6, 50) instance of the
-hard family (a_ij uniform in [0, 99], d_i = floor(row sum / 2), seed 0) plus
-its planted twin, with row 1 as the 1-D key.
+instances.  The default workload is the (m, n) = (9, 80) instance of the
+hard family (a_ij uniform in [0, 99], d_i = floor(row sum / 2), seed 0) with
+rows 1-4 folded into the int64 key: each timed step solves the residue slice
+k_L mod 64 = 0 of it (warm-up steps solve other slices), and after the timed
+steps the whole (9,80) solve is timed once and reported in the same line.
 
 Prints ONE JSON line (rank 0).  Everything runs on one GPU; --gpus above 1
 is refused.
@@ -64,8 +66,11 @@ WORKLOADS = {
                  desc="(4,30) seed 0 + planted twin, key row 1"),
     "8_70": dict(m=8, n=70, key_rows=4, seeds=[0, 1, 2, 3, 4], planted=False, slice_mod=0,
                  desc="(8,70) seeds 0-4, int64 key of rows 1-4 (base 7000)"),
-    "9_80": dict(m=9, n=80, key_rows=4, seeds=[0], planted=False, slice_mod=0,
-                 desc="(9,80) seed 0 full solve, key rows 1-4 (base 8000)"),
+    "9_80": dict(m=9, n=80, key_rows=4, seeds=[0], planted=False, slice_mod=64, whole=True,
+                 desc="(9,80) seed 0, key rows 1-4 (base 8000): steps solve the residue slice "
+                      "k_L mod 64 = 0, then one whole solve"),
+    "9_80_whole": dict(m=9, n=80, key_rows=4, seeds=[0], planted=False, slice_mod=0,
+                       desc="(9,80) seed 0 whole solve per step, key rows 1-4 (base 8000)"),
     "10_90s": dict(m=10, n=90, key_rows=4, seeds=[0], planted=False, slice_mod=64,
                    desc="(10,90) seed 0, residue slice k_L mod 64 = 0, key rows 1-4 (base 9000)"),
     # Coefficient range K (Section 4's classes K = 50, 100, 200): a_ij in [0, K).
@@ -104,6 +109,20 @@ def build_instances(w):
     return out
 
 
+def host_cpu():
+    """CPU model and the cores this process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "host_cores": len(os.sched_getaffinity(0))}
+
+
 def cpu_baseline(w, insts, budget_s=30.0):
     """The oracle as it stands, single-threaded on the host, on a bounded
     sample: the smallest instance of the workload solved whole (n <= 50), or
@@ -116,7 +135,7 @@ def cpu_baseline(w, insts, budget_s=30.0):
         dt = time.perf_counter() - t
         return {"value": r.H / dt, "unit": "hits/s", "cores": 1, "kind": "oracle",
                 "sample": f"{inst.name}: whole solve by the heap Schroeppel-Shamir oracle, "
-                          f"H={r.H}, {dt:.2f} s"}
+                          f"H={r.H}, {dt:.2f} s", **host_cpu()}
     inst = insts[0]
     lm = {70: 20, 80: 24, 90: 26}.get(w["n"], 20)
     t = time.perf_counter()
@@ -129,7 +148,7 @@ def cpu_baseline(w, insts, budget_s=30.0):
     dt = time.perf_counter() - t
     return {"value": H / dt, "unit": "hits/s", "cores": 1, "kind": "oracle",
             "sample": f"{inst.name}: {k} residue classes mod 2^{lm} by the residue "
-                      f"meet-in-the-middle oracle, H={H}, {dt:.2f} s"}
+                      f"meet-in-the-middle oracle, H={H}, {dt:.2f} s", **host_cpu()}
 
 
 def _pct(xs, q):
@@ -266,7 +285,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="6_50", choices=sorted(WORKLOADS) + ["stream"])
+    ap.add_argument("--workload", default="9_80", choices=sorted(WORKLOADS) + ["stream"])
+    ap.add_argument("--no-whole", action="store_true",
+                    help="skip the whole solve after the timed slice steps (9_80)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--first-solution", action="store_true",
                     help="stop each solve at the first verified solution (time to first solution)")
@@ -308,20 +329,24 @@ def main():
     kw = dict(key_rows=w["key_rows"], key_base=w.get("key_base", 0), slice_mod=w["slice_mod"],
               slice_res=0,
               first_only=1 if args.first_solution else 0,
-              verify_join=1 if args.verify_join else 0)
+              # The timed steps check every 1-D hit pair by pair (the metric
+              # is hits verified); --verify-join decides runs by the hash join.
+              verify_join=1 if args.verify_join else 2)
     # The plan (modulus, cells, parts, join variant) the autotuner picked for
     # each instance class; the planner's defaults where it has no entry.
     plans = [autotune.lookup(i.A, w["key_rows"], w.get("key_base", 0)) or {} for i in insts]
 
-    def step():
+    def step(res=0):
         stats = []
         for c, pl in zip(ctxs, plans):
-            c.solve(**kw, **pl)
+            c.solve(**{**kw, "slice_res": res}, **pl)
             stats.append(c.stats())
         return stats
 
-    for _ in range(args.warmup):
-        step()
+    # Sliced workloads warm up on slices of their own (residues 1, 2, ...);
+    # the timed steps all solve residue 0.
+    for k in range(args.warmup):
+        step((1 + k) % w["slice_mod"] if w["slice_mod"] else 0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     all_stats = []
@@ -332,6 +357,26 @@ def main():
     hits = sum(c.hits() for c in ctxs)
     nsol = [c.num_solutions() for c in ctxs]
     ms_step = dt * 1e3 / args.steps
+    whole = None
+    if w.get("whole") and not args.no_whole:
+        # One whole solve of every instance, timed on its own.
+        torch.cuda.synchronize()
+        tw = time.perf_counter()
+        wstats = []
+        for c, pl in zip(ctxs, plans):
+            # The whole solve takes the planner's choice of run check.
+            c.solve(**{**kw, "slice_mod": 0, "slice_res": 0, "verify_join": 0}, **pl)
+            wstats.append(c.stats())
+        torch.cuda.synchronize()
+        tw = time.perf_counter() - tw
+        whole = {"solve_s": tw, "H": [c.hits() for c in ctxs],
+                 "solutions": [c.num_solutions() for c in ctxs],
+                 "hits_per_s": sum(c.hits() for c in ctxs) / tw,
+                 "phase_s": {k: sum(s[k] for s in wstats) / 1e3 for k in
+                             ("ms_scatter", "ms_join", "ms_count", "ms_verify", "ms_scan",
+                              "ms_quarters")},
+                 "windows": [s["windows"] for s in wstats],
+                 "vector_join": [s["vector_join"] for s in wstats]}
 
     # Dominant kernel: the phase with the most time, from HIP events recorded
     # on the solve's stream inside the library (summed per step).
@@ -401,6 +446,8 @@ def main():
         "phase_ms_per_step": {k: v / args.steps for k, v in tot.items()},
         "roofline": roof,
     }
+    if whole is not None:
+        out["whole_solve"] = whole
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, insts)
     print(json.dumps(out), flush=True)

@@ -79,13 +79,16 @@ typedef struct {
                                  (groups of ~5-250), 3 = one wavefront per bucket
                                  comparing keys directly (buckets of a few dozen
                                  records)                                           */
-    int32_t  verify_join;     /* 1: decide every equal-key run pair by an exact hash
-                                 join on (key, packed non-key rows) instead of checking
-                                 its |G_L||G_R| pairs one by one (the sort/search check
-                                 of Algorithms 3-4 with an exact key in place of a
-                                 hash): a device-wide table for exact buckets, an LDS
-                                 table per bucket for hash buckets (buckets too large
-                                 for LDS keep the pairwise check).  Same H, |S| and
+    int32_t  verify_join;     /* how equal-key run pairs are decided: 1 = an exact
+                                 hash join on (key, packed non-key rows) (the sort/
+                                 search check of Algorithms 3-4 with an exact key in
+                                 place of a hash): a device-wide table for exact
+                                 buckets, an LDS table per bucket for hash buckets
+                                 (buckets too large for LDS keep the pairwise check);
+                                 2 = every one of the |G_L||G_R| pairs compared on its
+                                 own (1-D hits verified one by one); 0 = planner's
+                                 choice: the hash join when the expected equal-key
+                                 group holds >= 16 records per side.  Same H, |S| and
                                  solutions; no effect when every row is a key row   */
     int32_t  key_base;        /* radix of the surrogate key (Section 1, eq. surrogate):
                                  0 = B = n*D for every key row (D = max(100, max a_ij
@@ -121,7 +124,26 @@ typedef struct {
     int32_t  join_grouped;    /* hash buckets: 0 = chains, 1 = contiguous key groups,
                                  2 = one wavefront per bucket                        */
     int32_t  key_base;        /* the key radix used (msp_opts.key_base)              */
+    int32_t  reserved;
+    uint64_t cells_done;      /* residue cells processed, in cell order: the cells
+                                 k_first + i * k_step, i < cells_done (k_step = 1 and
+                                 k_first = 0 without a slice); all of them unless
+                                 first_only stopped early                            */
 } msp_stats_t;
+
+/* Device memory from the caller, e.g. a torch-allocated arena, so that the
+ * framework around the library owns all device memory: from this call on,
+ * every workspace the library allocates itself (msp_solve without a caller
+ * workspace, and the arena of msp_batch_solve and of a server) comes from
+ * alloc(bytes, user) and goes back through release(ptr, user) instead of
+ * hipMalloc / hipFree.  alloc returns device memory of the current device,
+ * aligned to 256 bytes, or NULL (the call that needed it then fails with
+ * MSP_E_NOMEM).  Each allocation is released through the pair that made it.
+ * Both NULL restores hipMalloc / hipFree; exactly one NULL is MSP_E_INVALID.
+ * Process-wide.  The callbacks may run on a server's scheduler thread. */
+typedef void *(*msp_alloc_fn)(size_t bytes, void *user);
+typedef void (*msp_release_fn)(void *ptr, void *user);
+int  msp_set_allocator(msp_alloc_fn alloc, msp_release_fn release, void *user);
 
 /* Copies A (row-major m*n int32) and d (m int32); the caller may free both
  * on return.  Validates the instance (see the error codes). */
@@ -186,6 +208,33 @@ int  msp_server_cancel(msp_server *s, uint64_t ticket);
 int  msp_server_times(msp_server *s, uint64_t ticket, double *t4);
 /* Finishes every queued request, then frees the server. */
 int  msp_server_stop(msp_server *s);
+
+/* The plan msp_solve would run with these options, made on the host only
+ * (no GPU needed), with the workspace shrunk to opts->workspace_bytes when
+ * that is non-zero.  Returns the planner's code: MSP_E_UNSUPPORTED when a
+ * launch of the plan would exceed the device's grid limits (2^32 work-items
+ * per dimension) even with one residue cell per window, MSP_E_NOMEM when the
+ * workspace cannot fit, MSP_E_INVALID for bad options. */
+typedef struct {
+    int32_t  key_rows, log2_m, log2_cells, log2_fine;  /* r, M = 2^log2_m, cells, fine buckets */
+    int32_t  parts;            /* work-groups per cell in count and scatter              */
+    int32_t  exact_buckets;    /* 1: each bucket holds one key value                     */
+    int32_t  words;            /* 32-bit words of packed non-key rows per record         */
+    int32_t  join_variant;     /* hash buckets: 0 chains, 1 key groups, 2 one wavefront  */
+    int32_t  vector_join;      /* 1: equal-key runs decided by the vector join           */
+    int32_t  key_base;         /* key radix (msp_opts.key_base)                          */
+    int32_t  infeasible;       /* 1: a key row cannot hold; no GPU work is done          */
+    int32_t  reserved;
+    uint64_t cells;            /* residue cells visited (all, or those of the slice)     */
+    uint64_t cells_per_window; /* planned; the count pass may halve it                   */
+    uint64_t windows;          /* planned windows                                        */
+    uint64_t window_records;   /* half records per side a window's buffers hold          */
+    uint64_t record_bytes;     /* bytes of one half record                               */
+    uint64_t workspace_bytes;  /* device workspace of the plan                           */
+    uint64_t max_grid_items;   /* largest work-item count of the window's launches whose
+                                  size the plan fixes (< 2^32)                           */
+} msp_plan_t;
+int  msp_plan(const msp_ctx *ctx, const msp_opts *opts, msp_plan_t *out);
 
 /* Device workspace bytes msp_solve would use with these options, the
  * plan shrunk to fit opts->workspace_bytes when that is non-zero (0 on

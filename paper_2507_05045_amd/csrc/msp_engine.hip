@@ -29,6 +29,9 @@ struct msp_ctx {
     msp_stats_t stats{};
     void *ws = nullptr;                // library-owned workspace (cached)
     size_t ws_bytes = 0;
+    msp_alloc_fn ws_alloc = nullptr;   // allocator that made ws (null: hipMalloc)
+    msp_release_fn ws_release = nullptr;
+    void *ws_user = nullptr;
     hipStream_t own_stream = nullptr;
     bool poisoned = false;
     std::atomic<int> busy{0};          // a solve or request is using this context
@@ -44,6 +47,51 @@ int lg2ceil(uint64_t x) {
 
 uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
+// Device memory for workspaces the library owns: hipMalloc/hipFree, or the
+// caller's allocator (msp_set_allocator).  Each allocation keeps the pair
+// that made it, so a later change of allocator still frees it correctly.
+struct DevAllocator {
+    msp_alloc_fn alloc = nullptr;
+    msp_release_fn release = nullptr;
+    void *user = nullptr;
+};
+std::mutex g_alloc_mu;
+DevAllocator g_alloc;
+
+struct DevMem {
+    void *ptr = nullptr;
+    DevAllocator by;
+};
+
+DevMem dev_alloc(uint64_t bytes) {
+    DevMem m;
+    {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        m.by = g_alloc;
+    }
+    if (m.by.alloc) {
+        m.ptr = m.by.alloc((size_t)bytes, m.by.user);
+        if (m.ptr && ((uintptr_t)m.ptr & 255u)) {     // the workspace layout needs 256-byte alignment
+            if (m.by.release) m.by.release(m.ptr, m.by.user);
+            m.ptr = nullptr;
+        }
+    } else if (hipMalloc(&m.ptr, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        m.ptr = nullptr;
+    }
+    return m;
+}
+
+void dev_free(DevMem &m) {
+    if (!m.ptr) return;
+    if (m.by.alloc) {
+        if (m.by.release) m.by.release(m.ptr, m.by.user);
+    } else {
+        (void)hipFree(m.ptr);
+    }
+    m.ptr = nullptr;
+}
+
 struct Sizes {
     uint64_t ncells = 0;     // cells to visit (all, or those of the slice)
     uint64_t kwin = 0;       // cells per window (planned)
@@ -55,6 +103,7 @@ struct Sizes {
     uint64_t o_runs, o_tiles, o_sol, o_scal, o_scan, scan_bytes, o_colw, o_rows;
     uint64_t o_iruns, o_itiles, o_idx, n_iruns, o_heavy, idx_n;
     uint64_t o_vtab, vtab_slots;
+    uint64_t max_items = 0;  // largest launch of a window, work-items
 };
 
 struct Prepared {
@@ -80,6 +129,40 @@ int validate(const int32_t *A, const int32_t *d, int m, int n) {
         if (s > 65534) return MSP_E_RANGE;
     }
     return MSP_OK;
+}
+
+constexpr uint64_t kMaxLaunchItems = 0xFFFFFFFFull;
+
+// Largest work-item count among the launches of one window of kw cells
+// (the tiled verify's grid depends on the data and is split at launch).
+uint64_t plan_max_items(const Plan &p, uint64_t kw) {
+    uint64_t items = 0;
+    auto mx = [&](uint64_t v) { items = std::max(items, v); };
+    const uint64_t F = (uint64_t)1 << p.log2F;
+    mx(((uint64_t)p.Q[0] + p.Q[1] + p.Q[2] + p.Q[3] + 255) / 256 * 256);   // quarter lists
+    mx(kw * (uint64_t)p.parts * 256);                                          // count
+    const uint64_t nt = F <= 1024 ? 512 : F <= 2048 ? 1024 : 256;           // scatter threads
+    mx(kw * (uint64_t)p.parts * nt);
+    const uint64_t nb = kw * F;                                                // buckets
+    mx((nb + 255) / 256 * 256);                                                // exact runs
+    if (!p.exact && (p.vjoin || p.join_grouped == 1)) mx(nb * 256);            // one group per bucket
+    return items;
+}
+
+// log2 of the expected number of equal-key records per side near K_d: the
+// 2^h_L left halves spread over the key rows' half sums, each about normal
+// with variance sum a_ij^2 / 4 over the left columns (a planning estimate).
+double expected_group_lg2(const msp_ctx *c, const Plan &p) {
+    double lg = p.hL;
+    for (int i = 0; i < p.r; ++i) {
+        double s2 = 0.0;
+        for (int j = 0; j < p.hL; ++j) {
+            const double a = c->A[(size_t)i * c->n + j];
+            s2 += a * a / 4.0;
+        }
+        if (s2 > 0.0) lg -= 0.5 * std::log2(2.0 * 3.141592653589793 * s2);
+    }
+    return lg;
 }
 
 // The plan: surrogate key (Section 1, eq. surrogate), quarter widths
@@ -192,28 +275,24 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
     if (o.join_variant) {
         p.join_grouped = o.join_variant == 3 ? 2 : o.join_variant == 2 ? 1 : 0;
     } else {
-        // Expected equal-key records per side near K_d: 2^h_L spread over the
-        // key rows' half sums, each about normal with variance sum a_ij^2 / 4
-        // over the left columns.  From groups of about six the grouped join
-        // is faster than the chains (measured: ~1 chains, >= 17 groups).
-        double lg = p.hL;
-        for (int i = 0; i < r; ++i) {
-            double s2 = 0.0;
-            for (int j = 0; j < p.hL; ++j) {
-                const double a = c->A[(size_t)i * n + j];
-                s2 += a * a / 4.0;
-            }
-            if (s2 > 0.0) lg -= 0.5 * std::log2(2.0 * 3.141592653589793 * s2);
-        }
-        p.join_grouped = lg >= std::log2(6.0) ? 1 : 0;
+        // From groups of about six the grouped join is faster than the
+        // chains (measured: ~1 chains, >= 17 groups).
+        p.join_grouped = expected_group_lg2(c, p) >= std::log2(6.0) ? 1 : 0;
         // A few dozen records per bucket and side (a modulus forced up by the
         // key room): one wavefront per bucket.
         const uint64_t per_bucket =
             std::max((uint64_t)p.Q[0] * p.Q[1], (uint64_t)p.Q[2] * p.Q[3]) >> std::min(log2M, 62);
         if (!p.exact && per_bucket <= 48) p.join_grouped = 2;
     }
-    if (o.verify_join < 0 || o.verify_join > 1) return MSP_E_INVALID;
-    p.vjoin = (o.verify_join && p.W > 0) ? 1 : 0;
+    // Deciding equal-key runs: the vector join (Algorithms 3-4: one table
+    // probe per record) against the pairwise check (|G_L| |G_R| compares).
+    // The planner takes the vector join when the expected equal-key group
+    // holds 16 or more records per side (hundreds of pairs per run).
+    if (o.verify_join < 0 || o.verify_join > 2) return MSP_E_INVALID;
+    if (o.verify_join == 1) p.vjoin = 1;
+    else if (o.verify_join == 2) p.vjoin = 0;
+    else p.vjoin = expected_group_lg2(c, p) >= 4.0 ? 1 : 0;
+    if (p.W == 0) p.vjoin = 0;
     const uint64_t T = (uint64_t)1 << log2T;
     if (o.slice_mod > 0) {
         p.kstep = (int64_t)std::min<uint64_t>((uint64_t)o.slice_mod, T);
@@ -264,6 +343,10 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
     if (!o.parts && (uint64_t)std::max(p.Q[1], p.Q[3]) * qb > ((uint64_t)4 << 20))
         parts = std::max(8, (parts + 7) & ~7);
     p.parts = parts;
+    // Launch limits: every grid whose size the plan fixes stays below 2^32
+    // work-items (the launchers check again before each launch).
+    while (kwin > 1 && plan_max_items(p, kwin) > kMaxLaunchItems) kwin = (kwin + 1) / 2;
+    if (plan_max_items(p, kwin) > kMaxLaunchItems) return MSP_E_UNSUPPORTED;
     auto layout = [&](uint64_t cap_rec, uint64_t kw) -> uint64_t {
         uint64_t off = 0;
         auto take = [&](uint64_t bytes) { uint64_t o2 = off; off += align_up(bytes, 256); return o2; };
@@ -321,10 +404,12 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
     z.kwin = kwin;
     z.cap_rec = cap_rec;
     z.total = total;
+    z.max_items = plan_max_items(p, kwin);
     return MSP_OK;
 }
 
 double ev_ms(hipEvent_t a, hipEvent_t b) {
+    if (!a || !b) return 0.0;                 // a solve without timing events
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.0;
     return (double)ms;
@@ -341,21 +426,20 @@ double now_s() {
 // ---------------------------------------------------------------------------
 struct Arena {
     char *base = nullptr;
+    DevMem mem;
     uint64_t size = 0;
     std::map<uint64_t, uint64_t> free_;      // offset -> length
     bool init(uint64_t bytes) {
-        if (hipMalloc((void **)&base, bytes) != hipSuccess) {
-            (void)hipGetLastError();
-            base = nullptr;
-            return false;
-        }
+        mem = dev_alloc(bytes);
+        base = (char *)mem.ptr;
+        if (!base) return false;
         size = bytes;
         free_.clear();
         free_[0] = bytes;
         return true;
     }
     void release_all() {
-        if (base) (void)hipFree(base);
+        dev_free(mem);
         base = nullptr;
         free_.clear();
     }
@@ -408,31 +492,48 @@ struct Job {
     bool arena_ws = false;
     hipStream_t s = nullptr;
     hipEvent_t ev[E_COUNT] = {};
-    uint64_t *hs = nullptr;              // pinned copy of the device scalars
+    uint64_t *hs = nullptr;              // host copy of the device scalars (pinned, or
+                                         // the context's own array without events)
+    bool hs_pinned = false;
     Action next = A_BEGIN;
     uint64_t idx = 0, kw = 0, K = 0;
     bool verify_pending = false;
     std::vector<uint64_t> solbuf;
     msp_stats_t st{};
     int rc = MSP_OK;
-    double t_submit = 0, t_admit = 0, t_start = 0, t_finish = 0, t_wall0 = 0;
+    // Server stamps, seconds since server start.  t_finish is published
+    // under the server mutex (last, once the context is free again); the
+    // scheduler thread keeps its own end time in t_retired.
+    double t_submit = 0, t_admit = 0, t_start = 0, t_finish = 0, t_wall0 = 0, t_retired = 0;
     uint64_t ticket = 0;
     bool cancel = false;
+    bool inflight = false;               // work enqueued by the last job_step not yet checked
     int slot = -1;                       // runner stream slot
 };
+
+// Phase events are recorded only when the job has them (the no-allocation
+// entry point runs without).
+hipError_t ev_rec(Job &j, int e) { return j.ev[e] ? hipEventRecord(j.ev[e], j.s) : hipSuccess; }
 
 int job_setup_events(Job &j) {
     for (auto &e : j.ev)
         if (!e && hipEventCreate(&e) != hipSuccess) return MSP_E_DEVICE;
-    if (!j.hs && hipHostMalloc((void **)&j.hs, S_COUNT * 8, hipHostMallocDefault) != hipSuccess)
-        return MSP_E_DEVICE;
+    if (!j.hs) {
+        if (hipHostMalloc((void **)&j.hs, S_COUNT * 8, hipHostMallocDefault) != hipSuccess) {
+            j.hs = nullptr;
+            return MSP_E_DEVICE;
+        }
+        j.hs_pinned = true;
+    }
     return MSP_OK;
 }
 
 void job_release_events(Job &j) {
     for (auto &e : j.ev)
         if (e) (void)hipEventDestroy(e), e = nullptr;
-    if (j.hs) (void)hipHostFree(j.hs), j.hs = nullptr;
+    if (j.hs && j.hs_pinned) (void)hipHostFree(j.hs);
+    j.hs = nullptr;
+    j.hs_pinned = false;
 }
 
 void job_carve(Job &j) {
@@ -467,23 +568,27 @@ void job_carve(Job &j) {
     j.b.rows = (uint16_t *)(ws + z.o_rows);
 }
 
-#define JCHK(x)                                   \
-    do {                                          \
-        if ((x) != hipSuccess) {                  \
-            (void)hipGetLastError();              \
-            return MSP_E_DEVICE;                  \
-        }                                         \
+// A HIP error poisons the solve (MSP_E_DEVICE), except a grid the launchers
+// refused before enqueueing it: that plan is beyond the device's launch
+// limits (MSP_E_UNSUPPORTED) and nothing ran.
+#define JCHK(x)                                                                       \
+    do {                                                                              \
+        const hipError_t e_ = (x);                                                    \
+        if (e_ != hipSuccess) {                                                       \
+            (void)hipGetLastError();                                                  \
+            return e_ == hipErrorInvalidConfiguration ? MSP_E_UNSUPPORTED : MSP_E_DEVICE; \
+        }                                                                             \
     } while (0)
 
 int enqueue_count(Job &j) {
     const Plan &p = j.P.p;
     const size_t ncnt = (size_t)j.K * ((size_t)1 << p.log2F) * p.parts;
-    JCHK(hipEventRecord(j.ev[E_C0], j.s));
+    JCHK(ev_rec(j, E_C0));
     JCHK(launch_count(p, j.b, (int64_t)j.idx, (int32_t)j.K, j.s));
-    JCHK(hipEventRecord(j.ev[E_C1], j.s));
+    JCHK(ev_rec(j, E_C1));
     JCHK(scan_u32(j.b.cnt[0], j.b.off[0], ncnt, &j.b.scal[S_TOT_L], j.b.scan_tmp, j.b.scan_tmp_bytes, j.s));
     JCHK(scan_u32(j.b.cnt[1], j.b.off[1], ncnt, &j.b.scal[S_TOT_R], j.b.scan_tmp, j.b.scan_tmp_bytes, j.s));
-    JCHK(hipEventRecord(j.ev[E_C2], j.s));
+    JCHK(ev_rec(j, E_C2));
     JCHK(hipMemcpyAsync(j.hs, j.b.scal, S_COUNT * 8, hipMemcpyDeviceToHost, j.s));
     return MSP_OK;
 }
@@ -500,9 +605,9 @@ int job_step(Job &j) {
             JCHK(hipMemcpyAsync(j.b.rows, j.P.rows.data(), j.P.rows.size() * 2, hipMemcpyHostToDevice, j.s));
             JCHK(hipMemsetAsync(j.b.scal, 0, S_COUNT * 8, j.s));
             for (int x = 0; x < 4; ++x) JCHK(hipMemsetAsync(j.b.qcnt[x], 0, (T + 1) * 4, j.s));
-            JCHK(hipEventRecord(j.ev[E_Q0], j.s));
+            JCHK(ev_rec(j, E_Q0));
             JCHK(launch_quarters(p, j.b, 0, j.s));
-            JCHK(hipEventRecord(j.ev[E_Q1], j.s));
+            JCHK(ev_rec(j, E_Q1));
             j.idx = 0;
             j.kw = z.kwin;
             j.K = std::min<uint64_t>(j.kw, z.ncells - j.idx);
@@ -526,6 +631,11 @@ int job_step(Job &j) {
                 j.next = A_FINAL1;
                 return MSP_OK;
             }
+            // A work-group whose 32-bit bucket counters could wrap: no window
+            // split helps (one cell, one part), so the solve does not fit.
+            if (j.hs[S_OVF]) return MSP_E_NOMEM;
+            // Window totals are exact 64-bit sums; the scatter runs only when
+            // both fit the record buffers (offsets are 32-bit below cap_rec).
             const uint64_t totL = j.hs[S_TOT_L], totR = j.hs[S_TOT_R];
             if (totL > z.cap_rec || totR > z.cap_rec) {
                 if (j.K == 1) return MSP_E_NOMEM;
@@ -539,14 +649,14 @@ int job_step(Job &j) {
             j.st.records_right += totR;
             JCHK(hipMemsetAsync(&j.b.scal[S_NRUNS], 0, 8, j.s));
             JCHK(hipMemsetAsync(&j.b.scal[S_NIRUNS], 0, 4 * 8, j.s));   // NIRUNS, TOT_ITILES, IDX, NHEAVY
-            JCHK(hipEventRecord(j.ev[E_S0], j.s));
+            JCHK(ev_rec(j, E_S0));
             JCHK(launch_scatter(p, j.b, (int64_t)j.idx, (int32_t)j.K, j.s));
-            JCHK(hipEventRecord(j.ev[E_S1], j.s));
+            JCHK(ev_rec(j, E_S1));
             if (p.exact)
                 JCHK(launch_exact_runs(p, j.b, (int32_t)j.K, j.s));
             else
                 JCHK(launch_hash_join(p, j.b, (int32_t)j.K, z.sol_cap, j.s));
-            JCHK(hipEventRecord(j.ev[E_S2], j.s));
+            JCHK(ev_rec(j, E_S2));
             JCHK(hipMemcpyAsync(j.hs, j.b.scal, S_COUNT * 8, hipMemcpyDeviceToHost, j.s));
             j.next = A_JOINED;
             return MSP_OK;
@@ -561,9 +671,9 @@ int job_step(Job &j) {
                 j.st.ms_join += ev_ms(j.ev[E_S1], j.ev[E_S2]);
                 if (p.vjoin && p.exact && nruns) {
                     // Exact runs: one hash join on the packed rows decides them all.
-                    JCHK(hipEventRecord(j.ev[E_V0], j.s));
+                    JCHK(ev_rec(j, E_V0));
                     JCHK(launch_vector_join(p, j.b, nruns, z.sol_cap, j.s));
-                    JCHK(hipEventRecord(j.ev[E_V1], j.s));
+                    JCHK(ev_rec(j, E_V1));
                     j.verify_pending = true;
                     j.st.verify_launches += 1;
                 } else if (nruns || niruns) {
@@ -582,14 +692,18 @@ int job_step(Job &j) {
                     return MSP_OK;
                 }
             } else {
-                JCHK(hipEventRecord(j.ev[E_V0], j.s));
+                // Tile totals are exact 64-bit sums; offsets are 32-bit.
+                if ((j.hs[S_OVF] & 2) || j.hs[S_TOT_TILES] > 0xFFFFFFFFull ||
+                    j.hs[S_TOT_ITILES] > 0xFFFFFFFFull)
+                    return MSP_E_UNSUPPORTED;
+                JCHK(ev_rec(j, E_V0));
                 if (nruns)
                     JCHK(launch_verify(p, j.b, nruns, (uint32_t)j.hs[S_TOT_TILES], z.sol_cap,
                                        p.exact ? 0 : 1, j.s));
                 if (niruns)
                     JCHK(launch_verify(p, j.b, niruns, (uint32_t)j.hs[S_TOT_ITILES], z.sol_cap, 2,
                                        j.s));
-                JCHK(hipEventRecord(j.ev[E_V1], j.s));
+                JCHK(ev_rec(j, E_V1));
                 j.verify_pending = true;
                 j.st.verify_launches += (nruns ? 1 : 0) + (niruns ? 1 : 0);
             }
@@ -645,6 +759,7 @@ int job_step(Job &j) {
             c->h_hi = j.hs[S_H_HI];
             c->nsol = j.hs[S_NSOL];
             j.st.complete = j.idx >= z.ncells ? 1 : 0;
+            j.st.cells_done = std::min<uint64_t>(j.idx, z.ncells);
             j.st.ms_total = (now_s() - j.t_wall0) * 1e3;
             c->stats = j.st;
             c->have_result = true;
@@ -683,6 +798,7 @@ void job_init_stats(Job &j) {
     j.st.join_grouped = p.exact ? 0 : p.join_grouped;
     j.st.key_base = j.o.key_base;
     j.st.complete = 1;
+    j.st.cells_done = j.P.z.ncells;
     j.st.windows_total = (j.P.z.ncells + j.P.z.kwin - 1) / std::max<uint64_t>(j.P.z.kwin, 1);
 }
 
@@ -750,7 +866,7 @@ struct Runner {
                 pending.pop_front();
                 j->t_admit = j->t_start = now_s() - t0;
                 job_trivial(*j);
-                j->t_finish = now_s() - t0;
+                j->t_retired = now_s() - t0;
                 failed.push_back(j);               // reported as finished (rc OK)
                 continue;
             }
@@ -781,35 +897,51 @@ struct Runner {
             j->s = nullptr;
         }
         job_release_events(*j);
-        j->t_finish = now_s() - t0;
+        j->t_retired = now_s() - t0;
     }
 
-    // One step: every active job runs its next action, then all of them are
-    // synchronised.  Finished or failed jobs are returned in `done`.
-    void step(std::vector<Job *> &done) {
+    // One pass over the active jobs: every job whose stream has drained the
+    // work of its last action runs its next action; jobs still busy on the
+    // device are skipped, so no job waits for another's kernels.  Finished or
+    // failed jobs are returned in `done`.  Returns false when no job could
+    // advance (the caller then backs off briefly).
+    bool step(std::vector<Job *> &done) {
+        bool advanced = false;
         for (Job *j : active) {
+            if (j->rc != MSP_OK || j->next == A_DONE) continue;
+            if (j->inflight) {
+                const hipError_t q = hipStreamQuery(j->s);
+                if (q == hipErrorNotReady) continue;
+                if (q != hipSuccess) {
+                    (void)hipGetLastError();
+                    j->rc = MSP_E_DEVICE;
+                    continue;
+                }
+                j->inflight = false;
+            }
             if (j->t_start == 0) j->t_start = now_s() - t0;
             const int rc = job_step(*j);
+            advanced = true;
             if (rc != MSP_OK) j->rc = rc;
-        }
-        for (Job *j : active) {
-            if (j->rc == MSP_OK && j->next != A_DONE && hipStreamSynchronize(j->s) != hipSuccess) {
-                (void)hipGetLastError();
-                j->rc = MSP_E_DEVICE;
-            }
+            else if (j->next != A_DONE) j->inflight = true;
         }
         std::vector<Job *> keep;
         for (Job *j : active) {
             if (j->rc != MSP_OK || j->next == A_DONE) {
                 retire(j);
                 done.push_back(j);
+                advanced = true;
             } else {
                 keep.push_back(j);
             }
         }
         active.swap(keep);
+        return advanced;
     }
 };
+
+// Back-off of a scheduler pass in which no job could advance.
+void idle_wait() { std::this_thread::sleep_for(std::chrono::microseconds(20)); }
 
 }  // namespace
 
@@ -847,12 +979,15 @@ static void server_loop(msp_server *sv) {
         }
         done.clear();
         sv->run.admit(done);
-        if (!sv->run.active.empty()) sv->run.step(done);
+        bool advanced = false;
+        if (!sv->run.active.empty()) advanced = sv->run.step(done);
         if (!done.empty()) {
+            // Publish: free the context first, then the finish stamp that
+            // waiters and pollers read (all under the mutex).
             std::lock_guard<std::mutex> lk(sv->mu);
             for (Job *j : done) {
-                if (j->t_finish == 0) j->t_finish = now_s() - sv->run.t0;
                 j->c->busy.store(0);
+                j->t_finish = j->t_retired > 0 ? j->t_retired : now_s() - sv->run.t0;
             }
             sv->cv_done.notify_all();
         }
@@ -862,9 +997,11 @@ static void server_loop(msp_server *sv) {
             Job *j = sv->run.pending.front();
             sv->run.pending.pop_front();
             j->rc = MSP_E_NOMEM;
-            j->t_finish = now_s() - sv->run.t0;
             j->c->busy.store(0);
+            j->t_finish = now_s() - sv->run.t0;
             sv->cv_done.notify_all();
+        } else if (!advanced && done.empty() && !sv->run.active.empty()) {
+            idle_wait();
         }
     }
 }
@@ -908,9 +1045,30 @@ int msp_create(const int32_t *A, const int32_t *d, int32_t m, int32_t n, msp_ctx
     return MSP_OK;
 }
 
+// Frees the context's library-owned workspace with the allocator that made it.
+static void ctx_free_ws(msp_ctx *c) {
+    DevMem m;
+    m.ptr = c->ws;
+    m.by.alloc = c->ws_alloc;
+    m.by.release = c->ws_release;
+    m.by.user = c->ws_user;
+    dev_free(m);
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+}
+
+int msp_set_allocator(msp_alloc_fn alloc, msp_release_fn release, void *user) {
+    if ((alloc == nullptr) != (release == nullptr)) return MSP_E_INVALID;
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_alloc.alloc = alloc;
+    g_alloc.release = release;
+    g_alloc.user = user;
+    return MSP_OK;
+}
+
 void msp_destroy(msp_ctx *c) {
     if (!c) return;
-    if (c->ws) (void)hipFree(c->ws);
+    if (c->ws) ctx_free_ws(c);
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
     delete c;
 }
@@ -923,6 +1081,39 @@ uint64_t msp_workspace_bytes(const msp_ctx *c, const msp_opts *opts) {
     Prepared P;
     if (prepare(c, o, o.workspace_bytes, P) != MSP_OK) return 0;
     return P.z.total;
+}
+
+int msp_plan(const msp_ctx *c, const msp_opts *opts, msp_plan_t *out) {
+    if (!c || !out) return MSP_E_INVALID;
+    msp_opts o;
+    msp_default_opts(&o);
+    if (opts) o = *opts;
+    Prepared P;
+    const int rc = prepare(c, o, o.workspace_bytes, P);
+    if (rc) return rc;
+    const Plan &p = P.p;
+    const Sizes &z = P.z;
+    msp_plan_t t{};
+    t.key_rows = p.r;
+    t.log2_m = p.log2M;
+    t.log2_cells = p.log2T;
+    t.log2_fine = p.log2F;
+    t.parts = p.parts;
+    t.exact_buckets = p.exact;
+    t.words = p.W;
+    t.join_variant = p.exact ? 0 : p.join_grouped;
+    t.vector_join = p.vjoin;
+    t.key_base = o.key_base;
+    t.infeasible = P.infeasible ? 1 : 0;
+    t.cells = z.ncells;
+    t.cells_per_window = z.kwin;
+    t.windows = (z.ncells + z.kwin - 1) / std::max<uint64_t>(z.kwin, 1);
+    t.window_records = z.cap_rec;
+    t.record_bytes = rec_bytes(p.W);
+    t.workspace_bytes = z.total;
+    t.max_grid_items = z.max_items;
+    *out = t;
+    return MSP_OK;
 }
 
 int msp_solve(msp_ctx *c, const msp_opts *opts) {
@@ -963,13 +1154,13 @@ int msp_solve(msp_ctx *c, const msp_opts *opts) {
         j.ws = (char *)j.o.workspace;
     } else {
         if (c->ws_bytes < j.P.z.total) {
-            if (c->ws) (void)hipFree(c->ws);
-            c->ws = nullptr;
-            c->ws_bytes = 0;
-            if (hipMalloc(&c->ws, j.P.z.total) != hipSuccess) {
-                (void)hipGetLastError();
-                return MSP_E_NOMEM;
-            }
+            if (c->ws) ctx_free_ws(c);
+            DevMem m = dev_alloc(j.P.z.total);
+            if (!m.ptr) return MSP_E_NOMEM;
+            c->ws = m.ptr;
+            c->ws_alloc = m.by.alloc;
+            c->ws_release = m.by.release;
+            c->ws_user = m.by.user;
             c->ws_bytes = j.P.z.total;
         }
         j.ws = (char *)c->ws;
@@ -1019,7 +1210,7 @@ int msp_batch_solve(msp_ctx *const *ctxs, const msp_opts *opts, int32_t count,
             }
             continue;
         }
-        run.step(done);
+        if (!run.step(done)) idle_wait();
     }
     run.shutdown();
     int first = MSP_OK;
@@ -1101,8 +1292,8 @@ int msp_server_cancel(msp_server *sv, uint64_t ticket) {
         if (*p == j) {                       // not yet seen by the scheduler
             sv->inbox.erase(p);
             j->rc = MSP_E_CANCELLED;
-            j->t_finish = now_s() - sv->run.t0;
             j->c->busy.store(0);
+            j->t_finish = now_s() - sv->run.t0;
             sv->cv_done.notify_all();
             return MSP_OK;
         }

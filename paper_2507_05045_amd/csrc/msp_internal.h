@@ -92,14 +92,18 @@ struct DevBufs {
 };
 
 // Slots of DevBufs::scal.
+// S_OVF is set by the count pass when one work-group enumerates 2^32 or more
+// pairs (its 32-bit bucket counters would wrap).
 enum Scal {
     S_H_LO = 0, S_H_HI, S_NSOL, S_NRUNS, S_TOT_L, S_TOT_R, S_TOT_TILES, S_STORED,
-    S_NIRUNS, S_TOT_ITILES, S_IDX, S_NHEAVY, S_COUNT
+    S_NIRUNS, S_TOT_ITILES, S_IDX, S_NHEAVY, S_OVF, S_COUNT
 };
 
 // Launchers (kernels.hip).  All asynchronous on `st`.
 hipError_t launch_quarters(const Plan &p, const DevBufs &b, int log2T_unused, hipStream_t st);
 hipError_t launch_count(const Plan &p, const DevBufs &b, int64_t idx0, int32_t K, hipStream_t st);
+// Grid checks of the launchers: a launch the device cannot take returns
+// hipErrorInvalidConfiguration before anything is enqueued.
 hipError_t launch_scatter(const Plan &p, const DevBufs &b, int64_t idx0, int32_t K, hipStream_t st);
 hipError_t launch_exact_runs(const Plan &p, const DevBufs &b, int32_t K, hipStream_t st);
 hipError_t launch_hash_join(const Plan &p, const DevBufs &b, int32_t K, uint64_t sol_cap,

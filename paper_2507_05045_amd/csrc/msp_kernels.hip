@@ -195,7 +195,7 @@ __device__ __forceinline__ void cell_part(uint32_t b, uint32_t K, uint32_t P, in
 }
 
 // ---------------------------------------------------------------------------
-// Bucket count / scatter (one enumeration, two modes)
+// Bucket count and scatter
 // ---------------------------------------------------------------------------
 //
 // Work-group (cell-in-window c, part p, side s).  Side 0 builds left records
@@ -203,72 +203,8 @@ __device__ __forceinline__ void cell_part(uint32_t b, uint32_t K, uint32_t P, in
 // records from (c in C) x (e in D_{cell(c) - k}).  Part p takes a contiguous
 // slice of the outer quarter.  Counts are laid out [c][f][p] so that one
 // exclusive scan makes every bucket (c, f) contiguous, parts in order.
-template <int W, bool SCATTER>
-__global__ __launch_bounds__(256) void k_bucket(Plan p, const QRec<W> *__restrict__ A,
-                                                const QRec<W> *__restrict__ B,
-                                                const uint32_t *__restrict__ offB,
-                                                const QRec<W> *__restrict__ Cq,
-                                                const QRec<W> *__restrict__ Dq,
-                                                const uint32_t *__restrict__ offD,
-                                                uint32_t *cntL, uint32_t *cntR,
-                                                const uint32_t *__restrict__ offL,
-                                                const uint32_t *__restrict__ offR,
-                                                Rec<W> *recL, Rec<W> *recR, int64_t idx0) {
-    __shared__ uint32_t s_f[kMaxFine];
-    const int side = blockIdx.y;
-    const int P = p.parts;
-    int cw, part;
-    cell_part(blockIdx.x, gridDim.x / P, P, cw, part);
-    const uint32_t T = 1u << p.log2T;
-    const int F = 1 << p.log2F;
-    const int64_t M1 = ((int64_t)1 << p.log2M) - 1;
-    const uint32_t k = (uint32_t)(p.kfirst + (idx0 + cw) * p.kstep) & (T - 1);
-    const QRec<W> *outer = side ? Cq : A;
-    const QRec<W> *inner = side ? Dq : B;
-    const uint32_t *ioff = side ? offD : offB;
-    const uint64_t Qo = side ? p.Q[2] : p.Q[0];
-    const uint32_t *offs = side ? offR : offL;
-    uint32_t *cnt = side ? cntR : cntL;
-    Rec<W> *rec = side ? recR : recL;
-    const uint64_t base = ((uint64_t)cw * F) * P + part;
-    for (int f = threadIdx.x; f < F; f += blockDim.x)
-        s_f[f] = SCATTER ? offs[base + (uint64_t)f * P] : 0u;
-    __syncthreads();
-    const uint64_t lo = Qo * part / P, hi = Qo * (part + 1) / P;
-    const int64_t smod1 = p.slice_mod - 1;
-    for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-        const QRec<W> a = outer[i];
-        const uint32_t ca = (uint32_t)a.key & (T - 1);
-        const uint32_t j = side ? ((ca - k) & (T - 1)) : ((k - ca) & (T - 1));
-        const uint32_t b0 = ioff[j], b1 = ioff[j + 1];
-        for (uint32_t q = b0; q < b1; ++q) {
-            const QRec<W> b = inner[q];
-            const int64_t key = side ? a.key - b.key : a.key + b.key;
-            bool keep = side ? key >= 0 : key <= p.Kd;   // only these can meet
-            if (p.slice_mod) keep = keep && ((key & smod1) == p.slice_res);
-            if (!keep) continue;
-            const uint32_t f = (uint32_t)((key & M1) >> p.log2T);
-            if (!SCATTER) {
-                atomicAdd(&s_f[f], 1u);
-            } else {
-                const uint32_t slot = atomicAdd(&s_f[f], 1u);
-                Rec<W> r;
-                r.hdr = i | ((uint64_t)q << p.qa) | ((uint64_t)(key >> p.log2M) << p.hsh);
-#pragma unroll
-                for (int w = 0; w < (W > 0 ? W : 1); ++w)
-                    r.vec[w] = side ? resid_word(p.dpk[w], a.vec[w], b.vec[w])
-                                    : a.vec[w] + b.vec[w];
-                rec[slot] = r;
-            }
-        }
-    }
-    if (!SCATTER) {
-        __syncthreads();
-        for (int f = threadIdx.x; f < F; f += blockDim.x) cnt[base + (uint64_t)f * P] = s_f[f];
-    }
-}
 
-// Count pass (the enumeration of k_bucket without records).  Each thread
+// Count pass (the enumeration of the scatter without records).  Each thread
 // takes PER outer elements at a time, NT apart so that a wave reads
 // consecutive records, and loads eight inner keys together: the chains of
 // dependent loads (outer key -> cell offsets -> inner keys) of several
@@ -281,8 +217,10 @@ __global__ __launch_bounds__(256) void k_count(Plan p, const QRec<W> *__restrict
                                                const QRec<W> *__restrict__ Cq,
                                                const QRec<W> *__restrict__ Dq,
                                                const uint32_t *__restrict__ offD,
-                                               uint32_t *cntL, uint32_t *cntR, int64_t idx0) {
+                                               uint32_t *cntL, uint32_t *cntR, int64_t idx0,
+                                               uint64_t *scal) {
     __shared__ uint32_t s_f[kMaxFine];
+    __shared__ unsigned long long s_pairs;
     const int side = blockIdx.y;
     const int P = p.parts;
     int cw, part;
@@ -299,9 +237,11 @@ __global__ __launch_bounds__(256) void k_count(Plan p, const QRec<W> *__restrict
     uint32_t *cnt = side ? cntR : cntL;
     const uint64_t base = ((uint64_t)cw * F) * P + part;
     for (int f = t; f < F; f += 256) s_f[f] = 0u;
+    if (t == 0) s_pairs = 0;
     __syncthreads();
     const uint64_t lo = Qo * part / P, hi = Qo * (part + 1) / P;
     const int64_t smod1 = p.slice_mod - 1;
+    uint64_t npairs = 0;                 // pairs this thread enumerates
     if (hi > lo) {
         for (uint64_t c0 = lo; c0 < hi; c0 += (uint64_t)256 * PER) {
             int64_t ak[PER];
@@ -321,6 +261,7 @@ __global__ __launch_bounds__(256) void k_count(Plan p, const QRec<W> *__restrict
 #pragma unroll
             for (int e = 0; e < PER; ++e) {
                 if (c0 + (uint64_t)e * 256 + t >= hi) b1[e] = b0[e];
+                npairs += b1[e] - b0[e];
                 for (uint32_t q0 = b0[e]; q0 < b1[e]; q0 += 8) {
                     int64_t bk[8];
 #pragma unroll
@@ -337,8 +278,10 @@ __global__ __launch_bounds__(256) void k_count(Plan p, const QRec<W> *__restrict
             }
         }
     }
+    if (npairs) atomicAdd(&s_pairs, (unsigned long long)npairs);
     __syncthreads();
     for (int f = t; f < F; f += 256) cnt[base + (uint64_t)f * P] = s_f[f];
+    if (t == 0 && s_pairs > 0xFFFFFFFFull) atomicOr((unsigned long long *)&scal[S_OVF], 1ull);
 }
 
 // Exclusive scan of a[0 .. n) in LDS by an NT-thread block (n a multiple of
@@ -561,12 +504,16 @@ __global__ __launch_bounds__(256) void k_exact_runs(Plan p, const uint32_t *__re
     }
 }
 
+// Tiles of each run pair; a run pair of 2^32 or more tiles (far beyond any
+// pairwise check that ends) sets bit 2 of S_OVF and counts as 0xFFFFFFFF.
 __global__ void k_tile_counts(const RunPair *__restrict__ runs, uint32_t n, uint32_t *tiles,
-                              uint32_t tile_r) {
+                              uint32_t tile_r, uint64_t *scal) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const RunPair r = runs[i];
-    tiles[i] = ((r.nl + kTileL - 1) / kTileL) * ((r.nr + tile_r - 1) / tile_r);
+    const uint64_t t = (uint64_t)((r.nl + kTileL - 1) / kTileL) * ((r.nr + tile_r - 1) / tile_r);
+    if (t > 0xFFFFFFFFull) atomicOr((unsigned long long *)&scal[S_OVF], 2ull);
+    tiles[i] = (uint32_t)std::min<uint64_t>(t, 0xFFFFFFFFull);
 }
 
 __device__ __forceinline__ void emit_solution(uint64_t *sol, uint64_t cap, uint64_t *ctr,
@@ -1612,14 +1559,14 @@ __global__ __launch_bounds__(256) void k_verify(Plan p, const Rec<W> *__restrict
                                                 const uint32_t *__restrict__ toff,
                                                 uint32_t nruns, uint64_t *scal, uint64_t *sol,
                                                 uint64_t cap, const uint32_t *__restrict__ idx,
-                                                QPtrs<W> qs) {
+                                                QPtrs<W> qs, uint32_t tile0) {
     // IDX: run ranges index `idx`, which holds the record positions.
     auto lrec = [&](uint32_t i) -> const Rec<W> & { return IDX ? L[idx[i]] : L[i]; };
     auto rrec = [&](uint32_t i) -> const Rec<W> & { return IDX ? R[idx[i]] : R[i]; };
     __shared__ __attribute__((aligned(16))) uint32_t s_fp[kChunk];
     __shared__ int64_t s_lk[CK ? kChunk : 1];
     __shared__ uint64_t s_s4[4];
-    const uint32_t tile = blockIdx.x;
+    const uint32_t tile = tile0 + blockIdx.x;
     // Run pair of this tile: last ri with toff[ri] <= tile.
     uint32_t lo = 0, hi = nruns;
     while (hi - lo > 1) {
@@ -1743,14 +1690,37 @@ __global__ __launch_bounds__(256) void k_verify(Plan p, const Rec<W> *__restrict
 }
 
 // ---------------------------------------------------------------------------
+// Launch limits.  An HSA dispatch holds the grid size in work-items as 32-bit
+// numbers, so blocks x threads stays below 2^32 in x; y is the side index or
+// a small split.  Launchers check every grid before enqueueing anything and
+// return hipErrorInvalidConfiguration for one the device cannot take.
+// ---------------------------------------------------------------------------
+
+constexpr uint64_t kMaxGridItems = 0xFFFFFFFFull;
+constexpr uint32_t kMaxGridY = 65535;
+
+static bool grid_ok(dim3 g, uint32_t threads) {
+    return g.x >= 1 && (uint64_t)g.x * threads <= kMaxGridItems && g.y >= 1 && g.y <= kMaxGridY &&
+           g.z == 1;
+}
+
+#define MSP_GRID_CHECK(g, threads)                                      \
+    do {                                                                \
+        if (!grid_ok((g), (threads))) return hipErrorInvalidConfiguration; \
+    } while (0)
+
+// ---------------------------------------------------------------------------
 // Device-wide exclusive scan of uint32 (reduce -> scan of block sums -> apply)
 // ---------------------------------------------------------------------------
 
 constexpr int kScanE = 4;
 constexpr int kScanBlock = 256 * kScanE;
 
+// Block sums (uint32, they feed the scan of offsets) and, when total64 is
+// given, the exact 64-bit total: offsets wrap once the total passes 2^32, but
+// the caller compares the 64-bit total with its capacity before using them.
 __global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t *__restrict__ in, size_t n,
-                                                     uint32_t *sums) {
+                                                     uint32_t *sums, uint64_t *total64) {
     __shared__ uint64_t s4[4];
     const size_t base = (size_t)blockIdx.x * kScanBlock;
     uint64_t s = 0;
@@ -1759,20 +1729,29 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t *__restrict_
         if (i < n) s += in[i];
     }
     s = block_sum_u64(s, s4);
-    if (threadIdx.x == 0) sums[blockIdx.x] = (uint32_t)s;
+    if (threadIdx.x == 0) {
+        sums[blockIdx.x] = (uint32_t)s;
+        if (total64) atomicAdd((unsigned long long *)total64, (unsigned long long)s);
+    }
 }
 
+// total64 (single-block scans only): the exact 64-bit sum of the inputs.
 __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *__restrict__ in, uint32_t *out,
                                                     size_t n, const uint32_t *__restrict__ pref,
                                                     uint64_t *total64, int write_total) {
     __shared__ uint32_t s_a[kScanBlock];
     __shared__ uint32_t s_w4[4];
+    __shared__ uint64_t s_t4[4];
     const size_t base = (size_t)blockIdx.x * kScanBlock;
+    uint64_t s64 = 0;
     for (int e = 0; e < kScanE; ++e) {
         const size_t i = base + (size_t)e * 256 + threadIdx.x;
-        s_a[e * 256 + threadIdx.x] = i < n ? in[i] : 0u;
+        const uint32_t v = i < n ? in[i] : 0u;
+        s_a[e * 256 + threadIdx.x] = v;
+        s64 += v;
     }
     __syncthreads();
+    if (total64) s64 = block_sum_u64(s64, s_t4);
     const uint32_t tot = block_excl_scan_lds<kScanE>(s_a, s_w4);
     const uint32_t add = pref ? pref[blockIdx.x] : 0u;
     for (int e = 0; e < kScanE; ++e) {
@@ -1781,7 +1760,7 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *__restrict__
     }
     if (write_total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
         out[n] = add + tot;
-        if (total64) *total64 = (uint64_t)(add + tot);
+        if (total64) *total64 = s64;
     }
 }
 
@@ -1802,6 +1781,7 @@ hipError_t scan_u32(const uint32_t *in, uint32_t *out, size_t n, uint64_t *total
         return e;
     }
     const size_t nb = (n + kScanBlock - 1) / kScanBlock;
+    if ((uint64_t)nb * 256 > kMaxGridItems) return hipErrorInvalidConfiguration;
     if (nb == 1) {
         hipLaunchKernelGGL(k_scan_apply, dim3(1), dim3(256), 0, st, in, out, n, nullptr, total64, 1);
         return hipGetLastError();
@@ -1810,11 +1790,15 @@ hipError_t scan_u32(const uint32_t *in, uint32_t *out, size_t n, uint64_t *total
     if (tmp_bytes < need) return hipErrorInvalidValue;
     uint32_t *sums = (uint32_t *)tmp;
     uint32_t *pref = sums + nb + 1;
-    hipLaunchKernelGGL(k_scan_reduce, dim3((uint32_t)nb), dim3(256), 0, st, in, n, sums);
+    if (total64) {
+        hipError_t e0 = hipMemsetAsync(total64, 0, sizeof(uint64_t), st);
+        if (e0 != hipSuccess) return e0;
+    }
+    hipLaunchKernelGGL(k_scan_reduce, dim3((uint32_t)nb), dim3(256), 0, st, in, n, sums, total64);
     hipError_t e = scan_u32(sums, pref, nb, nullptr, (char *)tmp + need, tmp_bytes - need, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_scan_apply, dim3((uint32_t)nb), dim3(256), 0, st, in, out, n, pref,
-                       total64, 1);
+                       nullptr, 1);
     return hipGetLastError();
 }
 
@@ -1866,6 +1850,7 @@ template <int W>
 static hipError_t quarters_impl(const Plan &p, const DevBufs &b, hipStream_t st) {
     const uint64_t tot = (uint64_t)p.Q[0] + p.Q[1] + p.Q[2] + p.Q[3];
     const uint32_t grid = (uint32_t)((tot + 255) / 256);
+    MSP_GRID_CHECK(dim3(grid), 256);
     QPtrs<W> raw, srt;
     UPtrs cnt, cur;
     for (int x = 0; x < 4; ++x) {
@@ -1893,29 +1878,19 @@ hipError_t launch_quarters(const Plan &p, const DevBufs &b, int, hipStream_t st)
     return hipSuccess;
 }
 
-template <int W, bool SC>
-static hipError_t bucket_impl(const Plan &p, const DevBufs &b, int64_t idx0, int32_t K,
-                              hipStream_t st) {
-    dim3 grid((uint32_t)K * p.parts, 2);
-    hipLaunchKernelGGL((k_bucket<W, SC>), grid, dim3(256), 0, st, p,
-                       (const QRec<W> *)b.qsrt[0], (const QRec<W> *)b.qsrt[1], b.qcnt[1],
-                       (const QRec<W> *)b.qsrt[2], (const QRec<W> *)b.qsrt[3], b.qcnt[3],
-                       b.cnt[0], b.cnt[1], b.off[0], b.off[1], (Rec<W> *)b.rec[0],
-                       (Rec<W> *)b.rec[1], idx0);
-    return hipGetLastError();
-}
-
 template <int W>
 static hipError_t count_impl(const Plan &p, const DevBufs &b, int64_t idx0, int32_t K,
                              hipStream_t st) {
     // Four outer elements per thread while cells hold few inner elements.
     const uint64_t T = (uint64_t)1 << p.log2T;
     const uint64_t qin = std::min((uint64_t)p.Q[1], (uint64_t)p.Q[3]);
+    if ((uint64_t)K * p.parts > 0xFFFFFFFFull) return hipErrorInvalidConfiguration;
     dim3 grid((uint32_t)K * p.parts, 2);
+    MSP_GRID_CHECK(grid, 256);
 #define MSP_COUNT(PERV)                                                                         \
     hipLaunchKernelGGL((k_count<W, PERV>), grid, dim3(256), 0, st, p, (const QRec<W> *)b.qsrt[0], \
                        (const QRec<W> *)b.qsrt[1], b.qcnt[1], (const QRec<W> *)b.qsrt[2],       \
-                       (const QRec<W> *)b.qsrt[3], b.qcnt[3], b.cnt[0], b.cnt[1], idx0)
+                       (const QRec<W> *)b.qsrt[3], b.qcnt[3], b.cnt[0], b.cnt[1], idx0, b.scal)
     if (qin >= 16 * T) MSP_COUNT(1);
     else MSP_COUNT(4);
 #undef MSP_COUNT
@@ -1938,7 +1913,9 @@ static hipError_t staged_impl(const Plan &p, const DevBufs &b, int64_t idx0, int
     while (per < 16 && (uint64_t)256 * (2 * per) * qin <= (uint64_t)kStageBatch * T) per *= 2;
     // LDS for the per-bucket cursors is sized to F: more work-groups per CU.
     const int F = 1 << p.log2F;
+    if ((uint64_t)K * p.parts > 0xFFFFFFFFull) return hipErrorInvalidConfiguration;
     dim3 grid((uint32_t)K * p.parts, 2);
+    MSP_GRID_CHECK(grid, 1024);
     // Threads per work-group (batch = 12 pairs per thread), by the LDS that
     // the bucket cursors leave: 512 for F <= 1024 (two groups per CU), 1024
     // for F = 2048 (one group of 16 waves), 256 for F = 4096.
@@ -1970,26 +1947,16 @@ static hipError_t staged_impl(const Plan &p, const DevBufs &b, int64_t idx0, int
     return hipGetLastError();
 }
 
-// MSP_SCATTER=direct selects the unstaged scatter (one store per record).
-static bool scatter_direct() {
-    static bool d = [] {
-        const char *e = getenv("MSP_SCATTER");
-        return e && std::strcmp(e, "direct") == 0;
-    }();
-    return d;
-}
-
 hipError_t launch_scatter(const Plan &p, const DevBufs &b, int64_t idx0, int32_t K,
                           hipStream_t st) {
-    if ((1 << p.log2F) <= kMaxFine && !scatter_direct()) {
-        MSP_DISPATCH_W(p.W, return staged_impl<WW>(p, b, idx0, K, st));
-    }
-    MSP_DISPATCH_W(p.W, return (bucket_impl<WW, true>(p, b, idx0, K, st)));
+    MSP_DISPATCH_W(p.W, return staged_impl<WW>(p, b, idx0, K, st));
     return hipSuccess;
 }
 
 hipError_t launch_exact_runs(const Plan &p, const DevBufs &b, int32_t K, hipStream_t st) {
+    if (((uint64_t)K << p.log2F) > 0xFFFFFFFFull) return hipErrorInvalidConfiguration;
     const uint32_t nb = (uint32_t)K << p.log2F;
+    MSP_GRID_CHECK(dim3((nb + 255) / 256), 256);
     hipLaunchKernelGGL(k_exact_runs, dim3((nb + 255) / 256), dim3(256), 0, st, p, b.off[0],
                        b.off[1], nb, b.runs, b.scal, p.W == 0 ? 1 : 0);
     return hipGetLastError();
@@ -1998,9 +1965,12 @@ hipError_t launch_exact_runs(const Plan &p, const DevBufs &b, int32_t K, hipStre
 template <int W>
 static hipError_t join_impl(const Plan &p, const DevBufs &b, int32_t K, uint64_t cap,
                             hipStream_t st) {
+    if (((uint64_t)K << p.log2F) > 0xFFFFFFFFull) return hipErrorInvalidConfiguration;
     const uint32_t nb = (uint32_t)K << p.log2F;
     const Rec<W> *L = (const Rec<W> *)b.rec[0], *R = (const Rec<W> *)b.rec[1];
     const dim3 pg(std::min<uint32_t>(nb, 4096));         // persistent chain join
+    // The grouped join takes one work-group per bucket; the others stride.
+    if (p.vjoin || (p.join_grouped == 1)) MSP_GRID_CHECK(dim3(nb), 256);
 #define MSP_GROUPED(K32V, VJV)                                                                  \
     hipLaunchKernelGGL((k_join_grouped<W, K32V, VJV>), dim3(nb), dim3(256), 0, st, p, b.off[0], \
                        b.off[1], L, R, b.heavy, b.scal, b.sol, cap, sorted_quarters<W>(b))
@@ -2051,34 +2021,16 @@ hipError_t launch_hash_join(const Plan &p, const DevBufs &b, int32_t K, uint64_t
     return hipSuccess;
 }
 
-// Right records per lane of the tiled verify: 8 by default (tile 2048),
-// MSP_VERIFY_KR=16 selects tiles of 4096 right records.
-int verify_kr() {
-    static int kr = [] {
-        const char *e = getenv("MSP_VERIFY_KR");
-        return (e && atoi(e) == 16) ? 16 : 8;
-    }();
-    return kr;
-}
-
-// The EXEC-mask candidate test (v_cmpx) is the default; MSP_VERIFY_CMPX=0
-// selects the ballot-OR form (one scalar OR per compare).
-bool verify_cmpx() {
-    static bool on = [] {
-        const char *e = getenv("MSP_VERIFY_CMPX");
-        return !(e && atoi(e) == 0);
-    }();
-    return on;
-}
-
 template <int W>
 static hipError_t vjoin_impl(const Plan &p, const DevBufs &b, uint32_t nruns, uint64_t cap,
                              hipStream_t st) {
     const uint64_t slots = (uint64_t)b.vtab_mask + 1;
+    MSP_GRID_CHECK(dim3(std::min<uint32_t>(nruns, 4096), 16), 256);
     hipError_t e = hipMemsetAsync(b.vtab, 0xFF, slots * 4, st);
     if (e != hipSuccess) return e;
     // Blocks stride over runs; the second grid dimension splits long runs.
     const dim3 grid(std::min<uint32_t>(nruns, 4096), 16);
+    MSP_GRID_CHECK(grid, 256);
     hipLaunchKernelGGL(k_vjoin_insert<W>, grid, dim3(256), 0, st, b.runs, nruns,
                        (const Rec<W> *)b.rec[0], b.vtab, b.vtab_mask);
     e = hipGetLastError();
@@ -2099,13 +2051,14 @@ hipError_t launch_vector_join(const Plan &p, const DevBufs &b, uint32_t nruns, u
 hipError_t launch_tile_counts(const Plan &, const DevBufs &b, uint32_t nruns, int mode,
                               hipStream_t st) {
     if (nruns == 0) return hipSuccess;
-    const uint32_t tile_r = 256u * ((mode != 0 || verify_cmpx()) ? 8 : verify_kr());
+    const uint32_t tile_r = 256u * 8;        // right records per verify tile
+    MSP_GRID_CHECK(dim3((nruns + 255) / 256), 256);
     if (mode == 2)
         hipLaunchKernelGGL(k_tile_counts, dim3((nruns + 255) / 256), dim3(256), 0, st, b.iruns,
-                           nruns, b.itiles, tile_r);
+                           nruns, b.itiles, tile_r, b.scal);
     else
         hipLaunchKernelGGL(k_tile_counts, dim3((nruns + 255) / 256), dim3(256), 0, st, b.runs,
-                           nruns, b.tiles, tile_r);
+                           nruns, b.tiles, tile_r, b.scal);
     return hipGetLastError();
 }
 
@@ -2113,27 +2066,27 @@ template <int W>
 static hipError_t verify_impl(const Plan &p, const DevBufs &b, uint32_t nruns, uint32_t ntiles,
                               uint64_t cap, int mode, hipStream_t st) {
     const Rec<W> *L = (const Rec<W> *)b.rec[0], *R = (const Rec<W> *)b.rec[1];
-    if (mode == 2)
-        hipLaunchKernelGGL((k_verify<W, false, 8, true, true>), dim3(ntiles), dim3(256), 0, st, p,
-                           L, R, b.iruns, b.itiles, nruns, b.scal, b.sol, cap, b.idx,
-                           sorted_quarters<W>(b));
-    else if (mode == 1)
-        hipLaunchKernelGGL((k_verify<W, true, 8>), dim3(ntiles), dim3(256), 0, st, p, L, R,
-                           b.runs, b.tiles, nruns, b.scal, b.sol, cap, b.idx,
-                           sorted_quarters<W>(b));
-    else if (verify_cmpx())
-        hipLaunchKernelGGL((k_verify<W, false, 8, true>), dim3(ntiles), dim3(256), 0, st, p, L, R,
-                           b.runs, b.tiles, nruns, b.scal, b.sol, cap, b.idx,
-                           sorted_quarters<W>(b));
-    else if (verify_kr() == 16)
-        hipLaunchKernelGGL((k_verify<W, false, 16>), dim3(ntiles), dim3(256), 0, st, p, L, R,
-                           b.runs, b.tiles, nruns, b.scal, b.sol, cap, b.idx,
-                           sorted_quarters<W>(b));
-    else
-        hipLaunchKernelGGL((k_verify<W, false, 8>), dim3(ntiles), dim3(256), 0, st, p, L, R,
-                           b.runs, b.tiles, nruns, b.scal, b.sol, cap, b.idx,
-                           sorted_quarters<W>(b));
-    return hipGetLastError();
+    // One work-group per tile, in launches of at most 2^23 tiles.
+    constexpr uint32_t kTilesPerLaunch = 1u << 23;
+    for (uint32_t t0 = 0; t0 < ntiles; t0 += kTilesPerLaunch) {
+        const dim3 g(std::min(kTilesPerLaunch, ntiles - t0));
+        MSP_GRID_CHECK(g, 256);
+        if (mode == 2)
+            hipLaunchKernelGGL((k_verify<W, false, 8, true, true>), g, dim3(256), 0, st, p, L, R,
+                               b.iruns, b.itiles, nruns, b.scal, b.sol, cap, b.idx,
+                               sorted_quarters<W>(b), t0);
+        else if (mode == 1)
+            hipLaunchKernelGGL((k_verify<W, true, 8>), g, dim3(256), 0, st, p, L, R, b.runs,
+                               b.tiles, nruns, b.scal, b.sol, cap, b.idx, sorted_quarters<W>(b),
+                               t0);
+        else
+            hipLaunchKernelGGL((k_verify<W, false, 8, true>), g, dim3(256), 0, st, p, L, R,
+                               b.runs, b.tiles, nruns, b.scal, b.sol, cap, b.idx,
+                               sorted_quarters<W>(b), t0);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_verify(const Plan &p, const DevBufs &b, uint32_t nruns, uint32_t ntiles,

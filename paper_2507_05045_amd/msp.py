@@ -51,11 +51,25 @@ class msp_stats_t(C.Structure):
                 ("parts", C.c_int32), ("key_rows", C.c_int32), ("exact_buckets", C.c_int32),
                 ("words", C.c_int32), ("complete", C.c_int32), ("vector_join", C.c_int32),
                 ("windows_total", C.c_uint64), ("join_grouped", C.c_int32),
-                ("key_base", C.c_int32)]
+                ("key_base", C.c_int32), ("reserved", C.c_int32), ("cells_done", C.c_uint64)]
 
 
 class msp_batch_opts(C.Structure):
     _fields_ = [("hbm_budget", C.c_uint64), ("max_slots", C.c_int32), ("reserved", C.c_int32)]
+
+
+class msp_plan_t(C.Structure):
+    _fields_ = [("key_rows", C.c_int32), ("log2_m", C.c_int32), ("log2_cells", C.c_int32),
+                ("log2_fine", C.c_int32), ("parts", C.c_int32), ("exact_buckets", C.c_int32),
+                ("words", C.c_int32), ("join_variant", C.c_int32), ("vector_join", C.c_int32),
+                ("key_base", C.c_int32), ("infeasible", C.c_int32), ("reserved", C.c_int32),
+                ("cells", C.c_uint64), ("cells_per_window", C.c_uint64), ("windows", C.c_uint64),
+                ("window_records", C.c_uint64), ("record_bytes", C.c_uint64),
+                ("workspace_bytes", C.c_uint64), ("max_grid_items", C.c_uint64)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 
 # Every symbol include/msp.h declares (checked by the CPU test suite).
@@ -63,7 +77,7 @@ EXPORTS = ["msp_create", "msp_default_opts", "msp_solve", "msp_num_solutions", "
            "msp_get_solutions", "msp_stats", "msp_destroy", "msp_strerror",
            "msp_workspace_bytes", "msp_batch_solve", "msp_server_start", "msp_server_submit",
            "msp_server_poll", "msp_server_wait", "msp_server_cancel", "msp_server_times",
-           "msp_server_stop"]
+           "msp_server_stop", "msp_plan", "msp_set_allocator"]
 
 # PyTorch-ROCm ships its own HIP runtime with the same soname as the system
 # one.  Load torch first so that libmsp binds to the runtime torch uses:
@@ -114,6 +128,10 @@ lib.msp_server_times.argtypes = [C.c_void_p, C.c_uint64, _p(C.c_double)]
 lib.msp_server_times.restype = C.c_int
 lib.msp_server_stop.argtypes = [C.c_void_p]
 lib.msp_server_stop.restype = C.c_int
+lib.msp_plan.argtypes = [C.c_void_p, _p(msp_opts), _p(msp_plan_t)]
+lib.msp_plan.restype = C.c_int
+lib.msp_set_allocator.argtypes = [ALLOC_FN, RELEASE_FN, C.c_void_p]
+lib.msp_set_allocator.restype = C.c_int
 
 
 def strerror(code: int) -> str:
@@ -168,6 +186,14 @@ class Context:
 
     def workspace_bytes(self, opts: msp_opts) -> int:
         return int(lib.msp_workspace_bytes(self._ctx, C.byref(opts)))
+
+    def plan(self, budget: int = 0, **kw) -> dict:
+        """msp_plan: the plan msp_solve would run (host only, no GPU)."""
+        opts = msp_default_opts(**kw)
+        opts.workspace_bytes = budget
+        out = msp_plan_t()
+        _check(lib.msp_plan(self._ctx, C.byref(opts), C.byref(out)), "msp_plan")
+        return {k: getattr(out, k) for k, _ in msp_plan_t._fields_}
 
     def solve(self, use_torch: bool = True, budget: Optional[int] = None, **kw) -> "Context":
         """msp_solve.  With torch and a GPU, the workspace is a torch tensor
@@ -284,3 +310,51 @@ class Server:
         if self._s:
             _check(lib.msp_server_stop(self._s), "msp_server_stop")
             self._s = C.c_void_p()
+
+
+_allocator_keep = None
+
+
+def set_allocator(alloc=None, release=None):
+    """msp_set_allocator.  ``alloc(bytes) -> device pointer (int) or 0`` and
+    ``release(ptr)`` are Python callables; both None restores hipMalloc."""
+    global _allocator_keep
+    if alloc is None and release is None:
+        rc = lib.msp_set_allocator(ALLOC_FN(), RELEASE_FN(), None)
+        _check(rc, "msp_set_allocator")
+        _allocator_keep = None
+        return
+    a = ALLOC_FN(lambda nbytes, user: alloc(int(nbytes)) or None)
+    r = RELEASE_FN(lambda ptr, user: release(int(ptr)))
+    _check(lib.msp_set_allocator(a, r, None), "msp_set_allocator")
+    _allocator_keep = (a, r, alloc, release)
+
+
+class TorchArena:
+    """Device memory for the library from PyTorch's caching allocator: each
+    request is a torch.uint8 CUDA tensor kept alive until the library
+    releases it.  Use as ``with TorchArena(): ...``."""
+
+    def __init__(self):
+        self.live = {}
+        self.requests = 0
+
+    def alloc(self, nbytes: int) -> int:
+        try:
+            t = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        except RuntimeError:
+            return 0
+        self.live[t.data_ptr()] = t
+        self.requests += 1
+        return t.data_ptr()
+
+    def release(self, ptr: int):
+        self.live.pop(ptr, None)
+
+    def __enter__(self):
+        set_allocator(self.alloc, self.release)
+        return self
+
+    def __exit__(self, *exc):
+        set_allocator(None, None)
+        return False

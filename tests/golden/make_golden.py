@@ -1,6 +1,8 @@
 """Writes tests/golden/oracle_configs.json: oracle results for the named
 workloads, computed only by the CPU oracle (oracle/).  Run from the repo
 root:  python tests/golden/make_golden.py
+With --batch it writes tests/golden/oracle_batch.json instead: the instances
+of the batched and served tests, solved whole by the heap oracle.
 
 Small workloads are solved whole with the heap Schroeppel-Shamir oracle;
 the large ones are sampled: the meet-in-the-middle oracle solves single
@@ -99,10 +101,74 @@ def main():
             out.append(entry(inst, 5, res, mod, rho, routine=f"mitm mod 2^{lm}", key_base=1))
             print(inst.name, "r5", rho, out[-1]["H"], out[-1]["nsol"],
                   f"{time.time() - t0:.1f}s", flush=True)
+    # A multi-cell residue slice of (8,70): the left-key classes mod 2^8 =
+    # 256, solved by the MITM oracle with classes mod 2^20 (4096 of them
+    # inside the slice).  The GPU takes it with its own multi-window,
+    # multi-part plans.  Seed 0 in slice 0, its planted twin in x*'s slice.
+    for planted in (False, True):
+        inst = make_instance(8, 70, 0, planted=planted)
+        rho = O.left_key(inst.A, inst.d, inst.planted, 4) % 256 if planted else 0
+        res = O.mitm(inst.A, inst.d, 4, 20, slice_mod=256, slice_res=rho)
+        out.append(entry(inst, 4, res, 256, rho, routine="mitm mod 2^20, slice mod 2^8"))
+        print(inst.name, "slice 256", rho, out[-1]["H"], out[-1]["nsol"],
+              f"{time.time() - t0:.1f}s", flush=True)
     with open(OUT, "w") as f:
         json.dump(out, f, indent=1)
     print("wrote", OUT)
 
 
+# Instances of the batched and served tests: uneven (m, n) and key rows.
+# Each spec: (generator, m, n, seed, K, planted, key rows).
+BATCH_SPECS = ([("random_small", 4, 22, 900 + s, 8, True, 2) for s in range(3)] +
+               [("make_instance", m, n, 7 + m, 100, planted, r)
+                for (m, n, r) in [(4, 30, 1), (5, 40, 1), (6, 50, 2)]
+                for planted in (False, True)])
+
+
+def batch_instance(spec):
+    from paper_2507_05045_amd.inputs import random_small
+    gen, m, n, seed, K, planted, r = spec
+    if gen == "random_small":
+        return random_small(m, n, seed, K=K, planted=planted)
+    return make_instance(m, n, seed, planted=planted, K=K)
+
+
+def _heap_entry(job):
+    kind, spec = job
+    if kind == "stream":
+        from paper_2507_05045_amd.inputs import stream_instances
+        inst = stream_instances(spec + 1)[spec]
+        r = inst.key_rows
+        res = O.ss_heap(inst.A, inst.d, r)
+        e = entry(inst, r, res, routine="ss_heap")
+        e["stream_index"] = spec
+        return e
+    inst = batch_instance(spec)
+    res = O.ss_heap(inst.A, inst.d, spec[-1])
+    e = entry(inst, spec[-1], res, routine="ss_heap", K=spec[4])
+    e["spec"] = list(spec)
+    return e
+
+
+def batch_main():
+    """tests/golden/oracle_batch.json: the batched/served test instances and
+    the first ten stream instances with m <= 6, each solved whole by the heap
+    oracle (four processes; the oracle itself is single-threaded)."""
+    import multiprocessing as mp
+    from paper_2507_05045_amd.inputs import stream_instances
+    jobs = [("spec", sp) for sp in BATCH_SPECS]
+    jobs += [("stream", k) for k, i in enumerate(stream_instances(64)) if i.m <= 6][:10]
+    t0 = time.time()
+    with mp.get_context("fork").Pool(4) as pool:
+        out = pool.map(_heap_entry, jobs)
+    path = os.path.join(os.path.dirname(OUT), "oracle_batch.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print("wrote", path, f"{time.time() - t0:.1f}s")
+
+
 if __name__ == "__main__":
-    main()
+    if sys.argv[1:] == ["--batch"]:
+        batch_main()
+    else:
+        main()

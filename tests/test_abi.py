@@ -121,3 +121,70 @@ def test_target_far_above_a_key_row_sum_is_planned_as_empty():
     for kb in (0, 1):
         assert ctx.workspace_bytes(msp.msp_default_opts(key_rows=4, key_base=kb)) > 0
     ctx.close()
+
+
+def test_plan_struct_matches_the_header(tmp_path):
+    from paper_2507_05045_amd import msp
+    names = [f for f, _ in msp.msp_plan_t._fields_]
+    size, offs = _c_layout(tmp_path, "msp_plan_t", names)
+    assert C.sizeof(msp.msp_plan_t) == size
+    assert [getattr(msp.msp_plan_t, f).offset for f in names] == offs
+
+
+# The largest plans the solver runs: every launch whose size the plan fixes
+# stays below 2^32 work-items, and the windows cover every cell.
+LARGE_PLANS = [
+    ((8, 70), dict(key_rows=5, key_base=1)),
+    ((9, 80), dict(key_rows=5, key_base=1)),
+    ((9, 80), dict(key_rows=4)),
+    ((9, 80), dict(key_rows=4, slice_mod=64)),
+    ((10, 90), dict(key_rows=4, slice_mod=64)),
+    ((10, 90), dict(key_rows=4)),
+    ((10, 90), dict(key_rows=4, slice_mod=64, verify_join=1)),
+    ((6, 50), dict(key_rows=1)),
+    ((6, 50), dict(key_rows=1, verify_join=2)),
+]
+
+
+@pytest.mark.parametrize("shape,kw", LARGE_PLANS, ids=lambda v: str(v))
+def test_largest_plans_fit_the_launch_limits(shape, kw):
+    from paper_2507_05045_amd import autotune, msp
+    from paper_2507_05045_amd.inputs import make_instance
+    inst = make_instance(*shape, 0)
+    ctx = msp.Context(inst.A, inst.d)
+    tuned = autotune.lookup(inst.A, kw["key_rows"], kw.get("key_base", 0)) or {}
+    budget = 64 << 30
+    for opts in ({**kw}, {**kw, **tuned}):
+        pl = ctx.plan(budget=budget, **opts)
+        assert 0 < pl["max_grid_items"] < 2 ** 32, (opts, pl)
+        assert pl["windows"] * pl["cells_per_window"] >= pl["cells"]
+        assert pl["workspace_bytes"] <= budget
+        assert pl["log2_m"] - pl["log2_cells"] == pl["log2_fine"] <= 12
+    ctx.close()
+
+
+def test_plan_picks_the_vector_join_for_large_equal_key_groups():
+    """The (6,50) row-1 key has runs of ~10^5 records per side: the planner
+    decides them by the vector join unless pairwise checks are asked for;
+    (8,70) with four key rows has groups of about one record: pairwise."""
+    from paper_2507_05045_amd import msp
+    from paper_2507_05045_amd.inputs import make_instance
+    big = msp.Context(make_instance(6, 50, 0).A, make_instance(6, 50, 0).d)
+    assert big.plan(key_rows=1)["vector_join"] == 1
+    assert big.plan(key_rows=1, verify_join=2)["vector_join"] == 0
+    every = make_instance(4, 30, 0)
+    ctx4 = msp.Context(every.A, every.d)
+    assert ctx4.plan(key_rows=4, verify_join=1)["vector_join"] == 0   # every row a key row
+    ctx4.close()
+    small = msp.Context(make_instance(8, 70, 0).A, make_instance(8, 70, 0).d)
+    assert small.plan(key_rows=4)["vector_join"] == 0
+    assert small.plan(key_rows=4, verify_join=1)["vector_join"] == 1
+    big.close()
+    small.close()
+
+
+def test_set_allocator_rejects_half_a_pair():
+    from paper_2507_05045_amd import msp
+    a = msp.ALLOC_FN(lambda n, u: None)
+    assert msp.lib.msp_set_allocator(a, msp.RELEASE_FN(), None) == -1
+    assert msp.lib.msp_set_allocator(msp.ALLOC_FN(), msp.RELEASE_FN(), None) == 0

@@ -1,6 +1,10 @@
-"""Batched and served solves on the GPU: every result must be identical
-(H, |S|, solution vectors) to the same instance solved alone, whatever it
-was batched with, and served requests must overlap on the device."""
+"""Batched and served solves on the GPU.  Every instance's result (H, |S|,
+solution vectors) must equal the oracle's (the heap Schroeppel-Shamir
+oracle, solved whole; tests/golden/oracle_batch.json) and the same instance
+solved alone, whatever it was batched with; served requests must overlap on
+the device."""
+import json
+import os
 import sys
 import time
 
@@ -12,6 +16,8 @@ from paper_2507_05045_amd.inputs import make_instance, random_small, stream_inst
 
 pytestmark = pytest.mark.gpu
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_batch.json")
+
 
 def say(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -21,22 +27,35 @@ def result(ctx):
     return ctx.hits(), ctx.num_solutions(), ctx.solutions()
 
 
+def _golden():
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+def _res(e, n):
+    sols = np.array([[int(c) for c in s] for s in e["solutions"]], dtype=np.uint8).reshape(-1, n)
+    return int(e["H"]), e["nsol"], sols
+
+
 def mix():
-    """Instances of uneven (m, n) and key rows, small enough for a test."""
+    """Instances of uneven (m, n) and key rows, with their oracle results."""
     out = []
-    for s in range(3):
-        i = random_small(4, 22, 900 + s, K=8, planted=True)
-        out.append((i, 2))
-    for (m, n, r) in [(4, 30, 1), (5, 40, 1), (6, 50, 2), (5, 40, 1)]:
-        for planted in (False, True):
-            out.append((make_instance(m, n, 7 + m, planted=planted), r))
+    for e in _golden():
+        if "spec" not in e:
+            continue
+        gen, m, n, seed, K, planted, r = e["spec"]
+        inst = (random_small(m, n, seed, K=K, planted=planted) if gen == "random_small"
+                else make_instance(m, n, seed, planted=planted, K=K))
+        assert inst.name == e["name"]
+        out.append((inst, r, _res(e, n)))
+    assert len(out) == 9
     return out
 
 
 def alone(insts):
     from paper_2507_05045_amd import msp
     res = []
-    for inst, r in insts:
+    for inst, r, _ in insts:
         c = msp.Context(inst.A, inst.d)
         c.solve(key_rows=r)
         res.append(result(c))
@@ -50,72 +69,82 @@ def same(a, b, what):
     assert np.array_equal(a[2], b[2]), what
 
 
+def test_mix_oracle_entries_are_pinned():
+    # The stored results of the small mix instances equal brute force.
+    for inst, r, ref in mix()[:3]:
+        o = O.brute(inst.A, inst.d, key_rows=r)
+        same(ref, (o.H, o.nsol, o.solutions), f"golden vs brute force {inst.name}")
+
+
 def test_batch_equals_alone_and_oracle():
     from paper_2507_05045_amd import msp
     insts = mix()
-    ref = alone(insts)
-    for k, (inst, r) in enumerate(insts[:3]):             # the small ones: brute force too
-        o = O.brute(inst.A, inst.d, key_rows=r)
-        same(ref[k], (o.H, o.nsol, o.solutions), f"alone vs oracle {k}")
+    solo = alone(insts)
+    for k, (inst, r, ref) in enumerate(insts):
+        same(solo[k], ref, f"alone vs oracle {inst.name}")
     for slots in (1, 3, 16):
-        ctxs = [msp.Context(i.A, i.d) for i, _ in insts]
+        ctxs = [msp.Context(i.A, i.d) for i, _, _ in insts]
         say("batch slots", slots)
-        rc = msp.batch_solve(ctxs, [dict(key_rows=r) for _, r in insts], max_slots=slots)
+        rc = msp.batch_solve(ctxs, [dict(key_rows=r) for _, r, _ in insts], max_slots=slots)
         assert rc == 0, msp.strerror(rc)
         for k, c in enumerate(ctxs):
-            same(result(c), ref[k], f"batch slots={slots} instance {k}")
+            same(result(c), insts[k][2], f"batch slots={slots} {insts[k][0].name} vs oracle")
             c.close()
 
 
 def test_batch_under_a_tiny_budget_queues():
     from paper_2507_05045_amd import msp
     insts = mix()[:6]
-    ref = alone(insts)
     # Budget that holds about one solve at a time: requests must wait.
     need = max(msp.Context(i.A, i.d).workspace_bytes(msp.msp_default_opts(key_rows=r))
-               for i, r in insts)
-    ctxs = [msp.Context(i.A, i.d) for i, _ in insts]
-    rc = msp.batch_solve(ctxs, [dict(key_rows=r) for _, r in insts], hbm_budget=need + (1 << 20),
+               for i, r, _ in insts)
+    ctxs = [msp.Context(i.A, i.d) for i, _, _ in insts]
+    rc = msp.batch_solve(ctxs, [dict(key_rows=r) for _, r, _ in insts], hbm_budget=need + (1 << 20),
                          max_slots=4)
     assert rc == 0, msp.strerror(rc)
     for k, c in enumerate(ctxs):
-        same(result(c), ref[k], f"tiny budget instance {k}")
+        same(result(c), insts[k][2], f"tiny budget {insts[k][0].name} vs oracle")
 
 
-def test_stream_instances_batched_equal_alone():
+def test_stream_instances_batched_equal_oracle():
     from paper_2507_05045_amd import msp
-    st = [i for i in stream_instances(64) if i.m <= 6][:10]
-    insts = [(i, i.key_rows) for i in st]
-    ref = alone(insts)
-    ctxs = [msp.Context(i.A, i.d) for i, _ in insts]
-    rc = msp.batch_solve(ctxs, [dict(key_rows=r) for _, r in insts], max_slots=8)
+    stream = stream_instances(64)
+    gold = [e for e in _golden() if "stream_index" in e]
+    assert len(gold) == 10
+    insts = [stream[e["stream_index"]] for e in gold]
+    ctxs = [msp.Context(i.A, i.d) for i in insts]
+    rc = msp.batch_solve(ctxs, [dict(key_rows=i.key_rows) for i in insts], max_slots=8)
     assert rc == 0
-    for k, c in enumerate(ctxs):
-        same(result(c), ref[k], f"stream {st[k].name}")
-        if st[k].planted is not None:
-            assert any(np.array_equal(s, st[k].planted) for s in c.solutions())
+    for i, c, e in zip(insts, ctxs, gold):
+        assert i.name == e["name"]
+        same(result(c), _res(e, i.n), f"stream {i.name} vs oracle")
+        if i.planted is not None:
+            assert any(np.array_equal(s, i.planted) for s in c.solutions())
 
 
 def test_server_continuous_batching_overlaps_and_matches():
     from paper_2507_05045_amd import msp
     insts = mix()
-    ref = alone(insts)
     srv = msp.Server(max_slots=4)
-    ctxs = [msp.Context(i.A, i.d) for i, _ in insts]
+    ctxs = [msp.Context(i.A, i.d) for i, _, _ in insts]
     tickets = []
-    for k, ((inst, r), c) in enumerate(zip(insts, ctxs)):
+    for k, ((inst, r, _), c) in enumerate(zip(insts, ctxs)):
         tickets.append(srv.submit(c, key_rows=r))
         time.sleep(0.002 * (k % 3))                      # staggered arrivals
     for t in tickets:
         assert srv.wait(t) == 0
     times = [srv.times(t) for t in tickets]
     for k, c in enumerate(ctxs):
-        same(result(c), ref[k], f"served instance {k}")
+        same(result(c), insts[k][2], f"served {insts[k][0].name} vs oracle")
     # Continuous batching: some requests were in flight at the same time.
     overlap = any(times[a][2] < times[b][3] and times[b][2] < times[a][3]
                   for a in range(len(times)) for b in range(a + 1, len(times)))
     assert overlap, times
     assert all(t[0] <= t[1] <= t[2] <= t[3] for t in times)
+    # A finished request's context is free again at once.
+    t2 = srv.submit(ctxs[0], key_rows=insts[0][1])
+    assert srv.wait(t2) == 0
+    same(result(ctxs[0]), insts[0][2], "resubmitted")
     srv.stop()
 
 
@@ -125,17 +154,54 @@ def test_server_cancel_and_errors():
     big = make_instance(8, 70, 3)
     cb = msp.Context(big.A, big.d)
     tb = srv.submit(cb, key_rows=4)
-    small = make_instance(4, 30, 0, planted=True)
-    cs = msp.Context(small.A, small.d)
+    small = [e for e in mix() if e[0].name == "msp_4_30_s11_planted"][0]
+    cs = msp.Context(small[0].A, small[0].d)
     ts = srv.submit(cs, key_rows=1)
     srv.cancel(tb)
     assert srv.wait(tb) == msp.MSP_E_CANCELLED
     assert srv.wait(ts) == 0
-    ref = alone([(small, 1)])[0]
-    same(result(cs), ref, "small request next to a cancelled one")
+    same(result(cs), small[2], "small request next to a cancelled one, vs oracle")
     # A context cannot be in two requests at once.
     t1 = srv.submit(cs, key_rows=1)
     with pytest.raises(msp.MspError):
         srv.submit(cs, key_rows=1)
     assert srv.wait(t1) == 0
     srv.stop()
+
+
+def test_torch_allocator_arena():
+    """msp_set_allocator: solves, batches and a server whose device memory
+    comes from PyTorch's allocator give the oracle's results, and every
+    allocation is released."""
+    from paper_2507_05045_amd import msp
+    insts = mix()
+    with msp.TorchArena() as arena:
+        c = msp.Context(insts[4][0].A, insts[4][0].d)
+        c.solve(use_torch=False, key_rows=insts[4][1])     # library-owned workspace
+        same(result(c), insts[4][2], "solve, torch arena")
+        assert arena.requests >= 1 and len(arena.live) == 1
+        c.close()
+        assert len(arena.live) == 0
+        ctxs = [msp.Context(i.A, i.d) for i, _, _ in insts]
+        rc = msp.batch_solve(ctxs, [dict(key_rows=r) for _, r, _ in insts],
+                             hbm_budget=8 << 30, max_slots=4)
+        assert rc == 0, msp.strerror(rc)
+        for k, cc in enumerate(ctxs):
+            same(result(cc), insts[k][2], f"batch in torch arena {insts[k][0].name}")
+        assert len(arena.live) == 0
+        srv = msp.Server(hbm_budget=8 << 30, max_slots=4)
+        assert len(arena.live) == 1
+        ts = [srv.submit(cc, key_rows=r) for cc, (_, r, _) in zip(ctxs, insts)]
+        for t in ts:
+            assert srv.wait(t) == 0
+        for k, cc in enumerate(ctxs):
+            same(result(cc), insts[k][2], f"served in torch arena {insts[k][0].name}")
+        srv.stop()
+        assert len(arena.live) == 0
+        n_req = arena.requests
+    # hipMalloc again once the allocator is reset.
+    c = msp.Context(insts[0][0].A, insts[0][0].d)
+    c.solve(use_torch=False, key_rows=insts[0][1])
+    same(result(c), insts[0][2], "after reset")
+    c.close()
+    assert arena.requests == n_req

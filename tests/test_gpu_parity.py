@@ -61,7 +61,9 @@ def test_small_random_vs_brute_force(case):
         say("case", case, "seed", seed)
         ref = O.brute(inst.A, inst.d, key_rows=case["r"])
         same(gsolve(inst.A, inst.d, key_rows=case["r"]), ref, f"default {case} {seed}")
-        # exact buckets decided by the vector join (no effect in hash mode)
+        # every run pair checked pair by pair, and decided by the vector join
+        same(gsolve(inst.A, inst.d, key_rows=case["r"], verify_join=2), ref,
+             f"pairwise {case} {seed}")
         same(gsolve(inst.A, inst.d, key_rows=case["r"], verify_join=1), ref,
              f"vector join {case} {seed}")
         # force hash buckets (modulus below K_d) and a few cell layouts
@@ -69,7 +71,7 @@ def test_small_random_vs_brute_force(case):
         for lm, lc, parts, jv in [(3, 1, 1, 1), (5, 2, 3, 2), (6, 6, 2, 0), (6, 3, 2, 2),
                                   (5, 2, 8, 1), (6, 3, 16, 2), (3, 1, 2, 3), (8, 3, 8, 3)]:
             g = gsolve(inst.A, inst.d, key_rows=case["r"], log2_m=lm, log2_cells=lc, parts=parts,
-                       join_variant=jv)
+                       join_variant=jv, verify_join=2)
             same(g, ref, f"M=2^{lm} T=2^{lc} P={parts} join={jv} {case} {seed}")
             # hash buckets decided by the vector join inside the grouped kernel
             g = gsolve(inst.A, inst.d, key_rows=case["r"], log2_m=lm, log2_cells=lc, parts=parts,
@@ -98,9 +100,11 @@ def test_mixed_radix_key_vs_brute_force(case):
         same(gsolve(inst.A, inst.d, key_rows=r, key_base=1), ref, f"default {case} {seed}")
         same(gsolve(inst.A, inst.d, key_rows=r, key_base=1, verify_join=1), ref,
              f"vector join {case} {seed}")
+        same(gsolve(inst.A, inst.d, key_rows=r, key_base=1, verify_join=2), ref,
+             f"pairwise {case} {seed}")
         for lm, lc, parts, jv in [(5, 2, 3, 2), (6, 3, 16, 1), (7, 3, 8, 3)]:
             g = gsolve(inst.A, inst.d, key_rows=r, key_base=1, log2_m=lm, log2_cells=lc,
-                       parts=parts, join_variant=jv)
+                       parts=parts, join_variant=jv, verify_join=2)
             same(g, ref, f"M=2^{lm} T=2^{lc} P={parts} join={jv} {case} {seed}")
         for s in (0, 5):
             o = O.brute(inst.A, inst.d, key_rows=r, slice_mod=8, slice_res=s, key_base=1)
@@ -117,12 +121,13 @@ def test_mixed_radix_carry_instance_and_bad_radix():
     ref = O.brute(A, d, key_rows=2, key_base=1)
     assert ref.H == 6 and ref.nsol == 6
     same(gsolve(A, d, key_rows=2, key_base=1), ref, "carry instance")
-    same(gsolve(A, d, key_rows=2, key_base=1, log2_m=2, log2_cells=1), ref, "carry, hash")
+    same(gsolve(A, d, key_rows=2, key_base=1, log2_m=2, log2_cells=1, verify_join=2), ref,
+         "carry, hash")
     with pytest.raises(msp.MspError):
         gsolve(A, d, key_rows=2, key_base=2)
     ctx = msp.Context(A, d)
     for jv in (1, 2, 3):
-        ctx.solve(key_rows=2, key_base=1, log2_m=2, log2_cells=1, join_variant=jv)
+        ctx.solve(key_rows=2, key_base=1, log2_m=2, log2_cells=1, join_variant=jv, verify_join=2)
         st = ctx.stats()
         assert (st["key_base"], st["join_grouped"], st["exact_buckets"]) == (1, jv - 1, 0)
         assert ctx.hits() == 6
@@ -137,8 +142,9 @@ def test_many_buckets_per_window_every_join():
     kw = dict(key_rows=5, key_base=1, slice_mod=64, slice_res=0)
     ref = gsolve(inst.A, inst.d, **kw)
     assert ref.H > 0
-    for extra in (dict(join_variant=1), dict(join_variant=2), dict(join_variant=3),
-                  dict(verify_join=1), dict(log2_cells=19, join_variant=2)):
+    for extra in (dict(join_variant=1, verify_join=2), dict(join_variant=2, verify_join=2),
+                  dict(join_variant=3, verify_join=2), dict(verify_join=1),
+                  dict(log2_cells=19, join_variant=2, verify_join=2)):
         say("many buckets", extra)
         same(gsolve(inst.A, inst.d, **kw, **extra), ref, f"{extra}")
 
@@ -148,7 +154,9 @@ def test_tiny_and_empty_quarters(n):
     A = np.array([[2] * n, [1] * n, [3] * n], dtype=np.int32)
     d = np.array([2, 1, 3], dtype=np.int32)
     for r in (1, 2, 3):
-        same(gsolve(A, d, key_rows=r), O.brute(A, d, key_rows=r), f"n={n} r={r}")
+        for vj in (0, 1, 2):
+            same(gsolve(A, d, key_rows=r, verify_join=vj), O.brute(A, d, key_rows=r),
+                 f"n={n} r={r} verify_join={vj}")
 
 
 def test_degenerate_instances():
@@ -233,17 +241,17 @@ def test_full_configs_vs_oracle(cfg):
         inst = _golden_instance(e)
         say("config", e["name"])
         kb = e.get("key_base", 0)
-        g = gsolve(inst.A, inst.d, key_rows=e["key_rows"], key_base=kb)
-        same(g, _golden_result(e, n), e["name"])
-        if inst.planted is not None:
-            assert any(np.array_equal(s, inst.planted) for s in g.solutions)
-        v = gsolve(inst.A, inst.d, key_rows=e["key_rows"], key_base=kb, verify_join=1)
-        same(v, _golden_result(e, n), e["name"] + " vector join")
+        for vj, what in ((0, "planner's choice"), (1, "vector join"), (2, "pairwise")):
+            g = gsolve(inst.A, inst.d, key_rows=e["key_rows"], key_base=kb, verify_join=vj)
+            same(g, _golden_result(e, n), f"{e['name']} {what}")
+            if inst.planted is not None:
+                assert any(np.array_equal(s, inst.planted) for s in g.solutions)
         if e["key_rows"] >= 4:
             # ~256 records per bucket and side: the wavefront-per-bucket join
             # in several 64-record chunks, and the heavy join past 256.
             for jv in (1, 3):
-                g = gsolve(inst.A, inst.d, key_rows=e["key_rows"], key_base=kb, join_variant=jv)
+                g = gsolve(inst.A, inst.d, key_rows=e["key_rows"], key_base=kb, join_variant=jv,
+                           verify_join=2)
                 same(g, _golden_result(e, n), e["name"] + f" join variant {jv}")
 
 
@@ -254,29 +262,70 @@ def test_large_configs_sampled_residue_classes(cfg):
     for e in _golden():
         if (e["m"], e["n"], e.get("K", 100)) != (m, n, K):
             continue
+        if e["slice_mod"] < (1 << 20):
+            continue                     # multi-cell slices: test_multi_cell_slice_shipped_plan
         inst = _golden_instance(e)
         r, kb = e["key_rows"], e.get("key_base", 0)
         say("sampled", e["name"], "r", r, "key_base", kb, e["slice_mod"], e["slice_res"])
-        g = gsolve(inst.A, inst.d, key_rows=r, key_base=kb, slice_mod=e["slice_mod"],
-                   slice_res=e["slice_res"])
-        same(g, _golden_result(e, n), f"{e['name']} rho={e['slice_res']}")
-        if inst.planted is not None:
-            assert any(np.array_equal(s, inst.planted) for s in g.solutions)
-        v = gsolve(inst.A, inst.d, key_rows=r, key_base=kb, slice_mod=e["slice_mod"],
-                   slice_res=e["slice_res"], verify_join=1)
-        same(v, _golden_result(e, n), f"{e['name']} rho={e['slice_res']} vector join")
+        for vj, what in ((0, "planner's choice"), (1, "vector join"), (2, "pairwise")):
+            g = gsolve(inst.A, inst.d, key_rows=r, key_base=kb, slice_mod=e["slice_mod"],
+                       slice_res=e["slice_res"], verify_join=vj)
+            same(g, _golden_result(e, n), f"{e['name']} rho={e['slice_res']} {what}")
+            if inst.planted is not None:
+                assert any(np.array_equal(s, inst.planted) for s in g.solutions)
 
 
-def test_8_70_full_solve_properties():
+def test_8_70_slices_partition_the_full_solve():
+    """The (8,70) planted twin solved whole and as its 64 residue slices
+    k_L mod 64: the slices' H add up to the whole H and their solution sets
+    to the whole set.  Five key rows in the mixed radix, and the vector join,
+    reach the same solution set by other routes."""
     inst = make_instance(8, 70, 0, planted=True)
     say("full (8,70) planted")
-    g = gsolve(inst.A, inst.d, key_rows=4)
+    g = gsolve(inst.A, inst.d, key_rows=4, verify_join=2)
     assert satisfies(inst.A, inst.d, g.solutions)
     assert any(np.array_equal(s, inst.planted) for s in g.solutions)
     assert g.nsol == g.solutions.shape[0]
-    # Residue classes mod 64 partition the solve.
-    parts = [gsolve(inst.A, inst.d, key_rows=4, slice_mod=64, slice_res=s) for s in (0, 1)]
-    assert all(p.H < g.H for p in parts)
+    tot, sols = 0, []
+    for s in range(64):
+        p = gsolve(inst.A, inst.d, key_rows=4, slice_mod=64, slice_res=s, verify_join=2)
+        tot += p.H
+        sols += [bytes(x) for x in p.solutions]
+    say("slices", tot, g.H, len(sols), g.nsol)
+    assert tot == g.H
+    assert sorted(sols) == sorted(bytes(x) for x in g.solutions)
+    sset = {bytes(x) for x in g.solutions}
+    r5 = gsolve(inst.A, inst.d, key_rows=5, key_base=1)
+    assert {bytes(x) for x in r5.solutions} == sset and r5.nsol == g.nsol
+    assert r5.H <= g.H
+    vj = gsolve(inst.A, inst.d, key_rows=4, verify_join=1)
+    assert vj.H == g.H and {bytes(x) for x in vj.solutions} == sset
+
+
+def test_multi_cell_slice_shipped_plan():
+    """A (8,70) slice k_L mod 256 that spans many residue cells, against the
+    MITM oracle: with the shipped autotuned plan as it is, and split into
+    several windows."""
+    from paper_2507_05045_amd import autotune, msp
+    for e in _golden():
+        if (e["m"], e["n"], e["slice_mod"]) != (8, 70, 256):
+            continue
+        inst = _golden_instance(e)
+        ref = _golden_result(e, 70)
+        plan = autotune.lookup(inst.A, 4) or {}
+        assert plan, "no shipped plan for (8,70)"
+        kw = dict(key_rows=4, slice_mod=256, slice_res=e["slice_res"], **plan)
+        for extra in (dict(), dict(window_records=1 << 24), dict(verify_join=2),
+                      dict(verify_join=2, window_records=1 << 24)):
+            ctx = msp.Context(inst.A, inst.d)
+            ctx.solve(**kw, **extra)
+            st = ctx.stats()
+            say("multi-cell slice", e["name"], extra, st["windows"], st["parts"], st["log2_cells"])
+            same(ctx.result(), ref, f"{e['name']} {extra}")
+            assert st["parts"] == plan.get("parts", st["parts"])
+            if "window_records" in extra:
+                assert st["windows"] >= 4
+            ctx.close()
 
 
 @pytest.mark.parametrize("lm", [6, 8])
@@ -289,7 +338,7 @@ def test_oversized_buckets_vs_oracle(lm):
         say("oversized", inst.name, lm)
         for jv in (1, 2):
             same(gsolve(inst.A, inst.d, key_rows=2, log2_m=lm, log2_cells=min(lm, 4),
-                        join_variant=jv), ref, f"{inst.name} M=2^{lm} join={jv}")
+                        join_variant=jv, verify_join=2), ref, f"{inst.name} M=2^{lm} join={jv}")
         # the vector join takes these buckets in left chunks (heavy kernel)
         same(gsolve(inst.A, inst.d, key_rows=2, log2_m=lm, log2_cells=min(lm, 4), verify_join=1),
              ref, f"{inst.name} M=2^{lm} vector join")
@@ -305,8 +354,8 @@ def test_grouped_join_mid_buckets_vs_oracle(lm):
         ref = O.ss_heap(inst.A, inst.d, key_rows=2)
         say("grouped mid buckets", inst.name, lm)
         for lc in (4, 6):
-            same(gsolve(inst.A, inst.d, key_rows=2, log2_m=lm, log2_cells=lc, join_variant=2),
-                 ref, f"{inst.name} M=2^{lm} T=2^{lc} grouped")
+            same(gsolve(inst.A, inst.d, key_rows=2, log2_m=lm, log2_cells=lc, join_variant=2,
+                        verify_join=2), ref, f"{inst.name} M=2^{lm} T=2^{lc} grouped")
             same(gsolve(inst.A, inst.d, key_rows=2, log2_m=lm, log2_cells=lc, verify_join=1),
                  ref, f"{inst.name} M=2^{lm} T=2^{lc} vector join")
 
@@ -329,19 +378,36 @@ def test_vector_join_ties_and_windows():
             ctx.close()
 
 
+def _first_only_vs_oracle(inst, r, **kw):
+    """First-solution mode against the oracle: the solve stops after the
+    first residue window with a solution; its H and solutions are exactly the
+    oracle's over the cells it processed (classes k_L mod T below cells_done)."""
+    from paper_2507_05045_amd import msp
+    ctx = msp.Context(inst.A, inst.d)
+    ctx.solve(key_rows=r, first_only=1, **kw)
+    first = ctx.result()
+    st = first.stats
+    ctx.close()
+    assert first.nsol >= 1
+    assert st["windows"] <= st["windows_total"] and st["cells_done"] >= 1
+    ref = O.mitm(inst.A, inst.d, r, st["log2_cells"], 0, st["cells_done"])
+    same(first, ref, f"{inst.name} first solution over {st['cells_done']} cells")
+    assert satisfies(inst.A, inst.d, first.solutions)
+    return first, st
+
+
 def test_first_solution_mode():
     # Algorithm 2 returns the first x: the solve stops after the first residue
-    # window that yields a solution; what it returns is part of the full set.
-    from paper_2507_05045_amd import msp
+    # window that yields a solution.
+    for m, n, r in ((5, 40, 2), (6, 50, 2)):
+        inst = make_instance(m, n, 0, planted=True)
+        first, st = _first_only_vs_oracle(inst, r, window_records=1 << 16, verify_join=2)
+        say("first solution", inst.name, st["windows"], "/", st["windows_total"])
+        _first_only_vs_oracle(inst, r, window_records=1 << 16, verify_join=1)
+    # (8,70): the returned solutions satisfy Ax = d and lie in the full set.
     inst = make_instance(8, 70, 0, planted=True)
     full = gsolve(inst.A, inst.d, key_rows=4)
-    ctx = msp.Context(inst.A, inst.d)
-    ctx.solve(key_rows=4, first_only=1, window_records=1 << 28)
-    first = ctx.result()
-    assert 1 <= first.nsol <= full.nsol
-    assert {bytes(x) for x in first.solutions} <= {bytes(x) for x in full.solutions}
-    assert first.H <= full.H
-    st = first.stats
-    assert st["windows"] <= st["windows_total"]
-    assert st["complete"] == (1 if first.H == full.H else 0) or first.nsol == full.nsol
-    ctx.close()
+    g = gsolve(inst.A, inst.d, key_rows=4, first_only=1, window_records=1 << 28)
+    assert 1 <= g.nsol <= full.nsol and g.H <= full.H
+    assert satisfies(inst.A, inst.d, g.solutions)
+    assert {bytes(x) for x in g.solutions} <= {bytes(x) for x in full.solutions}
