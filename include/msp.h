@@ -97,6 +97,16 @@ typedef struct {
                                  holds more rows.  Both give the same H, |S| and
                                  solutions on a whole solve; a slice keeps
                                  k_L mod slice_mod of the key in use             */
+    int32_t  row_fingerprint; /* what a half record stores of the non-key rows:
+                                 1 = one 32-bit fingerprint h(v) = sum_i c_i v_i mod
+                                 2^32 (linear, so h(left) = h(a) + h(b) and the right
+                                 side stores h(d) - h(c) - h(e)); equal fingerprints
+                                 are candidates, each checked exactly on the packed
+                                 rows of its four quarter subsets; 2 = the packed
+                                 rows themselves (2 rows per word); 0 = planner:
+                                 the fingerprint when the rows take 2 or more words.
+                                 Same H, |S| and solutions                        */
+    int32_t  reserved0;
 } msp_opts;
 
 /* Per-solve statistics; phase times are measured with HIP events on the
@@ -124,7 +134,7 @@ typedef struct {
     int32_t  join_grouped;    /* hash buckets: 0 = chains, 1 = contiguous key groups,
                                  2 = one wavefront per bucket                        */
     int32_t  key_base;        /* the key radix used (msp_opts.key_base)              */
-    int32_t  reserved;
+    int32_t  row_fingerprint; /* 1: half records carried a row fingerprint          */
     uint64_t cells_done;      /* residue cells processed, in cell order: the cells
                                  k_first + i * k_step, i < cells_done (k_step = 1 and
                                  k_first = 0 without a slice); all of them unless
@@ -219,12 +229,12 @@ typedef struct {
     int32_t  key_rows, log2_m, log2_cells, log2_fine;  /* r, M = 2^log2_m, cells, fine buckets */
     int32_t  parts;            /* work-groups per cell in count and scatter              */
     int32_t  exact_buckets;    /* 1: each bucket holds one key value                     */
-    int32_t  words;            /* 32-bit words of packed non-key rows per record         */
+    int32_t  words;            /* 32-bit words of the packed non-key rows (2 rows each)  */
     int32_t  join_variant;     /* hash buckets: 0 chains, 1 key groups, 2 one wavefront  */
     int32_t  vector_join;      /* 1: equal-key runs decided by the vector join           */
     int32_t  key_base;         /* key radix (msp_opts.key_base)                          */
     int32_t  infeasible;       /* 1: a key row cannot hold; no GPU work is done          */
-    int32_t  reserved;
+    int32_t  row_fingerprint;  /* 1: half records carry a row fingerprint               */
     uint64_t cells;            /* residue cells visited (all, or those of the slice)     */
     uint64_t cells_per_window; /* planned; the count pass may halve it                   */
     uint64_t windows;          /* planned windows                                        */

@@ -100,6 +100,7 @@ struct Sizes {
     uint64_t total = 0;      // workspace bytes
     // offsets into the workspace
     uint64_t o_qraw[4], o_qsrt[4], o_qcnt[4], o_qcur[4], o_cnt[2], o_off[2], o_rec[2];
+    uint64_t o_qvraw[4], o_qvsrt[4], o_offt[2];
     uint64_t o_runs, o_tiles, o_sol, o_scal, o_scan, scan_bytes, o_colw, o_rows;
     uint64_t o_iruns, o_itiles, o_idx, n_iruns, o_heavy, idx_n;
     uint64_t o_vtab, vtab_slots;
@@ -227,6 +228,14 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
         if (2 * w + 1 < p.nv) hi = (uint32_t)std::min<int32_t>(c->d[r + 2 * w + 1], 65535);
         p.dpk[w] = lo | (hi << 16);
     }
+    // Half records carry the packed rows (W words) or one fingerprint word;
+    // fingerprint matches are candidates that the joins check exactly.
+    if (o.row_fingerprint < 0 || o.row_fingerprint > 2) return MSP_E_INVALID;
+    p.fp = o.row_fingerprint == 2 ? 0 : o.row_fingerprint == 1 ? (p.W >= 1) : (p.W >= 2);
+    p.Wr = p.fp ? 1 : p.W;
+    p.hd = 0;
+    for (int v = 0; v < p.nv; ++v) p.hd += kFpMul[v] * (uint32_t)c->d[r + v];
+    for (int x = 0; x < 4; ++x) p.qv[x] = nullptr;
 
     // Residue modulus M and cells T.  Exact buckets when M can exceed K_d
     // cheaply (small keys, e.g. one key row); else buckets of ~1K records.
@@ -310,7 +319,8 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
     const uint64_t all_rec = std::max((uint64_t)p.Q[0] * p.Q[1], (uint64_t)p.Q[2] * p.Q[3]);
     const uint64_t thin = (o.slice_mod > 0 && (uint64_t)o.slice_mod > T) ? (uint64_t)o.slice_mod / T : 1;
     const uint64_t est_cell = std::max<uint64_t>(1, all_rec / T / thin);
-    const uint64_t rb = rec_bytes(p.W), qb = qrec_bytes(p.W);
+    const uint64_t rb = rec_bytes(p.Wr), qb = qrec_bytes(p.Wr);
+    const uint64_t qvb = p.fp ? 4ull * p.W : 0;     // packed rows per quarter subset (fp)
     const int F = 1 << p.log2F;
     z.sol_cap = o.max_solutions ? o.max_solutions : ((uint64_t)1 << 20);
     // A window that covers every cell needs at most Q_A*Q_B records per
@@ -352,11 +362,14 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
         auto take = [&](uint64_t bytes) { uint64_t o2 = off; off += align_up(bytes, 256); return o2; };
         for (int x = 0; x < 4; ++x) z.o_qraw[x] = take((uint64_t)p.Q[x] * qb);
         for (int x = 0; x < 4; ++x) z.o_qsrt[x] = take((uint64_t)p.Q[x] * qb);
+        for (int x = 0; x < 4; ++x) z.o_qvraw[x] = take((uint64_t)p.Q[x] * qvb + 4);
+        for (int x = 0; x < 4; ++x) z.o_qvsrt[x] = take((uint64_t)p.Q[x] * qvb + 4);
         for (int x = 0; x < 4; ++x) z.o_qcnt[x] = take((T + 1) * 4);
         for (int x = 0; x < 4; ++x) z.o_qcur[x] = take((T + 1) * 4);
         const uint64_t ncnt = kw * F * (uint64_t)parts + 1;
         for (int s = 0; s < 2; ++s) z.o_cnt[s] = take(ncnt * 4);
         for (int s = 0; s < 2; ++s) z.o_off[s] = take(ncnt * 4);
+        for (int s = 0; s < 2; ++s) z.o_offt[s] = take(ncnt * 4);
         for (int s = 0; s < 2; ++s) z.o_rec[s] = take(cap_rec * rb);
         z.o_runs = take(kw * F * sizeof(RunPair));
         z.o_tiles = take((kw * F + 1) * 4);
@@ -544,10 +557,14 @@ void job_carve(Job &j) {
         j.b.qsrt[x] = ws + z.o_qsrt[x];
         j.b.qcnt[x] = (uint32_t *)(ws + z.o_qcnt[x]);
         j.b.qcur[x] = (uint32_t *)(ws + z.o_qcur[x]);
+        j.b.qvraw[x] = (uint32_t *)(ws + z.o_qvraw[x]);
+        j.b.qvsrt[x] = (uint32_t *)(ws + z.o_qvsrt[x]);
+        j.P.p.qv[x] = j.P.p.fp ? j.b.qvsrt[x] : nullptr;
     }
     for (int sd = 0; sd < 2; ++sd) {
         j.b.cnt[sd] = (uint32_t *)(ws + z.o_cnt[sd]);
         j.b.off[sd] = (uint32_t *)(ws + z.o_off[sd]);
+        j.b.offt[sd] = (uint32_t *)(ws + z.o_offt[sd]);
         j.b.rec[sd] = ws + z.o_rec[sd];
     }
     j.b.runs = (RunPair *)(ws + z.o_runs);
@@ -586,8 +603,11 @@ int enqueue_count(Job &j) {
     JCHK(ev_rec(j, E_C0));
     JCHK(launch_count(p, j.b, (int64_t)j.idx, (int32_t)j.K, j.s));
     JCHK(ev_rec(j, E_C1));
-    JCHK(scan_u32(j.b.cnt[0], j.b.off[0], ncnt, &j.b.scal[S_TOT_L], j.b.scan_tmp, j.b.scan_tmp_bytes, j.s));
-    JCHK(scan_u32(j.b.cnt[1], j.b.off[1], ncnt, &j.b.scal[S_TOT_R], j.b.scan_tmp, j.b.scan_tmp_bytes, j.s));
+    const uint32_t F = 1u << p.log2F, P = (uint32_t)p.parts;
+    JCHK(scan_counts(j.b.cnt[0], j.b.off[0], j.b.offt[0], ncnt, F, P, &j.b.scal[S_TOT_L],
+                     j.b.scan_tmp, j.b.scan_tmp_bytes, j.s));
+    JCHK(scan_counts(j.b.cnt[1], j.b.off[1], j.b.offt[1], ncnt, F, P, &j.b.scal[S_TOT_R],
+                     j.b.scan_tmp, j.b.scan_tmp_bytes, j.s));
     JCHK(ev_rec(j, E_C2));
     JCHK(hipMemcpyAsync(j.hs, j.b.scal, S_COUNT * 8, hipMemcpyDeviceToHost, j.s));
     return MSP_OK;
@@ -793,7 +813,8 @@ void job_init_stats(Job &j) {
     j.st.parts = p.parts;
     j.st.exact_buckets = p.exact;
     j.st.words = p.W;
-    j.st.record_bytes = rec_bytes(p.W);
+    j.st.record_bytes = rec_bytes(p.Wr);
+    j.st.row_fingerprint = p.fp;
     j.st.vector_join = p.vjoin;
     j.st.join_grouped = p.exact ? 0 : p.join_grouped;
     j.st.key_base = j.o.key_base;
@@ -1109,7 +1130,8 @@ int msp_plan(const msp_ctx *c, const msp_opts *opts, msp_plan_t *out) {
     t.cells_per_window = z.kwin;
     t.windows = (z.ncells + z.kwin - 1) / std::max<uint64_t>(z.kwin, 1);
     t.window_records = z.cap_rec;
-    t.record_bytes = rec_bytes(p.W);
+    t.record_bytes = rec_bytes(p.Wr);
+    t.row_fingerprint = p.fp;
     t.workspace_bytes = z.total;
     t.max_grid_items = z.max_items;
     *out = t;

@@ -19,6 +19,14 @@ constexpr int kLightGroup = 256;    // largest left group the light join verifie
 constexpr uint32_t kGroupCap = 1344;   // left records per bucket in the grouped join
 constexpr uint32_t kGroupSlots = 2048; // its LDS table (at most two-thirds full)
 
+// Multipliers of the row fingerprint h(v) = sum_i kFpMul[i] * v_i mod 2^32
+// over the non-key rows (odd constants).  h is linear, so a half record's
+// fingerprint is the sum of its two quarters', and the right side stores
+// h(d) - h(v_c) - h(v_e).
+constexpr uint32_t kFpMul[2 * kMaxWords] = {0x9E3779B1u, 0x85EBCA77u, 0xC2B2AE3Du, 0x27D4EB2Fu,
+                                            0x165667B1u, 0xD3A2646Du, 0xFD7046C5u, 0xB55A4F09u,
+                                            0x8F1BBCDBu, 0x6C8E9CF5u};
+
 // Everything the kernels need to know about one solve.
 struct Plan {
     int32_t m, n, r, nv, W;          // rows, columns, key rows, non-key rows, words
@@ -35,6 +43,10 @@ struct Plan {
     int64_t kstep, kfirst;           // cell k = kfirst + idx * kstep
     uint32_t dpk[kMaxWords];         // packed non-key right-hand sides
     uint32_t Q[4];                   // quarter sizes
+    int32_t fp;                      // 1: half records carry a row fingerprint, not the rows
+    int32_t Wr;                      // 32-bit words per half record and quarter record (1 with fp)
+    uint32_t hd;                     // fingerprint of the non-key right-hand sides
+    const uint32_t *qv[4];           // with fp: packed rows (W words) of the sorted quarters
 };
 
 // A quarter subset: 1-D key (for quarter C: K_d - key), subset mask, packed
@@ -69,10 +81,13 @@ struct RunPair {
 struct DevBufs {
     void *qraw[4];                   // unsorted quarter records
     void *qsrt[4];                   // quarter records sorted by residue cell
+    uint32_t *qvraw[4];              // with fp: packed rows of the quarter subsets, raw order
+    uint32_t *qvsrt[4];              // ... and in sorted order
     uint32_t *qcnt[4];               // per-cell counts, then exclusive offsets (T+1)
     uint32_t *qcur[4];               // scatter cursors (T)
     uint32_t *cnt[2];                // window counts per side (K*F*P + 1)
-    uint32_t *off[2];                // scanned offsets per side
+    uint32_t *off[2];                // scanned offsets per side, bucket order [c][f][p]
+    uint32_t *offt[2];               // the same offsets part-major [c][p][f]
     void *rec[2];                    // window records per side
     RunPair *runs;                   // run pairs for the tiled verify (record ranges)
     uint32_t *tiles;                 // per run pair tile counts -> offsets (+1)
@@ -121,6 +136,10 @@ hipError_t launch_tile_counts(const Plan &p, const DevBufs &b, uint32_t nruns, i
 hipError_t scan_u32(const uint32_t *in, uint32_t *out, size_t n, uint64_t *total64,
                     void *tmp, size_t tmp_bytes, hipStream_t st);
 size_t scan_tmp_bytes(size_t n);
+// Scan of the count pass's part-major counts in bucket order: offsets in
+// bucket order to `out` (out[n] = total) and part-major to `out_t`.
+hipError_t scan_counts(const uint32_t *in, uint32_t *out, uint32_t *out_t, size_t n, uint32_t F,
+                       uint32_t P, uint64_t *total64, void *tmp, size_t tmp_bytes, hipStream_t st);
 
 size_t qrec_bytes(int W);
 size_t rec_bytes(int W);

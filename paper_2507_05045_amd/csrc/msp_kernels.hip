@@ -127,7 +127,7 @@ __device__ __forceinline__ uint64_t half_mask(const Plan &p, const QPtrs<W> &qs,
 template <int W>
 __global__ __launch_bounds__(256) void k_quarter_gen(Plan p, const int64_t *__restrict__ colw,
                                                      const uint16_t *__restrict__ rows,
-                                                     QPtrs<W> out, UPtrs cnt) {
+                                                     QPtrs<W> out, UPtrs cnt, UPtrs qvec) {
     __shared__ int64_t s_w[96];
     __shared__ uint16_t s_rows[kMaxWords * 2 * 96];
     for (int i = threadIdx.x; i < p.n; i += blockDim.x) s_w[i] = colw[i];
@@ -156,8 +156,18 @@ __global__ __launch_bounds__(256) void k_quarter_gen(Plan p, const int64_t *__re
     QRec<W> r;
     r.key = key;
     r.mask = u;
+    if (p.fp) {
+        // Fingerprint: sum_v kFpMul[v] * s_v mod 2^32 (linear, so the halves
+        // add up); the packed rows go to their own array for exact checks.
+        uint32_t h = 0;
 #pragma unroll
-    for (int w = 0; w < (W > 0 ? W : 1); ++w) r.vec[w] = s[2 * w] | (s[2 * w + 1] << 16);
+        for (int v = 0; v < kMaxWords * 2; ++v) h += kFpMul[v] * s[v];
+        r.vec[0] = h;
+        for (int w = 0; w < p.W; ++w) qvec.q[x][(size_t)u * p.W + w] = s[2 * w] | (s[2 * w + 1] << 16);
+    } else {
+#pragma unroll
+        for (int w = 0; w < (W > 0 ? W : 1); ++w) r.vec[w] = s[2 * w] | (s[2 * w + 1] << 16);
+    }
     out.q[x][u] = r;
     const uint32_t T = 1u << p.log2T;
     atomicAdd(&cnt.q[x][(uint32_t)key & (T - 1)], 1u);
@@ -166,7 +176,7 @@ __global__ __launch_bounds__(256) void k_quarter_gen(Plan p, const int64_t *__re
 // Counting-sort scatter of each quarter by residue cell.
 template <int W>
 __global__ __launch_bounds__(256) void k_quarter_sort(Plan p, QPtrs<W> raw, QPtrs<W> srt,
-                                                      UPtrs cur) {
+                                                      UPtrs cur, UPtrs vraw, UPtrs vsrt) {
     uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int x = 0;
     while (x < 4 && g >= p.Q[x]) { g -= p.Q[x]; ++x; }
@@ -175,6 +185,9 @@ __global__ __launch_bounds__(256) void k_quarter_sort(Plan p, QPtrs<W> raw, QPtr
     const uint32_t T = 1u << p.log2T;
     const uint32_t pos = atomicAdd(&cur.q[x][(uint32_t)r.key & (T - 1)], 1u);
     srt.q[x][pos] = r;
+    if (p.fp)
+        for (int w = 0; w < p.W; ++w)
+            vsrt.q[x][(size_t)pos * p.W + w] = vraw.q[x][(size_t)g * p.W + w];
 }
 
 // Work-group -> (cell in window, part).  Work-groups are dealt to the 8 XCDs
@@ -235,7 +248,6 @@ __global__ __launch_bounds__(256) void k_count(Plan p, const QRec<W> *__restrict
     const uint32_t *ioff = side ? offD : offB;
     const uint64_t Qo = side ? p.Q[2] : p.Q[0];
     uint32_t *cnt = side ? cntR : cntL;
-    const uint64_t base = ((uint64_t)cw * F) * P + part;
     for (int f = t; f < F; f += 256) s_f[f] = 0u;
     if (t == 0) s_pairs = 0;
     __syncthreads();
@@ -280,7 +292,11 @@ __global__ __launch_bounds__(256) void k_count(Plan p, const QRec<W> *__restrict
     }
     if (npairs) atomicAdd(&s_pairs, (unsigned long long)npairs);
     __syncthreads();
-    for (int f = t; f < F; f += 256) cnt[base + (uint64_t)f * P] = s_f[f];
+    // Counts of one work-group are contiguous ([cell][part][fine] layout):
+    // whole cache lines, not one word per line.  The offset scan reads them
+    // in bucket order [cell][fine][part].
+    const uint64_t cbase = ((uint64_t)cw * P + part) * F;
+    for (int f = t; f < F; f += 256) cnt[cbase + f] = s_f[f];
     if (t == 0 && s_pairs > 0xFFFFFFFFull) atomicOr((unsigned long long *)&scal[S_OVF], 1ull);
 }
 
@@ -324,8 +340,15 @@ __device__ uint32_t block_excl_scan_rt(T *a, int n, uint32_t *wv) {
 // (outer element, inner element) and its fine bucket are staged, 8 bytes per
 // pair: the record itself is rebuilt from the quarter lists at write-out,
 // which costs two cached loads instead of a 16-24 byte LDS round trip.
-constexpr int kStageBatch = 3072;          // pairs per LDS batch
+constexpr int kStageBatch = 3072;          // pairs per LDS batch (index staging, per 256 threads)
 
+// Records of at most one row word (a fingerprint, one packed word, or none)
+// are built whole while the pairs are enumerated and staged in LDS as they
+// will be stored (8-byte header + 4-byte word, plus the fine bucket and the
+// permutation slot: 16 bytes per pair, batches of 8 pairs per thread); the
+// write-out then reads only LDS.  Wider records stage the pair's (outer,
+// inner) indices (10 bytes, batches of 12 per thread) and rebuild the record
+// from the quarter lists at write-out.
 template <int W, int PER, int MAXF, int NT>
 __global__ __launch_bounds__(NT) void k_scatter_staged(Plan p, const QRec<W> *__restrict__ A,
                                                         const QRec<W> *__restrict__ B,
@@ -336,15 +359,19 @@ __global__ __launch_bounds__(NT) void k_scatter_staged(Plan p, const QRec<W> *__
                                                         const uint32_t *__restrict__ offL,
                                                         const uint32_t *__restrict__ offR,
                                                         Rec<W> *recL, Rec<W> *recR, int64_t idx0) {
-    constexpr int BATCH = kStageBatch * (NT / 256);
+    constexpr bool SR = W <= 1;                  // whole records staged
+    constexpr int BATCH = SR ? 8 * NT : kStageBatch * (NT / 256);
     constexpr int NW = NT / 64;
     constexpr int per = PER;                     // outer elements per thread per chunk
     constexpr int WV = W > 0 ? W : 1;
     static_assert(NT * PER <= 65536, "chunk-relative outer index must fit 16 bits");
+    static_assert(BATCH <= 65536, "batch slots must fit 16 bits");
     __shared__ uint32_t s_cur[MAXF];
     __shared__ uint32_t s_cnt[MAXF];
-    __shared__ uint32_t s_q[BATCH];              // inner element of the pair
-    __shared__ uint16_t s_io[BATCH];             // outer element, relative to the chunk
+    __shared__ uint32_t s_q[SR ? 1 : BATCH];     // inner element of the pair
+    __shared__ uint16_t s_io[SR ? 1 : BATCH];    // outer element, relative to the chunk
+    __shared__ uint64_t s_hdr[SR ? BATCH : 1];   // the record's header ...
+    __shared__ uint32_t s_wd[SR ? BATCH : 1];    // ... and its row word
     __shared__ uint16_t s_f[BATCH];              // fine bucket, 0xFFFF = filtered out
     __shared__ uint16_t s_perm[BATCH];
     __shared__ uint32_t s_w4[NW];
@@ -364,10 +391,17 @@ __global__ __launch_bounds__(NT) void k_scatter_staged(Plan p, const QRec<W> *__
     const uint64_t Qo = side ? p.Q[2] : p.Q[0];
     const uint32_t *offs = side ? offR : offL;
     Rec<W> *rec = side ? recR : recL;
-    const uint64_t base = ((uint64_t)cw * F) * P + part;
-    for (int f = t; f < F; f += NT) s_cur[f] = offs[base + (uint64_t)f * P];
+    // Bucket offsets of this work-group, from the part-major copy the scan
+    // writes ([cell][part][fine]: one contiguous run).
+    const uint64_t tbase = ((uint64_t)cw * P + part) * F;
+    for (int f = t; f < F; f += NT) s_cur[f] = offs[tbase + f];
     const uint64_t lo = Qo * part / P, hi = Qo * (part + 1) / P;
     const int64_t smod1 = p.slice_mod - 1;
+    // The row word of a staged record from the two quarters' words.
+    auto word = [&](uint32_t a, uint32_t b) -> uint32_t {
+        if (p.fp) return side ? p.hd - a - b : a + b;
+        return side ? resid_word(p.dpk[0], a, b) : a + b;
+    };
     for (uint64_t c0 = lo; c0 < hi; c0 += (uint64_t)NT * per) {
         // This thread's outer elements (per of them, NT apart so that a wave
         // reads consecutive records) and the chunk-relative offsets of their
@@ -376,12 +410,14 @@ __global__ __launch_bounds__(NT) void k_scatter_staged(Plan p, const QRec<W> *__
         // and ignores it), so the keys, then the cell ranges, of all its
         // elements are in flight together.
         int64_t akey[PER];
+        uint32_t aw[PER];
         uint32_t b0[PER], nn[PER], c1[PER];
         uint32_t mysum = 0;
 #pragma unroll
         for (int e = 0; e < per; ++e) {
             const uint64_t i = c0 + (uint64_t)e * NT + t;
             akey[e] = outer[i < hi ? i : lo].key;
+            if (SR) aw[e] = outer[i < hi ? i : lo].vec[0];
         }
 #pragma unroll
         for (int e = 0; e < per; ++e) {
@@ -414,13 +450,20 @@ __global__ __launch_bounds__(NT) void k_scatter_staged(Plan p, const QRec<W> *__
                 const uint32_t n = nn[e];
                 const uint32_t qa = off >= P0 ? 0u : min(n, P0 - off);
                 const uint32_t qb = (off + n <= P0 + nb) ? n : (P0 + nb > off ? P0 + nb - off : 0u);
-                // Keys of up to 8 inner elements are loaded together, then used.
+                const uint64_t ai = c0 + (uint64_t)e * NT + t;
+                // Keys (and words) of up to 8 inner elements are loaded
+                // together, then used.
                 constexpr int kU = 8;
                 for (uint32_t q0 = qa; q0 < qb; q0 += kU) {
                     int64_t bk[kU];
+                    uint32_t bw[kU];
 #pragma unroll
-                    for (int u = 0; u < kU; ++u)
-                        if (q0 + u < qb) bk[u] = inner[b0[e] + q0 + u].key;
+                    for (int u = 0; u < kU; ++u) {
+                        if (q0 + u < qb) {
+                            bk[u] = inner[b0[e] + q0 + u].key;
+                            if (SR) bw[u] = inner[b0[e] + q0 + u].vec[0];
+                        }
+                    }
 #pragma unroll
                     for (int u = 0; u < kU; ++u) {
                         if (q0 + u >= qb) break;
@@ -428,8 +471,14 @@ __global__ __launch_bounds__(NT) void k_scatter_staged(Plan p, const QRec<W> *__
                         bool keep = side ? key >= 0 : key <= p.Kd;
                         if (p.slice_mod) keep = keep && ((key & smod1) == p.slice_res);
                         const uint32_t o = off + q0 + u - P0;
-                        s_q[o] = b0[e] + q0 + u;
-                        s_io[o] = (uint16_t)(e * NT + t);
+                        if (SR) {
+                            const uint64_t q = b0[e] + q0 + u;
+                            s_hdr[o] = ai | (q << p.qa) | ((uint64_t)(key >> p.log2M) << p.hsh);
+                            s_wd[o] = word(aw[e], bw[u]);
+                        } else {
+                            s_q[o] = b0[e] + q0 + u;
+                            s_io[o] = (uint16_t)(e * NT + t);
+                        }
                         s_f[o] = keep ? (uint16_t)((key & M1) >> p.log2T) : (uint16_t)0xFFFF;
                     }
                 }
@@ -450,22 +499,27 @@ __global__ __launch_bounds__(NT) void k_scatter_staged(Plan p, const QRec<W> *__
                 const uint32_t slot = s_perm[o];
                 const uint32_t f = s_f[slot];
                 const uint32_t start = f ? s_cnt[f - 1] : 0u;
-                const uint32_t q = s_q[slot];
-                const uint64_t ai = c0 + s_io[slot];
-                // Key and rows only (adjacent in QRec): the mask is not needed.
-                const int64_t ak = outer[ai].key, bk = inner[q].key;
-                uint32_t av[WV], bv[WV];
-#pragma unroll
-                for (int w = 0; w < WV; ++w) {
-                    av[w] = outer[ai].vec[w];
-                    bv[w] = inner[q].vec[w];
-                }
-                const int64_t key = side ? ak - bk : ak + bk;
                 Rec<W> r;
-                r.hdr = ai | ((uint64_t)q << p.qa) | ((uint64_t)(key >> p.log2M) << p.hsh);
+                if (SR) {
+                    r.hdr = s_hdr[slot];
+                    r.vec[0] = s_wd[slot];
+                } else {
+                    const uint32_t q = s_q[slot];
+                    const uint64_t ai = c0 + s_io[slot];
+                    // Key and rows only (adjacent in QRec): the mask is not needed.
+                    const int64_t ak = outer[ai].key, bk = inner[q].key;
+                    uint32_t av[WV], bv[WV];
 #pragma unroll
-                for (int w = 0; w < WV; ++w)
-                    r.vec[w] = side ? resid_word(p.dpk[w], av[w], bv[w]) : av[w] + bv[w];
+                    for (int w = 0; w < WV; ++w) {
+                        av[w] = outer[ai].vec[w];
+                        bv[w] = inner[q].vec[w];
+                    }
+                    const int64_t key = side ? ak - bk : ak + bk;
+                    r.hdr = ai | ((uint64_t)q << p.qa) | ((uint64_t)(key >> p.log2M) << p.hsh);
+#pragma unroll
+                    for (int w = 0; w < WV; ++w)
+                        r.vec[w] = side ? resid_word(p.dpk[w], av[w], bv[w]) : av[w] + bv[w];
+                }
                 rec[s_cur[f] + (o - start)] = r;
             }
             __syncthreads();
@@ -533,6 +587,33 @@ __device__ __forceinline__ bool rows_match(const Rec<W> &l, const Rec<W> &r) {
 #pragma unroll
     for (int w = 0; w < W; ++w) ok = ok && (l.vec[w] == r.vec[w]);
     return ok;
+}
+
+// Exact check of the non-key rows of a candidate pair from the quarter lists.
+// Half records either carry the packed rows themselves (then equality of the
+// stored words already is the exact check) or, with p.fp, one 32-bit
+// fingerprint of them; a fingerprint match is only a candidate, decided here
+// by the packed rows of the four quarter subsets the headers point to.
+__device__ __forceinline__ bool exact_rows(const Plan &p, uint64_t hl, uint64_t hr) {
+    if (!p.fp) return true;
+    const uint64_t mo = (1ull << p.qa) - 1, mi = (1ull << p.qb) - 1;
+    const size_t oL = hl & mo, iL = (hl >> p.qa) & mi, oR = hr & mo, iR = (hr >> p.qa) & mi;
+    const int W = p.W;
+    bool ok = true;
+    for (int w = 0; w < W; ++w) {
+        const uint32_t l = p.qv[0][oL * W + w] + p.qv[1][iL * W + w];
+        const uint32_t r = resid_word(p.dpk[w], p.qv[2][oR * W + w], p.qv[3][iR * W + w]);
+        ok = ok && (l == r);
+    }
+    return ok;
+}
+
+// A pair whose stored words match: a solution once its rows hold exactly.
+template <int W>
+__device__ __forceinline__ void emit_pair(const Plan &p, const QPtrs<W> &qs, uint64_t *sol,
+                                          uint64_t cap, uint64_t *ctr, uint64_t hl, uint64_t hr) {
+    if (!exact_rows(p, hl, hr)) return;
+    emit_solution(sol, cap, ctr, half_mask(p, qs, 0, hl), half_mask(p, qs, 1, hr));
 }
 
 // ---------------------------------------------------------------------------
@@ -615,8 +696,7 @@ __global__ __launch_bounds__(256) void k_vjoin_probe(Plan p, const RunPair *__re
 #pragma unroll
                 for (int w = 0; w < WV; ++w) ok = ok && (L[e].vec[w] == v[w]);
                 if (ok)
-                    emit_solution(sol, cap, &scal[S_NSOL], half_mask(p, qs, 0, L[e].hdr),
-                                  half_mask(p, qs, 1, R[rj].hdr));
+                    emit_pair(p, qs, sol, cap, &scal[S_NSOL], L[e].hdr, R[rj].hdr);
             }
         }
     }
@@ -746,9 +826,7 @@ __global__ __launch_bounds__(256) void k_join_light(Plan p, const uint32_t *__re
 #pragma unroll
                         for (int w = 0; w < WV; ++w) ok = ok && (s_vec[w][i] == v[w]);
                         if (ok)
-                            emit_solution(sol, cap, &scal[S_NSOL],
-                                          half_mask(p, qs, 0, L[l0 + i].hdr),
-                                          half_mask(p, qs, 1, R[r0 + rj].hdr));
+                            emit_pair(p, qs, sol, cap, &scal[S_NSOL], L[l0 + i].hdr, R[r0 + rj].hdr);
                     }
                 };
                 auto probe = [&](const int64_t key, const uint32_t *v, uint32_t rj) {
@@ -842,9 +920,7 @@ __global__ __launch_bounds__(256) void k_join_pairs(Plan p, const uint32_t *__re
 #pragma unroll
                             for (int w = 0; w < WV; ++w) ok = ok && (L[li].vec[w] == R[rj].vec[w]);
                             if (ok)
-                                emit_solution(sol, cap, &scal[S_NSOL],
-                                              half_mask(p, qs, 0, L[li].hdr),
-                                              half_mask(p, qs, 1, rh));
+                                emit_pair(p, qs, sol, cap, &scal[S_NSOL], L[li].hdr, rh);
                         }
                     }
                 }
@@ -997,8 +1073,7 @@ __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__
 #pragma unroll
                 for (int w = 0; w < WV; ++w) ok = ok && (s_vec[w][li] == v[w]);
                 if (ok)
-                    emit_solution(sol, cap, &scal[S_NSOL], half_mask(p, qs, 0, L[l0 + li].hdr),
-                                  half_mask(p, qs, 1, R[r0 + rj].hdr));
+                    emit_pair(p, qs, sol, cap, &scal[S_NSOL], L[l0 + li].hdr, R[r0 + rj].hdr);
             }
         };
 #pragma unroll
@@ -1118,8 +1193,7 @@ __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__
 #pragma unroll
                 for (int w = 1; w < WV; ++w) ok = ok && (s_vec[w][q] == v[w]);
                 if (ok)
-                    emit_solution(sol, cap, &scal[S_NSOL], half_mask(p, qs, 0, L[l0 + s_grp[q]].hdr),
-                                  half_mask(p, qs, 1, R[r0 + rj].hdr));
+                    emit_pair(p, qs, sol, cap, &scal[S_NSOL], L[l0 + s_grp[q]].hdr, R[r0 + rj].hdr);
             }
         }
     };
@@ -1256,8 +1330,7 @@ __global__ __launch_bounds__(256) void k_join_heavy_vj(Plan p, const uint32_t *_
 #pragma unroll
                     for (int w = 0; w < WV; ++w) ok = ok && (s_vec[w][li] == v[w]);
                     if (ok)
-                        emit_solution(sol, cap, &scal[S_NSOL], half_mask(p, qs, 0, L[l0 + li].hdr),
-                                      half_mask(p, qs, 1, rhdr));
+                        emit_pair(p, qs, sol, cap, &scal[S_NSOL], L[l0 + li].hdr, rhdr);
                 }
             }
             }   // right steps
@@ -1488,8 +1561,7 @@ __global__ __launch_bounds__(256) void k_join_heavy(Plan p, const uint32_t *__re
 #pragma unroll
                 for (int w = 0; w < WV; ++w) ok = ok && (s_vec[w][li] == v[w]);
                 if (ok)
-                    emit_solution(sol, cap, &scal[S_NSOL], half_mask(p, qs, 0, L[l0 + li].hdr),
-                                  half_mask(p, qs, 1, R[r0 + j].hdr));
+                    emit_pair(p, qs, sol, cap, &scal[S_NSOL], L[l0 + li].hdr, R[r0 + j].hdr);
             }
         }
     }
@@ -1617,7 +1689,7 @@ __global__ __launch_bounds__(256) void k_verify(Plan p, const Rec<W> *__restrict
         const Rec<W> ll = lrec(li);
         const Rec<W> rr = rrec(ri);
         if (rows_match<W>(ll, rr))
-            emit_solution(sol, cap, &scal[S_NSOL], half_mask(p, qs, 0, ll.hdr), half_mask(p, qs, 1, rr.hdr));
+            emit_pair(p, qs, sol, cap, &scal[S_NSOL], ll.hdr, rr.hdr);
     };
     uint64_t hits = 0;
     for (uint32_t c0 = lb; c0 < le; c0 += kChunk) {
@@ -1764,6 +1836,71 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *__restrict__
     }
 }
 
+// Bucket-order scan of part-major counts.  Element i of the scan order
+// [cell][fine][part] sits at ((cell * P + part) * F + fine) of the input; the
+// offsets are written in scan order (bucket ranges for the joins) and again
+// part-major (each count/scatter work-group's F offsets contiguous).
+struct CountMap {
+    uint32_t F, P;
+    __device__ __forceinline__ size_t src(size_t i) const {
+        const size_t fp = (size_t)F * P;
+        const size_t c = i / fp, rem = i - c * fp;
+        const size_t f = rem / P, p = rem - f * P;
+        return (c * P + p) * F + f;
+    }
+};
+
+__global__ __launch_bounds__(256) void k_scan_reduce_map(const uint32_t *__restrict__ in, size_t n,
+                                                         CountMap mp, uint32_t *sums,
+                                                         uint64_t *total64) {
+    __shared__ uint64_t s4[4];
+    const size_t base = (size_t)blockIdx.x * kScanBlock;
+    uint64_t s = 0;
+    for (int e = 0; e < kScanE; ++e) {
+        const size_t i = base + (size_t)e * 256 + threadIdx.x;
+        if (i < n) s += in[mp.src(i)];
+    }
+    s = block_sum_u64(s, s4);
+    if (threadIdx.x == 0) {
+        sums[blockIdx.x] = (uint32_t)s;
+        if (total64) atomicAdd((unsigned long long *)total64, (unsigned long long)s);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply_map(const uint32_t *__restrict__ in,
+                                                        uint32_t *out, uint32_t *out_t, size_t n,
+                                                        CountMap mp,
+                                                        const uint32_t *__restrict__ pref,
+                                                        uint64_t *total64) {
+    __shared__ uint32_t s_a[kScanBlock];
+    __shared__ uint32_t s_w4[4];
+    __shared__ uint64_t s_t4[4];
+    const size_t base = (size_t)blockIdx.x * kScanBlock;
+    uint64_t s64 = 0;
+    for (int e = 0; e < kScanE; ++e) {
+        const size_t i = base + (size_t)e * 256 + threadIdx.x;
+        const uint32_t v = i < n ? in[mp.src(i)] : 0u;
+        s_a[e * 256 + threadIdx.x] = v;
+        s64 += v;
+    }
+    __syncthreads();
+    if (total64) s64 = block_sum_u64(s64, s_t4);
+    const uint32_t tot = block_excl_scan_lds<kScanE>(s_a, s_w4);
+    const uint32_t add = pref ? pref[blockIdx.x] : 0u;
+    for (int e = 0; e < kScanE; ++e) {
+        const size_t i = base + (size_t)e * 256 + threadIdx.x;
+        if (i < n) {
+            const uint32_t o = s_a[e * 256 + threadIdx.x] + add;
+            out[i] = o;
+            out_t[mp.src(i)] = o;
+        }
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+        out[n] = add + tot;
+        if (total64) *total64 = s64;
+    }
+}
+
 size_t scan_tmp_bytes(size_t n) {
     size_t bytes = 0;
     while (n > (size_t)kScanBlock) {
@@ -1799,6 +1936,34 @@ hipError_t scan_u32(const uint32_t *in, uint32_t *out, size_t n, uint64_t *total
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_scan_apply, dim3((uint32_t)nb), dim3(256), 0, st, in, out, n, pref,
                        nullptr, 1);
+    return hipGetLastError();
+}
+
+hipError_t scan_counts(const uint32_t *in, uint32_t *out, uint32_t *out_t, size_t n, uint32_t F,
+                       uint32_t P, uint64_t *total64, void *tmp, size_t tmp_bytes, hipStream_t st) {
+    if (n == 0) return scan_u32(in, out, 0, total64, tmp, tmp_bytes, st);
+    const CountMap mp{F, P};
+    const size_t nb = (n + kScanBlock - 1) / kScanBlock;
+    if ((uint64_t)nb * 256 > kMaxGridItems) return hipErrorInvalidConfiguration;
+    if (nb == 1) {
+        hipLaunchKernelGGL(k_scan_apply_map, dim3(1), dim3(256), 0, st, in, out, out_t, n, mp,
+                           nullptr, total64);
+        return hipGetLastError();
+    }
+    const size_t need = (nb + 1) * sizeof(uint32_t) * 2 + 256;
+    if (tmp_bytes < need) return hipErrorInvalidValue;
+    uint32_t *sums = (uint32_t *)tmp;
+    uint32_t *pref = sums + nb + 1;
+    if (total64) {
+        hipError_t e0 = hipMemsetAsync(total64, 0, sizeof(uint64_t), st);
+        if (e0 != hipSuccess) return e0;
+    }
+    hipLaunchKernelGGL(k_scan_reduce_map, dim3((uint32_t)nb), dim3(256), 0, st, in, n, mp, sums,
+                       total64);
+    hipError_t e = scan_u32(sums, pref, nb, nullptr, (char *)tmp + need, tmp_bytes - need, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scan_apply_map, dim3((uint32_t)nb), dim3(256), 0, st, in, out, out_t, n,
+                       mp, pref, nullptr);
     return hipGetLastError();
 }
 
@@ -1859,7 +2024,13 @@ static hipError_t quarters_impl(const Plan &p, const DevBufs &b, hipStream_t st)
         cnt.q[x] = b.qcnt[x];
         cur.q[x] = b.qcur[x];
     }
-    hipLaunchKernelGGL(k_quarter_gen<W>, dim3(grid), dim3(256), 0, st, p, b.colw, b.rows, raw, cnt);
+    UPtrs vraw, vsrt;
+    for (int x = 0; x < 4; ++x) {
+        vraw.q[x] = b.qvraw[x];
+        vsrt.q[x] = b.qvsrt[x];
+    }
+    hipLaunchKernelGGL(k_quarter_gen<W>, dim3(grid), dim3(256), 0, st, p, b.colw, b.rows, raw, cnt,
+                       vraw);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t T = (size_t)1 << p.log2T;
@@ -1869,12 +2040,13 @@ static hipError_t quarters_impl(const Plan &p, const DevBufs &b, hipStream_t st)
         e = hipMemcpyAsync(b.qcur[x], b.qcnt[x], T * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_quarter_sort<W>, dim3(grid), dim3(256), 0, st, p, raw, srt, cur);
+    hipLaunchKernelGGL(k_quarter_sort<W>, dim3(grid), dim3(256), 0, st, p, raw, srt, cur, vraw,
+                       vsrt);
     return hipGetLastError();
 }
 
 hipError_t launch_quarters(const Plan &p, const DevBufs &b, int, hipStream_t st) {
-    MSP_DISPATCH_W(p.W, return quarters_impl<WW>(p, b, st));
+    MSP_DISPATCH_W(p.Wr, return quarters_impl<WW>(p, b, st));
     return hipSuccess;
 }
 
@@ -1898,7 +2070,7 @@ static hipError_t count_impl(const Plan &p, const DevBufs &b, int64_t idx0, int3
 }
 
 hipError_t launch_count(const Plan &p, const DevBufs &b, int64_t idx0, int32_t K, hipStream_t st) {
-    MSP_DISPATCH_W(p.W, return count_impl<WW>(p, b, idx0, K, st));
+    MSP_DISPATCH_W(p.Wr, return count_impl<WW>(p, b, idx0, K, st));
     return hipSuccess;
 }
 
@@ -1910,7 +2082,8 @@ static hipError_t staged_impl(const Plan &p, const DevBufs &b, int64_t idx0, int
     const uint64_t T = (uint64_t)1 << p.log2T;
     const uint64_t qin = std::min((uint64_t)p.Q[1], (uint64_t)p.Q[3]);
     int per = 1;
-    while (per < 16 && (uint64_t)256 * (2 * per) * qin <= (uint64_t)kStageBatch * T) per *= 2;
+    const uint64_t batch256 = W <= 1 ? 8 * 256 : kStageBatch;   // batch per 256 threads
+    while (per < 16 && (uint64_t)256 * (2 * per) * qin <= batch256 * T) per *= 2;
     // LDS for the per-bucket cursors is sized to F: more work-groups per CU.
     const int F = 1 << p.log2F;
     if ((uint64_t)K * p.parts > 0xFFFFFFFFull) return hipErrorInvalidConfiguration;
@@ -1925,7 +2098,7 @@ static hipError_t staged_impl(const Plan &p, const DevBufs &b, int64_t idx0, int
                        st, p,                                                                   \
                        (const QRec<W> *)b.qsrt[0], (const QRec<W> *)b.qsrt[1], b.qcnt[1],       \
                        (const QRec<W> *)b.qsrt[2], (const QRec<W> *)b.qsrt[3], b.qcnt[3],       \
-                       b.off[0], b.off[1], (Rec<W> *)b.rec[0], (Rec<W> *)b.rec[1], idx0)
+                       b.offt[0], b.offt[1], (Rec<W> *)b.rec[0], (Rec<W> *)b.rec[1], idx0)
 #define MSP_STAGED_PER(MF)                                                                      \
     switch (per) {                                                                              \
         case 1: MSP_STAGED(1, MF); break;                                                       \
@@ -1949,7 +2122,7 @@ static hipError_t staged_impl(const Plan &p, const DevBufs &b, int64_t idx0, int
 
 hipError_t launch_scatter(const Plan &p, const DevBufs &b, int64_t idx0, int32_t K,
                           hipStream_t st) {
-    MSP_DISPATCH_W(p.W, return staged_impl<WW>(p, b, idx0, K, st));
+    MSP_DISPATCH_W(p.Wr, return staged_impl<WW>(p, b, idx0, K, st));
     return hipSuccess;
 }
 
@@ -2017,7 +2190,7 @@ static hipError_t join_impl(const Plan &p, const DevBufs &b, int32_t K, uint64_t
 
 hipError_t launch_hash_join(const Plan &p, const DevBufs &b, int32_t K, uint64_t cap,
                             hipStream_t st) {
-    MSP_DISPATCH_W(p.W, return join_impl<WW>(p, b, K, cap, st));
+    MSP_DISPATCH_W(p.Wr, return join_impl<WW>(p, b, K, cap, st));
     return hipSuccess;
 }
 
@@ -2044,7 +2217,7 @@ static hipError_t vjoin_impl(const Plan &p, const DevBufs &b, uint32_t nruns, ui
 hipError_t launch_vector_join(const Plan &p, const DevBufs &b, uint32_t nruns, uint64_t cap,
                               hipStream_t st) {
     if (nruns == 0) return hipSuccess;
-    MSP_DISPATCH_W(p.W, return vjoin_impl<WW>(p, b, nruns, cap, st));
+    MSP_DISPATCH_W(p.Wr, return vjoin_impl<WW>(p, b, nruns, cap, st));
     return hipSuccess;
 }
 
@@ -2092,7 +2265,7 @@ static hipError_t verify_impl(const Plan &p, const DevBufs &b, uint32_t nruns, u
 hipError_t launch_verify(const Plan &p, const DevBufs &b, uint32_t nruns, uint32_t ntiles,
                          uint64_t cap, int mode, hipStream_t st) {
     if (ntiles == 0) return hipSuccess;
-    MSP_DISPATCH_W(p.W, return verify_impl<WW>(p, b, nruns, ntiles, cap, mode, st));
+    MSP_DISPATCH_W(p.Wr, return verify_impl<WW>(p, b, nruns, ntiles, cap, mode, st));
     return hipSuccess;
 }
 

@@ -38,7 +38,8 @@ class msp_opts(C.Structure):
                 ("max_solutions", C.c_uint64), ("window_records", C.c_uint64),
                 ("workspace", C.c_void_p), ("workspace_bytes", C.c_uint64),
                 ("stream", C.c_void_p), ("first_only", C.c_int32), ("join_variant", C.c_int32),
-                ("verify_join", C.c_int32), ("key_base", C.c_int32)]
+                ("verify_join", C.c_int32), ("key_base", C.c_int32),
+                ("row_fingerprint", C.c_int32), ("reserved0", C.c_int32)]
 
 
 class msp_stats_t(C.Structure):
@@ -51,7 +52,8 @@ class msp_stats_t(C.Structure):
                 ("parts", C.c_int32), ("key_rows", C.c_int32), ("exact_buckets", C.c_int32),
                 ("words", C.c_int32), ("complete", C.c_int32), ("vector_join", C.c_int32),
                 ("windows_total", C.c_uint64), ("join_grouped", C.c_int32),
-                ("key_base", C.c_int32), ("reserved", C.c_int32), ("cells_done", C.c_uint64)]
+                ("key_base", C.c_int32), ("row_fingerprint", C.c_int32),
+                ("cells_done", C.c_uint64)]
 
 
 class msp_batch_opts(C.Structure):
@@ -62,7 +64,7 @@ class msp_plan_t(C.Structure):
     _fields_ = [("key_rows", C.c_int32), ("log2_m", C.c_int32), ("log2_cells", C.c_int32),
                 ("log2_fine", C.c_int32), ("parts", C.c_int32), ("exact_buckets", C.c_int32),
                 ("words", C.c_int32), ("join_variant", C.c_int32), ("vector_join", C.c_int32),
-                ("key_base", C.c_int32), ("infeasible", C.c_int32), ("reserved", C.c_int32),
+                ("key_base", C.c_int32), ("infeasible", C.c_int32), ("row_fingerprint", C.c_int32),
                 ("cells", C.c_uint64), ("cells_per_window", C.c_uint64), ("windows", C.c_uint64),
                 ("window_records", C.c_uint64), ("record_bytes", C.c_uint64),
                 ("workspace_bytes", C.c_uint64), ("max_grid_items", C.c_uint64)]

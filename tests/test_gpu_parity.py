@@ -66,17 +66,26 @@ def test_small_random_vs_brute_force(case):
              f"pairwise {case} {seed}")
         same(gsolve(inst.A, inst.d, key_rows=case["r"], verify_join=1), ref,
              f"vector join {case} {seed}")
+        # half records with the packed rows themselves, and with a fingerprint
+        # even when the rows take one word
+        for rf in (1, 2):
+            for vj in (1, 2):
+                same(gsolve(inst.A, inst.d, key_rows=case["r"], verify_join=vj,
+                            row_fingerprint=rf), ref,
+                     f"row_fingerprint={rf} verify_join={vj} {case} {seed}")
         # force hash buckets (modulus below K_d) and a few cell layouts
         # parts 8 and 16 take the XCD-aware work-group mapping
         for lm, lc, parts, jv in [(3, 1, 1, 1), (5, 2, 3, 2), (6, 6, 2, 0), (6, 3, 2, 2),
                                   (5, 2, 8, 1), (6, 3, 16, 2), (3, 1, 2, 3), (8, 3, 8, 3)]:
-            g = gsolve(inst.A, inst.d, key_rows=case["r"], log2_m=lm, log2_cells=lc, parts=parts,
-                       join_variant=jv, verify_join=2)
-            same(g, ref, f"M=2^{lm} T=2^{lc} P={parts} join={jv} {case} {seed}")
+            for rf in (0, 2):
+                g = gsolve(inst.A, inst.d, key_rows=case["r"], log2_m=lm, log2_cells=lc,
+                           parts=parts, join_variant=jv, verify_join=2, row_fingerprint=rf)
+                same(g, ref, f"M=2^{lm} T=2^{lc} P={parts} join={jv} rows={rf} {case} {seed}")
             # hash buckets decided by the vector join inside the grouped kernel
-            g = gsolve(inst.A, inst.d, key_rows=case["r"], log2_m=lm, log2_cells=lc, parts=parts,
-                       verify_join=1)
-            same(g, ref, f"M=2^{lm} T=2^{lc} P={parts} vector join {case} {seed}")
+            for rf in (0, 2):
+                g = gsolve(inst.A, inst.d, key_rows=case["r"], log2_m=lm, log2_cells=lc,
+                           parts=parts, verify_join=1, row_fingerprint=rf)
+                same(g, ref, f"M=2^{lm} T=2^{lc} P={parts} vector join rows={rf} {case} {seed}")
 
 
 WIDE = [
@@ -242,10 +251,12 @@ def test_full_configs_vs_oracle(cfg):
         say("config", e["name"])
         kb = e.get("key_base", 0)
         for vj, what in ((0, "planner's choice"), (1, "vector join"), (2, "pairwise")):
-            g = gsolve(inst.A, inst.d, key_rows=e["key_rows"], key_base=kb, verify_join=vj)
-            same(g, _golden_result(e, n), f"{e['name']} {what}")
-            if inst.planted is not None:
-                assert any(np.array_equal(s, inst.planted) for s in g.solutions)
+            for rf in (0, 2):
+                g = gsolve(inst.A, inst.d, key_rows=e["key_rows"], key_base=kb, verify_join=vj,
+                           row_fingerprint=rf)
+                same(g, _golden_result(e, n), f"{e['name']} {what} rows={rf}")
+                if inst.planted is not None:
+                    assert any(np.array_equal(s, inst.planted) for s in g.solutions)
         if e["key_rows"] >= 4:
             # ~256 records per bucket and side: the wavefront-per-bucket join
             # in several 64-record chunks, and the heavy join past 256.
@@ -267,9 +278,10 @@ def test_large_configs_sampled_residue_classes(cfg):
         inst = _golden_instance(e)
         r, kb = e["key_rows"], e.get("key_base", 0)
         say("sampled", e["name"], "r", r, "key_base", kb, e["slice_mod"], e["slice_res"])
-        for vj, what in ((0, "planner's choice"), (1, "vector join"), (2, "pairwise")):
+        for vj, rf, what in ((0, 0, "planner's choice"), (1, 0, "vector join"),
+                             (2, 0, "pairwise"), (2, 2, "pairwise, packed rows")):
             g = gsolve(inst.A, inst.d, key_rows=r, key_base=kb, slice_mod=e["slice_mod"],
-                       slice_res=e["slice_res"], verify_join=vj)
+                       slice_res=e["slice_res"], verify_join=vj, row_fingerprint=rf)
             same(g, _golden_result(e, n), f"{e['name']} rho={e['slice_res']} {what}")
             if inst.planted is not None:
                 assert any(np.array_equal(s, inst.planted) for s in g.solutions)
@@ -316,7 +328,8 @@ def test_multi_cell_slice_shipped_plan():
         assert plan, "no shipped plan for (8,70)"
         kw = dict(key_rows=4, slice_mod=256, slice_res=e["slice_res"], **plan)
         for extra in (dict(), dict(window_records=1 << 24), dict(verify_join=2),
-                      dict(verify_join=2, window_records=1 << 24)):
+                      dict(verify_join=2, window_records=1 << 24),
+                      dict(verify_join=2, row_fingerprint=2)):
             ctx = msp.Context(inst.A, inst.d)
             ctx.solve(**kw, **extra)
             st = ctx.stats()
