@@ -167,6 +167,21 @@ void msp_default_opts(msp_opts *o);
  * opts may be NULL (defaults). */
 int  msp_solve(msp_ctx *ctx, const msp_opts *opts);
 
+/* msp_solve for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same solve and the same kernels, but the workspace is a fixed device array
+ * inside the library (MSP_NOALLOC_SCRATCH_BYTES = 128 MiB per GPU, held by
+ * every GPU the library runs on until the process ends), and the call makes
+ * no hipMalloc, hipFree, pinned-host or event allocation and creates no
+ * stream.  opts->workspace must be NULL (workspace_bytes 0 or the scratch
+ * size); opts->stream NULL runs on the null stream.  A plan that does not fit
+ * the scratch array fails with MSP_E_NOMEM.  Phase times in msp_stats are 0.
+ * Results are read as after msp_solve (they are kept in the context's host
+ * memory).  Every call on one GPU shares that GPU's scratch array: calls that
+ * overlap on the same GPU race and must be serialised by the caller. */
+#define MSP_NOALLOC_SCRATCH_BYTES (128ull << 20)
+int  msp_solve_noalloc(msp_ctx *ctx, const msp_opts *opts);
+
 /* Results of the last successful msp_solve. */
 int  msp_num_solutions(const msp_ctx *ctx, uint64_t *count);
 int  msp_hits(const msp_ctx *ctx, uint64_t *lo, uint64_t *hi);   /* 128-bit H */

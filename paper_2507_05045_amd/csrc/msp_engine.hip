@@ -35,6 +35,7 @@ struct msp_ctx {
     hipStream_t own_stream = nullptr;
     bool poisoned = false;
     std::atomic<int> busy{0};          // a solve or request is using this context
+    uint64_t hs_fixed[msp::S_COUNT] = {};   // scalar copies of msp_solve_noalloc
 };
 
 namespace {
@@ -1027,6 +1028,43 @@ static void server_loop(msp_server *sv) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// The no-allocation entry point's workspace: one file-scope device array per
+// GPU (every device that loads this library holds it until the process
+// ends).  Host code never passes the array's name to a kernel or a copy: it
+// is a host-side stand-in.  The device address comes from
+// hipGetSymbolAddress, once per device with that device current, and only
+// that address is used.
+// ---------------------------------------------------------------------------
+constexpr uint64_t kScratchBytes = MSP_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call on each device).
+static int scratch_address(void **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return MSP_E_NOLIB;
+    }
+    if (dev < 0 || dev >= kMaxDevices) return MSP_E_UNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return MSP_E_DEVICE;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return MSP_OK;
+}
+
 extern "C" {
 
 const char *msp_strerror(int code) {
@@ -1197,6 +1235,50 @@ int msp_solve(msp_ctx *c, const msp_opts *opts) {
         }
     }
     job_release_events(j);
+    if (rc == MSP_E_DEVICE) c->poisoned = true;
+    return rc;
+}
+
+int msp_solve_noalloc(msp_ctx *c, const msp_opts *opts) {
+    if (!c) return MSP_E_INVALID;
+    if (c->poisoned) return MSP_E_DEVICE;
+    msp_opts o;
+    msp_default_opts(&o);
+    if (opts) o = *opts;
+    if (o.workspace || (o.workspace_bytes && o.workspace_bytes != kScratchBytes))
+        return MSP_E_INVALID;            // the workspace is the library's scratch array
+    int expect = 0;
+    if (!c->busy.compare_exchange_strong(expect, 1)) return MSP_E_BUSY;
+    struct Unbusy { msp_ctx *c; ~Unbusy() { c->busy.store(0); } } unbusy{c};
+    Job j;
+    j.c = c;
+    j.o = o;
+    j.t_wall0 = now_s();
+    c->have_result = false;
+    void *ws = nullptr;
+    int rc = scratch_address(&ws);
+    if (rc) return rc;
+    // The plan must fit the scratch array: MSP_E_NOMEM otherwise.
+    rc = prepare(c, j.o, kScratchBytes, j.P);
+    if (rc) return rc;
+    job_init_stats(j);
+    if (j.P.infeasible) {
+        job_trivial(j);
+        return MSP_OK;
+    }
+    j.s = (hipStream_t)j.o.stream;       // NULL: the null stream (no stream is created)
+    j.ws = (char *)ws;
+    job_carve(j);
+    j.hs = c->hs_fixed;                  // no pinned buffer, no timing events
+    j.hs_pinned = false;
+    while (rc == MSP_OK && j.next != A_DONE) {
+        rc = job_step(j);
+        if (rc == MSP_OK && j.next != A_DONE && hipStreamSynchronize(j.s) != hipSuccess) {
+            (void)hipGetLastError();
+            rc = MSP_E_DEVICE;
+        }
+    }
+    j.hs = nullptr;
     if (rc == MSP_E_DEVICE) c->poisoned = true;
     return rc;
 }

@@ -79,7 +79,7 @@ EXPORTS = ["msp_create", "msp_default_opts", "msp_solve", "msp_num_solutions", "
            "msp_get_solutions", "msp_stats", "msp_destroy", "msp_strerror",
            "msp_workspace_bytes", "msp_batch_solve", "msp_server_start", "msp_server_submit",
            "msp_server_poll", "msp_server_wait", "msp_server_cancel", "msp_server_times",
-           "msp_server_stop", "msp_plan", "msp_set_allocator"]
+           "msp_server_stop", "msp_plan", "msp_set_allocator", "msp_solve_noalloc"]
 
 # PyTorch-ROCm ships its own HIP runtime with the same soname as the system
 # one.  Load torch first so that libmsp binds to the runtime torch uses:
@@ -130,6 +130,8 @@ lib.msp_server_times.argtypes = [C.c_void_p, C.c_uint64, _p(C.c_double)]
 lib.msp_server_times.restype = C.c_int
 lib.msp_server_stop.argtypes = [C.c_void_p]
 lib.msp_server_stop.restype = C.c_int
+lib.msp_solve_noalloc.argtypes = [C.c_void_p, _p(msp_opts)]
+lib.msp_solve_noalloc.restype = C.c_int
 lib.msp_plan.argtypes = [C.c_void_p, _p(msp_opts), _p(msp_plan_t)]
 lib.msp_plan.restype = C.c_int
 lib.msp_set_allocator.argtypes = [ALLOC_FN, RELEASE_FN, C.c_void_p]
@@ -219,6 +221,13 @@ class Context:
         elif budget is not None:
             opts.workspace_bytes = budget
         _check(lib.msp_solve(self._ctx, C.byref(opts)), "msp_solve")
+        return self
+
+    def solve_noalloc(self, **kw) -> "Context":
+        """msp_solve_noalloc: the library's fixed scratch array as workspace;
+        no device allocation (stream: kw ``stream`` or the null stream)."""
+        opts = msp_default_opts(**kw)
+        _check(lib.msp_solve_noalloc(self._ctx, C.byref(opts)), "msp_solve_noalloc")
         return self
 
     def hits(self) -> int:
