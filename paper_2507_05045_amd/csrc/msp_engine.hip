@@ -101,7 +101,7 @@ struct Sizes {
     uint64_t total = 0;      // workspace bytes
     // offsets into the workspace
     uint64_t o_qraw[4], o_qsrt[4], o_qcnt[4], o_qcur[4], o_cnt[2], o_off[2], o_rec[2];
-    uint64_t o_qvraw[4], o_qvsrt[4], o_offt[2];
+    uint64_t o_qvraw[4], o_qvsrt[4], o_pre[2], o_tot[2];
     uint64_t o_runs, o_tiles, o_sol, o_scal, o_scan, scan_bytes, o_colw, o_rows;
     uint64_t o_iruns, o_itiles, o_idx, n_iruns, o_heavy, idx_n;
     uint64_t o_vtab, vtab_slots;
@@ -298,6 +298,14 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
     // probe per record) against the pairwise check (|G_L| |G_R| compares).
     // The planner takes the vector join when the expected equal-key group
     // holds 16 or more records per side (hundreds of pairs per run).
+    // Buckets of more than about a thousand records per side (a smaller
+    // modulus): the grouped join's 1024-thread variant, up to 4096 records.
+    {
+        const uint64_t per_bucket =
+            std::max((uint64_t)p.Q[0] * p.Q[1], (uint64_t)p.Q[2] * p.Q[3]) >> std::min(log2M, 62);
+        p.gbig = 0;
+        if (!p.exact && per_bucket > 1100) p.gbig = 1;
+    }
     if (o.verify_join < 0 || o.verify_join > 2) return MSP_E_INVALID;
     if (o.verify_join == 1) p.vjoin = 1;
     else if (o.verify_join == 2) p.vjoin = 0;
@@ -369,8 +377,9 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
         for (int x = 0; x < 4; ++x) z.o_qcur[x] = take((T + 1) * 4);
         const uint64_t ncnt = kw * F * (uint64_t)parts + 1;
         for (int s = 0; s < 2; ++s) z.o_cnt[s] = take(ncnt * 4);
-        for (int s = 0; s < 2; ++s) z.o_off[s] = take(ncnt * 4);
-        for (int s = 0; s < 2; ++s) z.o_offt[s] = take(ncnt * 4);
+        for (int s = 0; s < 2; ++s) z.o_off[s] = take((kw * F + 1) * 4);
+        for (int s = 0; s < 2; ++s) z.o_pre[s] = take(ncnt * 4);
+        for (int s = 0; s < 2; ++s) z.o_tot[s] = take((kw * F + 1) * 4);
         for (int s = 0; s < 2; ++s) z.o_rec[s] = take(cap_rec * rb);
         z.o_runs = take(kw * F * sizeof(RunPair));
         z.o_tiles = take((kw * F + 1) * 4);
@@ -565,7 +574,8 @@ void job_carve(Job &j) {
     for (int sd = 0; sd < 2; ++sd) {
         j.b.cnt[sd] = (uint32_t *)(ws + z.o_cnt[sd]);
         j.b.off[sd] = (uint32_t *)(ws + z.o_off[sd]);
-        j.b.offt[sd] = (uint32_t *)(ws + z.o_offt[sd]);
+        j.b.pre[sd] = (uint32_t *)(ws + z.o_pre[sd]);
+        j.b.tot[sd] = (uint32_t *)(ws + z.o_tot[sd]);
         j.b.rec[sd] = ws + z.o_rec[sd];
     }
     j.b.runs = (RunPair *)(ws + z.o_runs);
@@ -600,15 +610,15 @@ void job_carve(Job &j) {
 
 int enqueue_count(Job &j) {
     const Plan &p = j.P.p;
-    const size_t ncnt = (size_t)j.K * ((size_t)1 << p.log2F) * p.parts;
     JCHK(ev_rec(j, E_C0));
     JCHK(launch_count(p, j.b, (int64_t)j.idx, (int32_t)j.K, j.s));
     JCHK(ev_rec(j, E_C1));
     const uint32_t F = 1u << p.log2F, P = (uint32_t)p.parts;
-    JCHK(scan_counts(j.b.cnt[0], j.b.off[0], j.b.offt[0], ncnt, F, P, &j.b.scal[S_TOT_L],
-                     j.b.scan_tmp, j.b.scan_tmp_bytes, j.s));
-    JCHK(scan_counts(j.b.cnt[1], j.b.off[1], j.b.offt[1], ncnt, F, P, &j.b.scal[S_TOT_R],
-                     j.b.scan_tmp, j.b.scan_tmp_bytes, j.s));
+    const uint64_t nbk = (uint64_t)j.K << p.log2F;
+    for (int sd = 0; sd < 2; ++sd)
+        JCHK(scan_counts(j.b.cnt[sd], j.b.pre[sd], j.b.tot[sd], j.b.off[sd], nbk, F, P,
+                         &j.b.scal[sd ? S_TOT_R : S_TOT_L], j.b.scan_tmp, j.b.scan_tmp_bytes,
+                         j.s));
     JCHK(ev_rec(j, E_C2));
     JCHK(hipMemcpyAsync(j.hs, j.b.scal, S_COUNT * 8, hipMemcpyDeviceToHost, j.s));
     return MSP_OK;

@@ -18,6 +18,8 @@ constexpr int kMaxBig = 64;         // such groups exported per chunk pair (the 
 constexpr int kLightGroup = 256;    // largest left group the light join verifies per lane
 constexpr uint32_t kGroupCap = 1344;   // left records per bucket in the grouped join
 constexpr uint32_t kGroupSlots = 2048; // its LDS table (at most two-thirds full)
+constexpr uint32_t kGroupCapBig = 4096;    // the same for buckets of a few thousand records
+constexpr uint32_t kGroupSlotsBig = 8192;  // (1024-thread work-groups, one-word records)
 
 // Multipliers of the row fingerprint h(v) = sum_i kFpMul[i] * v_i mod 2^32
 // over the non-key rows (odd constants).  h is linear, so a half record's
@@ -36,6 +38,7 @@ struct Plan {
     int32_t exact;                   // 1: M > K_d, each bucket is one key value
     int32_t hsh;                     // qa + qb: shift of the key in Rec::hdr
     int32_t join_grouped;            // join variant: 0 chains, 1 contiguous groups, 2 pairs
+    int32_t gbig;                    // grouped join with 1024-thread groups (big buckets)
     int32_t vjoin;                   // exact runs decided by the vector hash join
     int32_t khb;                     // bits of key >> log2M (every stored key is in [0, K_d])
     int64_t Kd;                      // target key
@@ -86,8 +89,9 @@ struct DevBufs {
     uint32_t *qcnt[4];               // per-cell counts, then exclusive offsets (T+1)
     uint32_t *qcur[4];               // scatter cursors (T)
     uint32_t *cnt[2];                // window counts per side (K*F*P + 1)
-    uint32_t *off[2];                // scanned offsets per side, bucket order [c][f][p]
-    uint32_t *offt[2];               // the same offsets part-major [c][p][f]
+    uint32_t *off[2];                // bucket starts per side [c][f] (+1: the total)
+    uint32_t *pre[2];                // per part, records of earlier parts in the bucket [c][p][f]
+    uint32_t *tot[2];                // records per bucket [c][f]
     void *rec[2];                    // window records per side
     RunPair *runs;                   // run pairs for the tiled verify (record ranges)
     uint32_t *tiles;                 // per run pair tile counts -> offsets (+1)
@@ -136,10 +140,12 @@ hipError_t launch_tile_counts(const Plan &p, const DevBufs &b, uint32_t nruns, i
 hipError_t scan_u32(const uint32_t *in, uint32_t *out, size_t n, uint64_t *total64,
                     void *tmp, size_t tmp_bytes, hipStream_t st);
 size_t scan_tmp_bytes(size_t n);
-// Scan of the count pass's part-major counts in bucket order: offsets in
-// bucket order to `out` (out[n] = total) and part-major to `out_t`.
-hipError_t scan_counts(const uint32_t *in, uint32_t *out, uint32_t *out_t, size_t n, uint32_t F,
-                       uint32_t P, uint64_t *total64, void *tmp, size_t tmp_bytes, hipStream_t st);
+// Offsets of the count pass's part-major counts (nbk = cells x F buckets):
+// per-part prefixes within each bucket to `pre`, bucket totals to `tot`, and
+// bucket starts to `start` (start[nbk] = total, also to *total64 exactly).
+hipError_t scan_counts(const uint32_t *cnt, uint32_t *pre, uint32_t *tot, uint32_t *start,
+                       uint64_t nbk, uint32_t F, uint32_t P, uint64_t *total64, void *tmp,
+                       size_t tmp_bytes, hipStream_t st);
 
 size_t qrec_bytes(int W);
 size_t rec_bytes(int W);

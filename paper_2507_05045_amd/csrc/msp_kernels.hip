@@ -36,14 +36,17 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
     return v;
 }
 
-// Sum over a 256-thread block; result valid in thread 0.
-__device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t *lds4) {
+// Sum over a block of NT threads (lds holds NT / 64 words); result valid in
+// thread 0.
+template <int NT = 256>
+__device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t *lds) {
     v = wave_sum_u64(v);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) lds4[wave] = v;
+    if (lane == 0) lds[wave] = v;
     __syncthreads();
     uint64_t t = 0;
-    if (threadIdx.x == 0) t = lds4[0] + lds4[1] + lds4[2] + lds4[3];
+    if (threadIdx.x == 0)
+        for (int w = 0; w < NT / 64; ++w) t += lds[w];
     __syncthreads();
     return t;
 }
@@ -358,9 +361,12 @@ __global__ __launch_bounds__(NT) void k_scatter_staged(Plan p, const QRec<W> *__
                                                         const uint32_t *__restrict__ offD,
                                                         const uint32_t *__restrict__ offL,
                                                         const uint32_t *__restrict__ offR,
+                                                        const uint32_t *__restrict__ preL,
+                                                        const uint32_t *__restrict__ preR,
                                                         Rec<W> *recL, Rec<W> *recR, int64_t idx0) {
     constexpr bool SR = W <= 1;                  // whole records staged
-    constexpr int BATCH = SR ? 8 * NT : kStageBatch * (NT / 256);
+    // 16 bytes per staged pair: 8 per thread, 7 beside 4096 bucket cursors.
+    constexpr int BATCH = SR ? (MAXF > 2048 ? 7 : 8) * NT : kStageBatch * (NT / 256);
     constexpr int NW = NT / 64;
     constexpr int per = PER;                     // outer elements per thread per chunk
     constexpr int WV = W > 0 ? W : 1;
@@ -389,12 +395,13 @@ __global__ __launch_bounds__(NT) void k_scatter_staged(Plan p, const QRec<W> *__
     const QRec<W> *inner = side ? Dq : B;
     const uint32_t *ioff = side ? offD : offB;
     const uint64_t Qo = side ? p.Q[2] : p.Q[0];
-    const uint32_t *offs = side ? offR : offL;
+    const uint32_t *pre = side ? preR : preL;
+    const uint32_t *bst = side ? offR : offL;
     Rec<W> *rec = side ? recR : recL;
-    // Bucket offsets of this work-group, from the part-major copy the scan
-    // writes ([cell][part][fine]: one contiguous run).
+    // Where this work-group's records of bucket (cell, f) start: the bucket's
+    // start plus the records of the parts before it (both contiguous in f).
     const uint64_t tbase = ((uint64_t)cw * P + part) * F;
-    for (int f = t; f < F; f += NT) s_cur[f] = offs[tbase + f];
+    for (int f = t; f < F; f += NT) s_cur[f] = bst[(uint64_t)cw * F + f] + pre[tbase + f];
     const uint64_t lo = Qo * part / P, hi = Qo * (part + 1) / P;
     const int64_t smod1 = p.slice_mod - 1;
     // The row word of a staged record from the two quarters' words.
@@ -451,9 +458,9 @@ __global__ __launch_bounds__(NT) void k_scatter_staged(Plan p, const QRec<W> *__
                 const uint32_t qa = off >= P0 ? 0u : min(n, P0 - off);
                 const uint32_t qb = (off + n <= P0 + nb) ? n : (P0 + nb > off ? P0 + nb - off : 0u);
                 const uint64_t ai = c0 + (uint64_t)e * NT + t;
-                // Keys (and words) of up to 8 inner elements are loaded
-                // together, then used.
-                constexpr int kU = 8;
+                // Keys (and words) of up to kU inner elements are loaded
+                // together, then used (4 with whole records: registers).
+                constexpr int kU = SR ? 4 : 8;
                 for (uint32_t q0 = qa; q0 < qb; q0 += kU) {
                     int64_t bk[kU];
                     uint32_t bw[kU];
@@ -542,9 +549,8 @@ __global__ __launch_bounds__(256) void k_exact_runs(Plan p, const uint32_t *__re
     const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
     uint64_t h = 0;
     if (b < nb) {
-        const uint64_t P = p.parts;
-        const uint32_t l0 = offL[b * P], l1 = offL[(b + 1) * P];
-        const uint32_t r0 = offR[b * P], r1 = offR[(b + 1) * P];
+        const uint32_t l0 = offL[b], l1 = offL[b + 1];
+        const uint32_t r0 = offR[b], r1 = offR[b + 1];
         if (l1 > l0 && r1 > r0) {
             h = (uint64_t)(l1 - l0) * (r1 - r0);
             const uint64_t idx = atomicAdd((unsigned long long *)&scal[S_NRUNS], 1ull);
@@ -729,7 +735,6 @@ __global__ __launch_bounds__(256) void k_join_light(Plan p, const uint32_t *__re
     __shared__ uint64_t s_s4[4];
     __shared__ uint32_t s_gmax;
     const int t = threadIdx.x;
-    const uint64_t P = p.parts;
     // A bucket's ranges and this lane's share of its records, in registers.
     // Headers are kept raw (the key shift is applied where they are used), so
     // no instruction depends on a load inside its guard and all loads of a
@@ -745,10 +750,10 @@ __global__ __launch_bounds__(256) void k_join_light(Plan p, const uint32_t *__re
     // read record 0 and ignore it): a fixed number of loads per bucket lets
     // the wait for the current bucket leave the next bucket's loads pending.
     auto fetch = [&](uint32_t bb, Slot &f) {
-        f.l0 = offL[bb * P];
-        f.nl = offL[(bb + 1) * P] - f.l0;
-        f.r0 = offR[bb * P];
-        f.nr = offR[(bb + 1) * P] - f.r0;
+        f.l0 = offL[bb];
+        f.nl = offL[bb + 1] - f.l0;
+        f.r0 = offR[bb];
+        f.nr = offR[bb + 1] - f.r0;
 #pragma unroll
         for (int u = 0; u < kLU; ++u) {
             const uint32_t i = t + 256 * u;
@@ -884,13 +889,12 @@ __global__ __launch_bounds__(256) void k_join_pairs(Plan p, const uint32_t *__re
     using KT = typename std::conditional<K32, uint32_t, int64_t>::type;
     __shared__ uint64_t s_s4[4];
     const uint32_t lane = threadIdx.x & 63u;
-    const uint64_t P = p.parts;
     uint64_t hits = 0;
     // Bucket ranges are read by the whole wavefront, so every branch below
     // is uniform per wavefront.
     for (uint32_t b = blockIdx.x * 4u + (threadIdx.x >> 6); b < nb; b += gridDim.x * 4u) {
-        const uint32_t l0 = offL[b * P], nl = offL[(b + 1) * P] - l0;
-        const uint32_t r0 = offR[b * P], nr = offR[(b + 1) * P] - r0;
+        const uint32_t l0 = offL[b], nl = offL[b + 1] - l0;
+        const uint32_t r0 = offR[b], nr = offR[b + 1] - r0;
         if (nl == 0 || nr == 0) continue;
         if (nl > kPairsCap) {
             if (lane == 0) heavy[atomicAdd((unsigned long long *)&scal[S_NHEAVY], 1ull)] = b;
@@ -932,6 +936,29 @@ __global__ __launch_bounds__(256) void k_join_pairs(Plan p, const uint32_t *__re
 }
 
 // Hash of a (key, packed rows) pair for the vector join table.
+// Table hashes of the grouped join, in 32-bit arithmetic when the key part
+// fits 32 bits (fewer instructions than the 64-bit mixes).
+__device__ __forceinline__ uint32_t khash(uint32_t k) {
+    const uint32_t h = k * 0x9E3779B1u;
+    return h ^ (h >> 16);
+}
+__device__ __forceinline__ uint32_t khash(int64_t k) { return key_hash(k); }
+
+template <int W>
+__device__ __forceinline__ uint32_t kv_hash(int64_t key, const uint32_t *v);
+
+template <int W, typename KT>
+__device__ __forceinline__ uint32_t kvhash(KT key, const uint32_t *v) {
+    if constexpr (sizeof(KT) == 4 && W <= 1) {
+        uint32_t h = key * 0x9E3779B1u ^ v[0] * 0x85EBCA77u;
+        h ^= h >> 15;
+        h *= 0xC2B2AE3Du;
+        return h ^ (h >> 13);
+    } else {
+        return kv_hash<W>((int64_t)key, v);
+    }
+}
+
 template <int W>
 __device__ __forceinline__ uint32_t kv_hash(int64_t key, const uint32_t *v) {
     uint64_t h = (uint64_t)key * 0x9E3779B97F4A7C15ull;
@@ -945,9 +972,12 @@ __device__ __forceinline__ uint32_t kv_hash(int64_t key, const uint32_t *v) {
 // distinct key, counts scanned into contiguous groups, and the left rows laid
 // out in group order.  Each right record then walks its group with eight
 // independent LDS loads of first words in flight per step; the other words
-// are read only where the first matches.
-template <int W, bool K32, bool VJ>
-__global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__restrict__ offL,
+// are read only where the first matches.  NTJ threads per work-group and
+// CAP left records at most (SLOTS table entries): 256 / 1344 for buckets of
+// about a thousand records, 1024 / 4096 for buckets of a few thousand.
+template <int W, bool K32, bool VJ, int NTJ = 256, uint32_t CAP = kGroupCap,
+          uint32_t SLOTS = kGroupSlots>
+__global__ __launch_bounds__(NTJ) void k_join_grouped(Plan p, const uint32_t *__restrict__ offL,
                                                    const uint32_t *__restrict__ offR,
                                                    const Rec<W> *__restrict__ L,
                                                    const Rec<W> *__restrict__ R, uint32_t *heavy,
@@ -960,20 +990,21 @@ __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__
     // Capacity and table sized for four work-groups per CU: keys held in 32
     // bits when key >> log2M fits (K32), table at most two-thirds full.
     using KT = typename std::conditional<K32, uint32_t, int64_t>::type;
-    constexpr uint32_t kCap = kGroupCap;
+    constexpr uint32_t kCap = CAP;
+    constexpr int NW = NTJ / 64;
+    static_assert(SLOTS * 2 >= CAP * 3 && SLOTS / NTJ <= 16 && SLOTS >= NTJ, "table size");
     __shared__ KT s_key[kCap];
     __shared__ uint32_t s_vec[WV][kCap + 8];             // left rows: by left index, then by group
-    __shared__ uint32_t s_tab[kGroupSlots];
+    __shared__ uint32_t s_tab[SLOTS];
     __shared__ uint16_t s_slot[kCap];
-    __shared__ uint16_t s_grp[kCap];                     // group order -> left index
-    __shared__ uint32_t s_vt[VJ ? kGroupSlots : 1];      // VJ: (key, rows) -> left index
-    __shared__ uint32_t s_w4[4];
-    __shared__ uint64_t s_s4[4];
+    __shared__ uint16_t s_grp[VJ ? 1 : kCap];            // group order -> left index
+    __shared__ uint32_t s_vt[VJ ? SLOTS : 1];            // VJ: (key, rows) -> left index
+    __shared__ uint32_t s_w4[NW];
+    __shared__ uint64_t s_s4[NW];
     __shared__ uint32_t s_gmax;
     const uint32_t b = blockIdx.x;
-    const uint64_t P = p.parts;
-    const uint32_t l0 = offL[b * P], l1 = offL[(b + 1) * P];
-    const uint32_t r0 = offR[b * P], r1 = offR[(b + 1) * P];
+    const uint32_t l0 = offL[b], l1 = offL[b + 1];
+    const uint32_t r0 = offR[b], r1 = offR[b + 1];
     const uint32_t nl = l1 - l0, nr = r1 - r0;
     if (nl == 0 || nr == 0) return;                     // uniform across the block
     if (nl > kCap) {                                    // too big for LDS: heavy kernel
@@ -991,27 +1022,27 @@ __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__
     uint32_t rv[kPre][WV];
 #pragma unroll
     for (int e = 0; e < kPre; ++e) {
-        const uint32_t j = t + 256 * e;
+        const uint32_t j = t + NTJ * e;
         const uint32_t rj = j < nr ? r0 + j : 0u;
         rh[e] = R[rj].hdr;
 #pragma unroll
         for (int w = 0; w < WV; ++w) rv[e][w] = R[rj].vec[w];
     }
-    uint32_t slots = 256;
-    while (2 * slots < 3 * nl) slots <<= 1;             // <= kGroupSlots for nl <= kCap
+    uint32_t slots = NTJ;
+    while (2 * slots < 3 * nl) slots <<= 1;             // <= SLOTS for nl <= kCap
     const uint32_t smask = slots - 1;
-    for (uint32_t i = t; i < slots; i += 256) {
+    for (uint32_t i = t; i < slots; i += NTJ) {
         s_tab[i] = kEmpty;
         if (VJ) s_vt[i] = 0xFFFFFFFFu;
     }
     if (t == 0) s_gmax = 0;
     {   // all left loads of this lane issued together, then staged into LDS
-        constexpr int kLU = (kCap + 255) / 256;
+        constexpr int kLU = (kCap + NTJ - 1) / NTJ;
         uint64_t lh[kLU];
         uint32_t lv[kLU][WV];
 #pragma unroll
         for (int u = 0; u < kLU; ++u) {
-            const uint32_t i = t + 256 * u;
+            const uint32_t i = t + NTJ * u;
             const uint32_t li = i < nl ? l0 + i : 0u;
             lh[u] = L[li].hdr;
 #pragma unroll
@@ -1019,7 +1050,7 @@ __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__
         }
 #pragma unroll
         for (int u = 0; u < kLU; ++u) {
-            const uint32_t i = t + 256 * u;
+            const uint32_t i = t + NTJ * u;
             if (i < nl) {
                 s_key[i] = (KT)(lh[u] >> p.hsh);
 #pragma unroll
@@ -1029,9 +1060,9 @@ __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__
     }
     __syncthreads();
     // Build: one representative per distinct key, count per slot.
-    for (uint32_t i = t; i < nl; i += 256) {
+    for (uint32_t i = t; i < nl; i += NTJ) {
         const KT k = s_key[i];
-        uint32_t h = key_hash((int64_t)k) & smask;
+        uint32_t h = khash(k) & smask;
         for (;;) {
             uint32_t w = s_tab[h];
             if (w == kEmpty) {
@@ -1049,7 +1080,7 @@ __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__
 #pragma unroll
             for (int w = 0; w < WV; ++w) lvv[w] = s_vec[w][i];
             // At most two-thirds full: an empty slot is always reached.
-            uint32_t g = kv_hash<W>((int64_t)k, lvv) & smask;
+            uint32_t g = kvhash<W>(k, lvv) & smask;
             while (atomicCAS(&s_vt[g], 0xFFFFFFFFu, i) != 0xFFFFFFFFu) g = (g + 1) & smask;
         }
     }
@@ -1057,7 +1088,7 @@ __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__
     if (VJ) {
         uint64_t hits = 0;
         auto probe_vj = [&](const int64_t key, const uint32_t *v, uint32_t rj) {
-            uint32_t h = key_hash(key) & smask;
+            uint32_t h = khash((KT)key) & smask;
             for (;;) {
                 const uint32_t w = s_tab[h];
                 if (w == kEmpty) return;                 // no left record has this key
@@ -1065,7 +1096,7 @@ __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__
                 h = (h + 1) & smask;
             }
             hits += s_tab[h] & 0xFFFFu;                  // |G_L| pairs for this right record
-            for (uint32_t g = kv_hash<W>(key, v) & smask;; g = (g + 1) & smask) {
+            for (uint32_t g = kvhash<W>((KT)key, v) & smask;; g = (g + 1) & smask) {
                 const uint32_t li = s_vt[g];
                 if (li == 0xFFFFFFFFu) break;
                 if (s_key[li] != (KT)key) continue;
@@ -1078,21 +1109,21 @@ __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__
         };
 #pragma unroll
         for (int q = 0; q < kPre; ++q) {
-            const uint32_t j = t + 256 * q;
+            const uint32_t j = t + NTJ * q;
             if (j < nr) probe_vj((int64_t)(rh[q] >> p.hsh), rv[q], j);
         }
-        for (uint32_t j = t + 256 * kPre; j < nr; j += 256) {
+        for (uint32_t j = t + NTJ * kPre; j < nr; j += NTJ) {
             uint32_t v[WV];
 #pragma unroll
             for (int w = 0; w < WV; ++w) v[w] = R[r0 + j].vec[w];
             probe_vj(rkey(p, R[r0 + j]), v, j);
         }
-        const uint64_t tot = block_sum_u64(hits, s_s4);
+        const uint64_t tot = block_sum_u64<NTJ>(hits, s_s4);
         if (t == 0) add_u128(&scal[S_H_LO], &scal[S_H_HI], tot);
         return;
     }
     {   // exclusive scan of the counts (low halves), heads kept
-        const int E = (int)(slots >> 8), lane = t & 63, wave = t >> 6;
+        const int E = (int)(slots / NTJ), lane = t & 63, wave = t >> 6;
         uint32_t loc[16], sum = 0, gm = 0;
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
@@ -1122,17 +1153,17 @@ __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__
         return;
     }
     // Group left records by slot; afterwards the low half is the group end.
-    for (uint32_t i = t; i < nl; i += 256) {
+    for (uint32_t i = t; i < nl; i += NTJ) {
         const uint32_t pos = atomicAdd(&s_tab[s_slot[i]], 1u) & 0xFFFFu;
         s_grp[pos] = (uint16_t)i;
     }
     __syncthreads();
     {   // left rows into group order
-        constexpr int kLU = (kCap + 255) / 256;
+        constexpr int kLU = (kCap + NTJ - 1) / NTJ;
         uint32_t tmp[kLU][WV];
 #pragma unroll
         for (int u = 0; u < kLU; ++u) {
-            const uint32_t q = t + 256 * u;
+            const uint32_t q = t + NTJ * u;
             if (q < nl) {
                 const uint32_t li = s_grp[q];
 #pragma unroll
@@ -1142,7 +1173,7 @@ __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < kLU; ++u) {
-            const uint32_t q = t + 256 * u;
+            const uint32_t q = t + NTJ * u;
             if (q < nl) {
 #pragma unroll
                 for (int w = 0; w < WV; ++w) s_vec[w][q] = tmp[u][w];
@@ -1154,7 +1185,7 @@ __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__
     auto probe = [&](const int64_t key, const uint32_t *v, uint32_t rj) {
         // After the scan an empty slot keeps head 0xFFFF but its low half
         // holds a running offset, so emptiness is read from the head half.
-        uint32_t h = key_hash(key) & smask;
+        uint32_t h = khash((KT)key) & smask;
         uint32_t gs = kNone, ge = 0;
         for (;;) {
             const uint32_t w = s_tab[h];
@@ -1199,16 +1230,16 @@ __global__ __launch_bounds__(256) void k_join_grouped(Plan p, const uint32_t *__
     };
 #pragma unroll
     for (int e = 0; e < kPre; ++e) {
-        const uint32_t j = t + 256 * e;
+        const uint32_t j = t + NTJ * e;
         if (j < nr) probe((int64_t)(rh[e] >> p.hsh), rv[e], j);
     }
-    for (uint32_t j = t + 256 * kPre; j < nr; j += 256) {
+    for (uint32_t j = t + NTJ * kPre; j < nr; j += NTJ) {
         uint32_t v[WV];
 #pragma unroll
         for (int w = 0; w < WV; ++w) v[w] = R[r0 + j].vec[w];
         probe(rkey(p, R[r0 + j]), v, j);
     }
-    const uint64_t tot = block_sum_u64(hits, s_s4);
+    const uint64_t tot = block_sum_u64<NTJ>(hits, s_s4);
     if (t == 0) add_u128(&scal[S_H_LO], &scal[S_H_HI], tot);
 }
 
@@ -1237,12 +1268,11 @@ __global__ __launch_bounds__(256) void k_join_heavy_vj(Plan p, const uint32_t *_
     __shared__ uint64_t s_s4[4];
     const int t = threadIdx.x;
     const uint32_t nheavy = (uint32_t)scal[S_NHEAVY];
-    const uint64_t P = p.parts;
     uint64_t hits = 0;
     for (uint32_t hb = blockIdx.x; hb < nheavy; hb += gridDim.x) {
         const uint32_t b = heavy[hb];
-        const uint32_t L0 = offL[b * P], L1 = offL[(b + 1) * P];
-        const uint32_t r0 = offR[b * P], nr = offR[(b + 1) * P] - r0;
+        const uint32_t L0 = offL[b], L1 = offL[b + 1];
+        const uint32_t r0 = offR[b], nr = offR[b + 1] - r0;
         for (uint32_t l0 = L0; l0 < L1; l0 += kCap) {
             const uint32_t nl = min(kCap, L1 - l0);
             __syncthreads();                            // previous chunk done with LDS
@@ -1370,9 +1400,8 @@ __global__ __launch_bounds__(256) void k_join_heavy(Plan p, const uint32_t *__re
     uint64_t hits = 0;
     for (uint32_t hb = blockIdx.x; hb < nheavy; hb += gridDim.x) {
     const uint32_t b = heavy[hb];
-    const uint64_t P = p.parts;
-    const uint32_t L0 = offL[b * P], L1 = offL[(b + 1) * P];
-    const uint32_t R0 = offR[b * P], R1 = offR[(b + 1) * P];
+    const uint32_t L0 = offL[b], L1 = offL[b + 1];
+    const uint32_t R0 = offR[b], R1 = offR[b + 1];
     // Left chunks of at most kJoinCap records, each against the whole right
     // side: every (left, right) pair of the bucket is met exactly once.
     for (uint32_t lc0 = L0; lc0 < L1; lc0 += kJoinCap) {
@@ -1836,69 +1865,35 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *__restrict__
     }
 }
 
-// Bucket-order scan of part-major counts.  Element i of the scan order
-// [cell][fine][part] sits at ((cell * P + part) * F + fine) of the input; the
-// offsets are written in scan order (bucket ranges for the joins) and again
-// part-major (each count/scatter work-group's F offsets contiguous).
-struct CountMap {
-    uint32_t F, P;
-    __device__ __forceinline__ size_t src(size_t i) const {
-        const size_t fp = (size_t)F * P;
-        const size_t c = i / fp, rem = i - c * fp;
-        const size_t f = rem / P, p = rem - f * P;
-        return (c * P + p) * F + f;
-    }
-};
-
-__global__ __launch_bounds__(256) void k_scan_reduce_map(const uint32_t *__restrict__ in, size_t n,
-                                                         CountMap mp, uint32_t *sums,
-                                                         uint64_t *total64) {
-    __shared__ uint64_t s4[4];
-    const size_t base = (size_t)blockIdx.x * kScanBlock;
-    uint64_t s = 0;
-    for (int e = 0; e < kScanE; ++e) {
-        const size_t i = base + (size_t)e * 256 + threadIdx.x;
-        if (i < n) s += in[mp.src(i)];
-    }
-    s = block_sum_u64(s, s4);
-    if (threadIdx.x == 0) {
-        sums[blockIdx.x] = (uint32_t)s;
-        if (total64) atomicAdd((unsigned long long *)total64, (unsigned long long)s);
-    }
-}
-
-__global__ __launch_bounds__(256) void k_scan_apply_map(const uint32_t *__restrict__ in,
-                                                        uint32_t *out, uint32_t *out_t, size_t n,
-                                                        CountMap mp,
-                                                        const uint32_t *__restrict__ pref,
-                                                        uint64_t *total64) {
-    __shared__ uint32_t s_a[kScanBlock];
-    __shared__ uint32_t s_w4[4];
-    __shared__ uint64_t s_t4[4];
-    const size_t base = (size_t)blockIdx.x * kScanBlock;
-    uint64_t s64 = 0;
-    for (int e = 0; e < kScanE; ++e) {
-        const size_t i = base + (size_t)e * 256 + threadIdx.x;
-        const uint32_t v = i < n ? in[mp.src(i)] : 0u;
-        s_a[e * 256 + threadIdx.x] = v;
-        s64 += v;
-    }
-    __syncthreads();
-    if (total64) s64 = block_sum_u64(s64, s_t4);
-    const uint32_t tot = block_excl_scan_lds<kScanE>(s_a, s_w4);
-    const uint32_t add = pref ? pref[blockIdx.x] : 0u;
-    for (int e = 0; e < kScanE; ++e) {
-        const size_t i = base + (size_t)e * 256 + threadIdx.x;
-        if (i < n) {
-            const uint32_t o = s_a[e * 256 + threadIdx.x] + add;
-            out[i] = o;
-            out_t[mp.src(i)] = o;
+// Offsets of the count pass's part-major counts cnt[cell][part][fine]: one
+// thread per bucket (cell, fine) walks the parts, writing each part's
+// exclusive prefix within the bucket to pre[cell][part][fine] and the
+// bucket's total to tot[cell][fine] (lanes take consecutive buckets, so every
+// access is coalesced).  A scan of tot then gives each bucket's start.
+__global__ __launch_bounds__(256) void k_part_prefix(const uint32_t *__restrict__ cnt,
+                                                     uint32_t *pre, uint32_t *tot, uint64_t nbk,
+                                                     uint32_t F, uint32_t P) {
+    const uint64_t bk = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (bk >= nbk) return;
+    const uint64_t c = bk / F, f = bk - c * F;
+    const uint64_t base = c * P * F + f;
+    uint32_t run = 0, p = 0;
+    for (; p + 4 <= P; p += 4) {              // four independent loads in flight
+        uint32_t v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = cnt[base + (uint64_t)(p + u) * F];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            pre[base + (uint64_t)(p + u) * F] = run;
+            run += v[u];
         }
     }
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
-        out[n] = add + tot;
-        if (total64) *total64 = s64;
+    for (; p < P; ++p) {
+        const uint32_t v = cnt[base + (uint64_t)p * F];
+        pre[base + (uint64_t)p * F] = run;
+        run += v;
     }
+    tot[bk] = run;
 }
 
 size_t scan_tmp_bytes(size_t n) {
@@ -1939,32 +1934,16 @@ hipError_t scan_u32(const uint32_t *in, uint32_t *out, size_t n, uint64_t *total
     return hipGetLastError();
 }
 
-hipError_t scan_counts(const uint32_t *in, uint32_t *out, uint32_t *out_t, size_t n, uint32_t F,
-                       uint32_t P, uint64_t *total64, void *tmp, size_t tmp_bytes, hipStream_t st) {
-    if (n == 0) return scan_u32(in, out, 0, total64, tmp, tmp_bytes, st);
-    const CountMap mp{F, P};
-    const size_t nb = (n + kScanBlock - 1) / kScanBlock;
-    if ((uint64_t)nb * 256 > kMaxGridItems) return hipErrorInvalidConfiguration;
-    if (nb == 1) {
-        hipLaunchKernelGGL(k_scan_apply_map, dim3(1), dim3(256), 0, st, in, out, out_t, n, mp,
-                           nullptr, total64);
-        return hipGetLastError();
-    }
-    const size_t need = (nb + 1) * sizeof(uint32_t) * 2 + 256;
-    if (tmp_bytes < need) return hipErrorInvalidValue;
-    uint32_t *sums = (uint32_t *)tmp;
-    uint32_t *pref = sums + nb + 1;
-    if (total64) {
-        hipError_t e0 = hipMemsetAsync(total64, 0, sizeof(uint64_t), st);
-        if (e0 != hipSuccess) return e0;
-    }
-    hipLaunchKernelGGL(k_scan_reduce_map, dim3((uint32_t)nb), dim3(256), 0, st, in, n, mp, sums,
-                       total64);
-    hipError_t e = scan_u32(sums, pref, nb, nullptr, (char *)tmp + need, tmp_bytes - need, st);
+hipError_t scan_counts(const uint32_t *cnt, uint32_t *pre, uint32_t *tot, uint32_t *start,
+                       uint64_t nbk, uint32_t F, uint32_t P, uint64_t *total64, void *tmp,
+                       size_t tmp_bytes, hipStream_t st) {
+    if (nbk == 0) return scan_u32(tot, start, 0, total64, tmp, tmp_bytes, st);
+    const dim3 g((uint32_t)((nbk + 255) / 256));
+    MSP_GRID_CHECK(g, 256);
+    hipLaunchKernelGGL(k_part_prefix, g, dim3(256), 0, st, cnt, pre, tot, nbk, F, P);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_scan_apply_map, dim3((uint32_t)nb), dim3(256), 0, st, in, out, out_t, n,
-                       mp, pref, nullptr);
-    return hipGetLastError();
+    return scan_u32(tot, start, nbk, total64, tmp, tmp_bytes, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -2082,23 +2061,31 @@ static hipError_t staged_impl(const Plan &p, const DevBufs &b, int64_t idx0, int
     const uint64_t T = (uint64_t)1 << p.log2T;
     const uint64_t qin = std::min((uint64_t)p.Q[1], (uint64_t)p.Q[3]);
     int per = 1;
-    const uint64_t batch256 = W <= 1 ? 8 * 256 : kStageBatch;   // batch per 256 threads
+    // Batch per 256 threads (whole records: 8 pairs per thread, 7 beside 4096
+    // bucket cursors; index staging: 12).
+    const uint64_t batch256 = W <= 1 ? ((1u << p.log2F) > 2048 ? 7 : 8) * 256 : kStageBatch;
     while (per < 16 && (uint64_t)256 * (2 * per) * qin <= batch256 * T) per *= 2;
-    // LDS for the per-bucket cursors is sized to F: more work-groups per CU.
+    // 1024-thread groups hold 128 registers per lane: at most 4 elements per
+    // thread there (more spill).
     const int F = 1 << p.log2F;
+    if (W <= 1 || (F > 1024 && F <= 2048)) per = std::min(per, 4);
+    // LDS for the per-bucket cursors is sized to F: more work-groups per CU.
     if ((uint64_t)K * p.parts > 0xFFFFFFFFull) return hipErrorInvalidConfiguration;
     dim3 grid((uint32_t)K * p.parts, 2);
     MSP_GRID_CHECK(grid, 1024);
-    // Threads per work-group (batch = 12 pairs per thread), by the LDS that
-    // the bucket cursors leave: 512 for F <= 1024 (two groups per CU), 1024
-    // for F = 2048 (one group of 16 waves), 256 for F = 4096.
-#define MSP_NT(MF) ((MF) <= 1024 ? 512 : (MF) <= 2048 ? 1024 : 256)
+    // Threads per work-group, by the LDS that the bucket cursors leave.
+    // Index staging (12 pairs per thread): 512 for F <= 1024 (two groups per
+    // CU), 1024 for F = 2048 (one group of 16 waves), 256 for F = 4096.
+    // Whole one-word records (8 pairs per thread): 1024 (one group per CU;
+    // the largest batch, so the most records per bucket in each store).
+#define MSP_NT(MF) (W <= 1 ? 1024 : (MF) <= 1024 ? 512 : (MF) <= 2048 ? 1024 : 256)
 #define MSP_STAGED(PERV, MF)                                                                    \
     hipLaunchKernelGGL((k_scatter_staged<W, PERV, MF, MSP_NT(MF)>), grid, dim3(MSP_NT(MF)), 0, \
                        st, p,                                                                   \
                        (const QRec<W> *)b.qsrt[0], (const QRec<W> *)b.qsrt[1], b.qcnt[1],       \
                        (const QRec<W> *)b.qsrt[2], (const QRec<W> *)b.qsrt[3], b.qcnt[3],       \
-                       b.offt[0], b.offt[1], (Rec<W> *)b.rec[0], (Rec<W> *)b.rec[1], idx0)
+                       b.off[0], b.off[1], b.pre[0], b.pre[1], (Rec<W> *)b.rec[0],         \
+                       (Rec<W> *)b.rec[1], idx0)
 #define MSP_STAGED_PER(MF)                                                                      \
     switch (per) {                                                                              \
         case 1: MSP_STAGED(1, MF); break;                                                       \
@@ -2142,11 +2129,25 @@ static hipError_t join_impl(const Plan &p, const DevBufs &b, int32_t K, uint64_t
     const uint32_t nb = (uint32_t)K << p.log2F;
     const Rec<W> *L = (const Rec<W> *)b.rec[0], *R = (const Rec<W> *)b.rec[1];
     const dim3 pg(std::min<uint32_t>(nb, 4096));         // persistent chain join
-    // The grouped join takes one work-group per bucket; the others stride.
-    if (p.vjoin || (p.join_grouped == 1)) MSP_GRID_CHECK(dim3(nb), 256);
+    // The grouped join takes one work-group per bucket: 256 threads for
+    // buckets of about a thousand records, 1024 for buckets of a few thousand
+    // (p.gbig).
+    if (p.vjoin || p.join_grouped == 1) MSP_GRID_CHECK(dim3(nb), p.gbig ? 1024 : 256);
 #define MSP_GROUPED(K32V, VJV)                                                                  \
-    hipLaunchKernelGGL((k_join_grouped<W, K32V, VJV>), dim3(nb), dim3(256), 0, st, p, b.off[0], \
-                       b.off[1], L, R, b.heavy, b.scal, b.sol, cap, sorted_quarters<W>(b))
+    do {                                                                                        \
+        if constexpr (W <= 1) {                                                                 \
+            if (p.gbig) {                                                                       \
+                hipLaunchKernelGGL((k_join_grouped<W, K32V, VJV, 1024, kGroupCapBig,            \
+                                                   kGroupSlotsBig>),                            \
+                                   dim3(nb), dim3(1024), 0, st, p, b.off[0], b.off[1], L, R,     \
+                                   b.heavy, b.scal, b.sol, cap, sorted_quarters<W>(b));         \
+                break;                                                                          \
+            }                                                                                   \
+        }                                                                                       \
+            hipLaunchKernelGGL((k_join_grouped<W, K32V, VJV>), dim3(nb), dim3(256), 0, st, p,   \
+                               b.off[0], b.off[1], L, R, b.heavy, b.scal, b.sol, cap,            \
+                               sorted_quarters<W>(b));                                          \
+    } while (0)
     if (p.vjoin && p.khb <= 32)            // vector join: the grouped kernel decides every run
         MSP_GROUPED(true, true);
     else if (p.vjoin)
