@@ -221,12 +221,76 @@ __device__ __forceinline__ void cell_part(uint32_t b, uint32_t K, uint32_t P, in
 // exclusive scan makes every bucket (c, f) contiguous, parts in order.
 
 // Count pass (the enumeration of the scatter without records).  Each thread
-// takes PER outer elements at a time, NT apart so that a wave reads
-// consecutive records, and loads eight inner keys together: the chains of
-// dependent loads (outer key -> cell offsets -> inner keys) of several
-// elements are in flight at once.  Out-of-range lanes load a valid record and
-// ignore it, so every step issues the same loads.
-template <int W, int PER>
+// takes PER outer elements at a time, 256 apart so that a wave reads
+// consecutive records, and loads KU inner keys together (KU about the inner
+// elements per outer element of a cell, so few loads are wasted).  The side
+// and the slice filter are compile-time.  Out-of-range lanes load a valid
+// record and ignore it, so every step issues the same loads.
+template <int W, int PER, int KU, bool SLICE, int SIDE>
+__device__ __forceinline__ void count_body(const Plan &p, const QRec<W> *__restrict__ outer,
+                                           const QRec<W> *__restrict__ inner,
+                                           const uint32_t *__restrict__ ioff, uint64_t Qo,
+                                           uint32_t *cnt, int64_t idx0, uint64_t *scal,
+                                           uint32_t *s_f, unsigned long long *s_pairs) {
+    const int P = p.parts;
+    int cw, part;
+    cell_part(blockIdx.x, gridDim.x / P, P, cw, part);
+    const int t = threadIdx.x;
+    const uint32_t T = 1u << p.log2T;
+    const int F = 1 << p.log2F;
+    const uint32_t k = (uint32_t)(p.kfirst + (idx0 + cw) * p.kstep) & (T - 1);
+    for (int f = t; f < F; f += 256) s_f[f] = 0u;
+    if (t == 0) *s_pairs = 0;
+    __syncthreads();
+    const uint64_t lo = Qo * part / P, hi = Qo * (part + 1) / P;
+    const int64_t smod1 = p.slice_mod - 1, sres = p.slice_res, Kd = p.Kd;
+    const int lt = p.log2T;
+    const uint32_t fmask = (uint32_t)F - 1;
+    uint64_t npairs = 0;                 // pairs this thread enumerates
+    for (uint64_t c0 = lo; c0 < hi; c0 += (uint64_t)256 * PER) {
+        int64_t ak[PER];
+        uint32_t b0[PER], b1[PER];
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const uint64_t i = c0 + (uint64_t)e * 256 + t;
+            ak[e] = outer[i < hi ? i : lo].key;
+        }
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const uint32_t ca = (uint32_t)ak[e] & (T - 1);
+            const uint32_t j = SIDE ? ((ca - k) & (T - 1)) : ((k - ca) & (T - 1));
+            b0[e] = ioff[j];
+            b1[e] = ioff[j + 1];
+        }
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            if (c0 + (uint64_t)e * 256 + t >= hi) b1[e] = b0[e];
+            npairs += b1[e] - b0[e];
+            for (uint32_t q0 = b0[e]; q0 < b1[e]; q0 += KU) {
+                int64_t bk[KU];
+#pragma unroll
+                for (int u = 0; u < KU; ++u) bk[u] = inner[min(q0 + u, b1[e] - 1)].key;
+#pragma unroll
+                for (int u = 0; u < KU; ++u) {
+                    if (q0 + u >= b1[e]) break;
+                    const int64_t key = SIDE ? ak[e] - bk[u] : ak[e] + bk[u];
+                    bool keep = SIDE ? key >= 0 : key <= Kd;   // only these can meet
+                    if (SLICE) keep = keep && ((key & smod1) == sres);
+                    if (keep) atomicAdd(&s_f[(uint32_t)(key >> lt) & fmask], 1u);
+                }
+            }
+        }
+    }
+    if (npairs) atomicAdd(s_pairs, (unsigned long long)npairs);
+    __syncthreads();
+    // Counts of one work-group are contiguous ([cell][part][fine] layout):
+    // whole cache lines, not one word per line.
+    const uint64_t cbase = ((uint64_t)cw * P + part) * F;
+    for (int f = t; f < F; f += 256) cnt[cbase + f] = s_f[f];
+    if (t == 0 && *s_pairs > 0xFFFFFFFFull) atomicOr((unsigned long long *)&scal[S_OVF], 1ull);
+}
+
+template <int W, int PER, int KU, bool SLICE>
 __global__ __launch_bounds__(256) void k_count(Plan p, const QRec<W> *__restrict__ A,
                                                const QRec<W> *__restrict__ B,
                                                const uint32_t *__restrict__ offB,
@@ -237,70 +301,10 @@ __global__ __launch_bounds__(256) void k_count(Plan p, const QRec<W> *__restrict
                                                uint64_t *scal) {
     __shared__ uint32_t s_f[kMaxFine];
     __shared__ unsigned long long s_pairs;
-    const int side = blockIdx.y;
-    const int P = p.parts;
-    int cw, part;
-    cell_part(blockIdx.x, gridDim.x / P, P, cw, part);
-    const int t = threadIdx.x;
-    const uint32_t T = 1u << p.log2T;
-    const int F = 1 << p.log2F;
-    const int64_t M1 = ((int64_t)1 << p.log2M) - 1;
-    const uint32_t k = (uint32_t)(p.kfirst + (idx0 + cw) * p.kstep) & (T - 1);
-    const QRec<W> *outer = side ? Cq : A;
-    const QRec<W> *inner = side ? Dq : B;
-    const uint32_t *ioff = side ? offD : offB;
-    const uint64_t Qo = side ? p.Q[2] : p.Q[0];
-    uint32_t *cnt = side ? cntR : cntL;
-    for (int f = t; f < F; f += 256) s_f[f] = 0u;
-    if (t == 0) s_pairs = 0;
-    __syncthreads();
-    const uint64_t lo = Qo * part / P, hi = Qo * (part + 1) / P;
-    const int64_t smod1 = p.slice_mod - 1;
-    uint64_t npairs = 0;                 // pairs this thread enumerates
-    if (hi > lo) {
-        for (uint64_t c0 = lo; c0 < hi; c0 += (uint64_t)256 * PER) {
-            int64_t ak[PER];
-            uint32_t b0[PER], b1[PER];
-#pragma unroll
-            for (int e = 0; e < PER; ++e) {
-                const uint64_t i = c0 + (uint64_t)e * 256 + t;
-                ak[e] = outer[i < hi ? i : lo].key;
-            }
-#pragma unroll
-            for (int e = 0; e < PER; ++e) {
-                const uint32_t ca = (uint32_t)ak[e] & (T - 1);
-                const uint32_t j = side ? ((ca - k) & (T - 1)) : ((k - ca) & (T - 1));
-                b0[e] = ioff[j];
-                b1[e] = ioff[j + 1];
-            }
-#pragma unroll
-            for (int e = 0; e < PER; ++e) {
-                if (c0 + (uint64_t)e * 256 + t >= hi) b1[e] = b0[e];
-                npairs += b1[e] - b0[e];
-                for (uint32_t q0 = b0[e]; q0 < b1[e]; q0 += 8) {
-                    int64_t bk[8];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) bk[u] = inner[min(q0 + u, b1[e] - 1)].key;
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        if (q0 + u >= b1[e]) break;
-                        const int64_t key = side ? ak[e] - bk[u] : ak[e] + bk[u];
-                        bool keep = side ? key >= 0 : key <= p.Kd;   // only these can meet
-                        if (p.slice_mod) keep = keep && ((key & smod1) == p.slice_res);
-                        if (keep) atomicAdd(&s_f[(uint32_t)((key & M1) >> p.log2T)], 1u);
-                    }
-                }
-            }
-        }
-    }
-    if (npairs) atomicAdd(&s_pairs, (unsigned long long)npairs);
-    __syncthreads();
-    // Counts of one work-group are contiguous ([cell][part][fine] layout):
-    // whole cache lines, not one word per line.  The offset scan reads them
-    // in bucket order [cell][fine][part].
-    const uint64_t cbase = ((uint64_t)cw * P + part) * F;
-    for (int f = t; f < F; f += 256) cnt[cbase + f] = s_f[f];
-    if (t == 0 && s_pairs > 0xFFFFFFFFull) atomicOr((unsigned long long *)&scal[S_OVF], 1ull);
+    if (blockIdx.y == 0)
+        count_body<W, PER, KU, SLICE, 0>(p, A, B, offB, p.Q[0], cntL, idx0, scal, s_f, &s_pairs);
+    else
+        count_body<W, PER, KU, SLICE, 1>(p, Cq, Dq, offD, p.Q[2], cntR, idx0, scal, s_f, &s_pairs);
 }
 
 // Exclusive scan of a[0 .. n) in LDS by an NT-thread block (n a multiple of
@@ -345,13 +349,9 @@ __device__ uint32_t block_excl_scan_rt(T *a, int n, uint32_t *wv) {
 // which costs two cached loads instead of a 16-24 byte LDS round trip.
 constexpr int kStageBatch = 3072;          // pairs per LDS batch (index staging, per 256 threads)
 
-// Records of at most one row word (a fingerprint, one packed word, or none)
-// are built whole while the pairs are enumerated and staged in LDS as they
-// will be stored (8-byte header + 4-byte word, plus the fine bucket and the
-// permutation slot: 16 bytes per pair, batches of 8 pairs per thread); the
-// write-out then reads only LDS.  Wider records stage the pair's (outer,
-// inner) indices (10 bytes, batches of 12 per thread) and rebuild the record
-// from the quarter lists at write-out.
+// Records of two or more row words: the pair's (outer, inner) indices are
+// staged (10 bytes per pair, batches of 12 per thread) and the record is
+// rebuilt from the quarter lists at write-out.
 template <int W, int PER, int MAXF, int NT>
 __global__ __launch_bounds__(NT) void k_scatter_staged(Plan p, const QRec<W> *__restrict__ A,
                                                         const QRec<W> *__restrict__ B,
@@ -364,9 +364,7 @@ __global__ __launch_bounds__(NT) void k_scatter_staged(Plan p, const QRec<W> *__
                                                         const uint32_t *__restrict__ preL,
                                                         const uint32_t *__restrict__ preR,
                                                         Rec<W> *recL, Rec<W> *recR, int64_t idx0) {
-    constexpr bool SR = W <= 1;                  // whole records staged
-    // 16 bytes per staged pair: 8 per thread, 7 beside 4096 bucket cursors.
-    constexpr int BATCH = SR ? (MAXF > 2048 ? 7 : 8) * NT : kStageBatch * (NT / 256);
+    constexpr int BATCH = kStageBatch * (NT / 256);
     constexpr int NW = NT / 64;
     constexpr int per = PER;                     // outer elements per thread per chunk
     constexpr int WV = W > 0 ? W : 1;
@@ -374,10 +372,8 @@ __global__ __launch_bounds__(NT) void k_scatter_staged(Plan p, const QRec<W> *__
     static_assert(BATCH <= 65536, "batch slots must fit 16 bits");
     __shared__ uint32_t s_cur[MAXF];
     __shared__ uint32_t s_cnt[MAXF];
-    __shared__ uint32_t s_q[SR ? 1 : BATCH];     // inner element of the pair
-    __shared__ uint16_t s_io[SR ? 1 : BATCH];    // outer element, relative to the chunk
-    __shared__ uint64_t s_hdr[SR ? BATCH : 1];   // the record's header ...
-    __shared__ uint32_t s_wd[SR ? BATCH : 1];    // ... and its row word
+    __shared__ uint32_t s_q[BATCH];              // inner element of the pair
+    __shared__ uint16_t s_io[BATCH];             // outer element, relative to the chunk
     __shared__ uint16_t s_f[BATCH];              // fine bucket, 0xFFFF = filtered out
     __shared__ uint16_t s_perm[BATCH];
     __shared__ uint32_t s_w4[NW];
@@ -404,11 +400,6 @@ __global__ __launch_bounds__(NT) void k_scatter_staged(Plan p, const QRec<W> *__
     for (int f = t; f < F; f += NT) s_cur[f] = bst[(uint64_t)cw * F + f] + pre[tbase + f];
     const uint64_t lo = Qo * part / P, hi = Qo * (part + 1) / P;
     const int64_t smod1 = p.slice_mod - 1;
-    // The row word of a staged record from the two quarters' words.
-    auto word = [&](uint32_t a, uint32_t b) -> uint32_t {
-        if (p.fp) return side ? p.hd - a - b : a + b;
-        return side ? resid_word(p.dpk[0], a, b) : a + b;
-    };
     for (uint64_t c0 = lo; c0 < hi; c0 += (uint64_t)NT * per) {
         // This thread's outer elements (per of them, NT apart so that a wave
         // reads consecutive records) and the chunk-relative offsets of their
@@ -417,14 +408,12 @@ __global__ __launch_bounds__(NT) void k_scatter_staged(Plan p, const QRec<W> *__
         // and ignores it), so the keys, then the cell ranges, of all its
         // elements are in flight together.
         int64_t akey[PER];
-        uint32_t aw[PER];
         uint32_t b0[PER], nn[PER], c1[PER];
         uint32_t mysum = 0;
 #pragma unroll
         for (int e = 0; e < per; ++e) {
             const uint64_t i = c0 + (uint64_t)e * NT + t;
             akey[e] = outer[i < hi ? i : lo].key;
-            if (SR) aw[e] = outer[i < hi ? i : lo].vec[0];
         }
 #pragma unroll
         for (int e = 0; e < per; ++e) {
@@ -457,20 +446,13 @@ __global__ __launch_bounds__(NT) void k_scatter_staged(Plan p, const QRec<W> *__
                 const uint32_t n = nn[e];
                 const uint32_t qa = off >= P0 ? 0u : min(n, P0 - off);
                 const uint32_t qb = (off + n <= P0 + nb) ? n : (P0 + nb > off ? P0 + nb - off : 0u);
-                const uint64_t ai = c0 + (uint64_t)e * NT + t;
-                // Keys (and words) of up to kU inner elements are loaded
-                // together, then used (4 with whole records: registers).
-                constexpr int kU = SR ? 4 : 8;
+                // Keys of up to 8 inner elements are loaded together, then used.
+                constexpr int kU = 8;
                 for (uint32_t q0 = qa; q0 < qb; q0 += kU) {
                     int64_t bk[kU];
-                    uint32_t bw[kU];
 #pragma unroll
-                    for (int u = 0; u < kU; ++u) {
-                        if (q0 + u < qb) {
-                            bk[u] = inner[b0[e] + q0 + u].key;
-                            if (SR) bw[u] = inner[b0[e] + q0 + u].vec[0];
-                        }
-                    }
+                    for (int u = 0; u < kU; ++u)
+                        if (q0 + u < qb) bk[u] = inner[b0[e] + q0 + u].key;
 #pragma unroll
                     for (int u = 0; u < kU; ++u) {
                         if (q0 + u >= qb) break;
@@ -478,14 +460,8 @@ __global__ __launch_bounds__(NT) void k_scatter_staged(Plan p, const QRec<W> *__
                         bool keep = side ? key >= 0 : key <= p.Kd;
                         if (p.slice_mod) keep = keep && ((key & smod1) == p.slice_res);
                         const uint32_t o = off + q0 + u - P0;
-                        if (SR) {
-                            const uint64_t q = b0[e] + q0 + u;
-                            s_hdr[o] = ai | (q << p.qa) | ((uint64_t)(key >> p.log2M) << p.hsh);
-                            s_wd[o] = word(aw[e], bw[u]);
-                        } else {
-                            s_q[o] = b0[e] + q0 + u;
-                            s_io[o] = (uint16_t)(e * NT + t);
-                        }
+                        s_q[o] = b0[e] + q0 + u;
+                        s_io[o] = (uint16_t)(e * NT + t);
                         s_f[o] = keep ? (uint16_t)((key & M1) >> p.log2T) : (uint16_t)0xFFFF;
                     }
                 }
@@ -506,27 +482,22 @@ __global__ __launch_bounds__(NT) void k_scatter_staged(Plan p, const QRec<W> *__
                 const uint32_t slot = s_perm[o];
                 const uint32_t f = s_f[slot];
                 const uint32_t start = f ? s_cnt[f - 1] : 0u;
-                Rec<W> r;
-                if (SR) {
-                    r.hdr = s_hdr[slot];
-                    r.vec[0] = s_wd[slot];
-                } else {
-                    const uint32_t q = s_q[slot];
-                    const uint64_t ai = c0 + s_io[slot];
-                    // Key and rows only (adjacent in QRec): the mask is not needed.
-                    const int64_t ak = outer[ai].key, bk = inner[q].key;
-                    uint32_t av[WV], bv[WV];
+                const uint32_t q = s_q[slot];
+                const uint64_t ai = c0 + s_io[slot];
+                // Key and rows only (adjacent in QRec): the mask is not needed.
+                const int64_t ak = outer[ai].key, bk = inner[q].key;
+                uint32_t av[WV], bv[WV];
 #pragma unroll
-                    for (int w = 0; w < WV; ++w) {
-                        av[w] = outer[ai].vec[w];
-                        bv[w] = inner[q].vec[w];
-                    }
-                    const int64_t key = side ? ak - bk : ak + bk;
-                    r.hdr = ai | ((uint64_t)q << p.qa) | ((uint64_t)(key >> p.log2M) << p.hsh);
-#pragma unroll
-                    for (int w = 0; w < WV; ++w)
-                        r.vec[w] = side ? resid_word(p.dpk[w], av[w], bv[w]) : av[w] + bv[w];
+                for (int w = 0; w < WV; ++w) {
+                    av[w] = outer[ai].vec[w];
+                    bv[w] = inner[q].vec[w];
                 }
+                const int64_t key = side ? ak - bk : ak + bk;
+                Rec<W> r;
+                r.hdr = ai | ((uint64_t)q << p.qa) | ((uint64_t)(key >> p.log2M) << p.hsh);
+#pragma unroll
+                for (int w = 0; w < WV; ++w)
+                    r.vec[w] = side ? resid_word(p.dpk[w], av[w], bv[w]) : av[w] + bv[w];
                 rec[s_cur[f] + (o - start)] = r;
             }
             __syncthreads();
@@ -534,6 +505,162 @@ __global__ __launch_bounds__(NT) void k_scatter_staged(Plan p, const QRec<W> *__
             __syncthreads();
         }
     }
+}
+
+// Scatter of one-word records (a fingerprint, one packed word, or none):
+// the same enumeration and batching as k_scatter_staged, with the record
+// built whole as its pair is enumerated and staged in LDS as it will be
+// stored (8-byte header, 4-byte word, fine bucket, permutation slot: 16 bytes
+// per pair, 8 per thread; 7 beside 4096 bucket cursors).  The side (left or
+// right), the fingerprint and the slice filter are compile-time, so the pair
+// loop carries no selects between them.
+constexpr int kRecNT = 1024;
+
+template <int W, int PER, int MAXF, bool FP, bool SLICE, int SIDE>
+__device__ __forceinline__ void scatter_rec_body(
+    const Plan &p, const QRec<W> *__restrict__ outer, const QRec<W> *__restrict__ inner,
+    const uint32_t *__restrict__ ioff, uint64_t Qo, const uint32_t *__restrict__ bst,
+    const uint32_t *__restrict__ pre, Rec<W> *rec, int64_t idx0, uint32_t *s_cur,
+    uint32_t *s_cnt, uint64_t *s_hdr, uint32_t *s_wd, uint16_t *s_f, uint16_t *s_perm,
+    uint32_t *s_w4) {
+    constexpr int NT = kRecNT;
+    constexpr int BATCH = (MAXF > 2048 ? 7 : 8) * NT;
+    constexpr int NW = NT / 64;
+    const int P = p.parts;
+    int cw, part;
+    cell_part(blockIdx.x, gridDim.x / P, P, cw, part);
+    const int t = threadIdx.x;
+    const uint32_t T = 1u << p.log2T;
+    const int F = 1 << p.log2F;
+    const int Fs = F < NT ? NT : F;              // scan length (multiple of NT)
+    const uint32_t k = (uint32_t)(p.kfirst + (idx0 + cw) * p.kstep) & (T - 1);
+    const uint64_t tbase = ((uint64_t)cw * P + part) * F;
+    for (int f = t; f < F; f += NT) s_cur[f] = bst[(uint64_t)cw * F + f] + pre[tbase + f];
+    const uint64_t lo = Qo * part / P, hi = Qo * (part + 1) / P;
+    const int64_t smod1 = p.slice_mod - 1, sres = p.slice_res, Kd = p.Kd;
+    const int qa = p.qa, hsh = p.hsh, lm = p.log2M, lt = p.log2T;
+    const uint32_t hd = p.hd, dp0 = p.dpk[0];
+    for (uint64_t c0 = lo; c0 < hi; c0 += (uint64_t)NT * PER) {
+        // This thread's outer elements (PER of them, NT apart so that a wave
+        // reads consecutive records) and the offsets of their pairs in the
+        // chunk.  Past the end a lane reads element lo and ignores it, so all
+        // loads of an element are issued together.
+        int64_t akey[PER];
+        uint32_t aw[PER], b0[PER], nn[PER], c1[PER];
+        uint32_t mysum = 0;
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const uint64_t i = c0 + (uint64_t)e * NT + t;
+            akey[e] = outer[i < hi ? i : lo].key;
+            aw[e] = outer[i < hi ? i : lo].vec[0];
+        }
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const uint32_t ca = (uint32_t)akey[e] & (T - 1);
+            const uint32_t j = SIDE ? ((ca - k) & (T - 1)) : ((k - ca) & (T - 1));
+            b0[e] = ioff[j];
+            c1[e] = ioff[j + 1];
+        }
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            nn[e] = (c0 + (uint64_t)e * NT + t < hi) ? c1[e] - b0[e] : 0u;
+            mysum += nn[e];
+        }
+        const uint32_t inc = wave_incl_scan(mysum);
+        __syncthreads();                          // previous chunk done with s_w4
+        if ((t & 63) == 63) s_w4[t >> 6] = inc;
+        __syncthreads();
+        uint32_t myoff = inc - mysum, total = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            if (w < (t >> 6)) myoff += s_w4[w];
+            total += s_w4[w];
+        }
+        for (uint32_t P0 = 0; P0 < total; P0 += BATCH) {
+            const uint32_t nb = min((uint32_t)BATCH, total - P0);
+            for (int f = t; f < Fs; f += NT) s_cnt[f] = 0;
+            // Stage my pairs whose index falls in [P0, P0 + nb), records whole.
+            uint32_t off = myoff;
+#pragma unroll
+            for (int e = 0; e < PER; ++e) {
+                const uint32_t n = nn[e];
+                const uint32_t qa0 = off >= P0 ? 0u : min(n, P0 - off);
+                const uint32_t qb0 = (off + n <= P0 + nb) ? n : (P0 + nb > off ? P0 + nb - off : 0u);
+                const uint64_t ai = c0 + (uint64_t)e * NT + t;
+                for (uint32_t q = qa0; q < qb0; ++q) {
+                    const uint64_t qi = b0[e] + q;
+                    const int64_t bk = inner[qi].key;
+                    const uint32_t bw = inner[qi].vec[0];
+                    const int64_t key = SIDE ? akey[e] - bk : akey[e] + bk;
+                    bool keep = SIDE ? key >= 0 : key <= Kd;
+                    if (SLICE) keep = keep && ((key & smod1) == sres);
+                    const uint32_t o = off + q - P0;
+                    s_hdr[o] = ai | (qi << qa) | ((uint64_t)(key >> lm) << hsh);
+                    uint32_t wd;
+                    if (FP) wd = SIDE ? hd - aw[e] - bw : aw[e] + bw;
+                    else wd = SIDE ? resid_word(dp0, aw[e], bw) : aw[e] + bw;
+                    s_wd[o] = wd;
+                    s_f[o] = keep ? (uint16_t)((uint32_t)(key >> lt) & (uint32_t)(F - 1))
+                                  : (uint16_t)0xFFFF;
+                }
+                off += n;
+            }
+            __syncthreads();
+            for (uint32_t o = t; o < nb; o += NT)
+                if (s_f[o] != 0xFFFF) atomicAdd(&s_cnt[s_f[o]], 1u);
+            __syncthreads();
+            const uint32_t nvalid = block_excl_scan_rt<uint32_t, NT>(s_cnt, Fs, s_w4);
+            // Rank within the batch; afterwards s_cnt[f] = end of group f.
+            for (uint32_t o = t; o < nb; o += NT) {
+                const uint32_t f = s_f[o];
+                if (f != 0xFFFF) s_perm[atomicAdd(&s_cnt[f], 1u)] = (uint16_t)o;
+            }
+            __syncthreads();
+            for (uint32_t o = t; o < nvalid; o += NT) {
+                const uint32_t slot = s_perm[o];
+                const uint32_t f = s_f[slot];
+                const uint32_t start = f ? s_cnt[f - 1] : 0u;
+                Rec<W> r;
+                r.hdr = s_hdr[slot];
+                r.vec[0] = s_wd[slot];
+                rec[s_cur[f] + (o - start)] = r;
+            }
+            __syncthreads();
+            for (int f = t; f < F; f += NT) s_cur[f] += s_cnt[f] - (f ? s_cnt[f - 1] : 0u);
+            __syncthreads();
+        }
+    }
+}
+
+template <int W, int PER, int MAXF, bool FP, bool SLICE>
+__global__ __launch_bounds__(kRecNT) void k_scatter_rec(Plan p, const QRec<W> *__restrict__ A,
+                                                       const QRec<W> *__restrict__ B,
+                                                       const uint32_t *__restrict__ offB,
+                                                       const QRec<W> *__restrict__ Cq,
+                                                       const QRec<W> *__restrict__ Dq,
+                                                       const uint32_t *__restrict__ offD,
+                                                       const uint32_t *__restrict__ offL,
+                                                       const uint32_t *__restrict__ offR,
+                                                       const uint32_t *__restrict__ preL,
+                                                       const uint32_t *__restrict__ preR,
+                                                       Rec<W> *recL, Rec<W> *recR, int64_t idx0) {
+    static_assert(W <= 1, "one-word records");
+    constexpr int BATCH = (MAXF > 2048 ? 7 : 8) * kRecNT;
+    static_assert(BATCH <= 65536, "batch slots must fit 16 bits");
+    __shared__ uint32_t s_cur[MAXF];
+    __shared__ uint32_t s_cnt[MAXF > kRecNT ? MAXF : kRecNT];
+    __shared__ uint64_t s_hdr[BATCH];
+    __shared__ uint32_t s_wd[BATCH];
+    __shared__ uint16_t s_f[BATCH];
+    __shared__ uint16_t s_perm[BATCH];
+    __shared__ uint32_t s_w4[kRecNT / 64];
+    if (blockIdx.y == 0)
+        scatter_rec_body<W, PER, MAXF, FP, SLICE, 0>(p, A, B, offB, p.Q[0], offL, preL, recL, idx0,
+                                                     s_cur, s_cnt, s_hdr, s_wd, s_f, s_perm, s_w4);
+    else
+        scatter_rec_body<W, PER, MAXF, FP, SLICE, 1>(p, Cq, Dq, offD, p.Q[2], offR, preR, recR,
+                                                     idx0, s_cur, s_cnt, s_hdr, s_wd, s_f, s_perm,
+                                                     s_w4);
 }
 
 // ---------------------------------------------------------------------------
@@ -2032,18 +2159,32 @@ hipError_t launch_quarters(const Plan &p, const DevBufs &b, int, hipStream_t st)
 template <int W>
 static hipError_t count_impl(const Plan &p, const DevBufs &b, int64_t idx0, int32_t K,
                              hipStream_t st) {
-    // Four outer elements per thread while cells hold few inner elements.
+    // Four outer elements per thread while cells hold few inner elements;
+    // inner keys loaded about as many at a time as a cell holds per element.
     const uint64_t T = (uint64_t)1 << p.log2T;
     const uint64_t qin = std::min((uint64_t)p.Q[1], (uint64_t)p.Q[3]);
     if ((uint64_t)K * p.parts > 0xFFFFFFFFull) return hipErrorInvalidConfiguration;
     dim3 grid((uint32_t)K * p.parts, 2);
     MSP_GRID_CHECK(grid, 256);
-#define MSP_COUNT(PERV)                                                                         \
-    hipLaunchKernelGGL((k_count<W, PERV>), grid, dim3(256), 0, st, p, (const QRec<W> *)b.qsrt[0], \
-                       (const QRec<W> *)b.qsrt[1], b.qcnt[1], (const QRec<W> *)b.qsrt[2],       \
-                       (const QRec<W> *)b.qsrt[3], b.qcnt[3], b.cnt[0], b.cnt[1], idx0, b.scal)
-    if (qin >= 16 * T) MSP_COUNT(1);
-    else MSP_COUNT(4);
+    const bool sl = p.slice_mod != 0;
+#define MSP_COUNT(PERV, KUV)                                                                    \
+    do {                                                                                        \
+        if (sl)                                                                                 \
+            hipLaunchKernelGGL((k_count<W, PERV, KUV, true>), grid, dim3(256), 0, st, p,        \
+                               (const QRec<W> *)b.qsrt[0], (const QRec<W> *)b.qsrt[1],          \
+                               b.qcnt[1], (const QRec<W> *)b.qsrt[2],                           \
+                               (const QRec<W> *)b.qsrt[3], b.qcnt[3], b.cnt[0], b.cnt[1], idx0, \
+                               b.scal);                                                         \
+        else                                                                                    \
+            hipLaunchKernelGGL((k_count<W, PERV, KUV, false>), grid, dim3(256), 0, st, p,       \
+                               (const QRec<W> *)b.qsrt[0], (const QRec<W> *)b.qsrt[1],          \
+                               b.qcnt[1], (const QRec<W> *)b.qsrt[2],                           \
+                               (const QRec<W> *)b.qsrt[3], b.qcnt[3], b.cnt[0], b.cnt[1], idx0, \
+                               b.scal);                                                         \
+    } while (0)
+    if (qin >= 16 * T) MSP_COUNT(1, 8);
+    else if (qin > 2 * T) MSP_COUNT(4, 4);
+    else MSP_COUNT(4, 2);
 #undef MSP_COUNT
     return hipGetLastError();
 }
@@ -2061,24 +2202,19 @@ static hipError_t staged_impl(const Plan &p, const DevBufs &b, int64_t idx0, int
     const uint64_t T = (uint64_t)1 << p.log2T;
     const uint64_t qin = std::min((uint64_t)p.Q[1], (uint64_t)p.Q[3]);
     int per = 1;
-    // Batch per 256 threads (whole records: 8 pairs per thread, 7 beside 4096
-    // bucket cursors; index staging: 12).
-    const uint64_t batch256 = W <= 1 ? ((1u << p.log2F) > 2048 ? 7 : 8) * 256 : kStageBatch;
-    while (per < 16 && (uint64_t)256 * (2 * per) * qin <= batch256 * T) per *= 2;
+    while (per < 16 && (uint64_t)256 * (2 * per) * qin <= (uint64_t)kStageBatch * T) per *= 2;
     // 1024-thread groups hold 128 registers per lane: at most 4 elements per
     // thread there (more spill).
     const int F = 1 << p.log2F;
-    if (W <= 1 || (F > 1024 && F <= 2048)) per = std::min(per, 4);
+    if (F > 1024 && F <= 2048) per = std::min(per, 4);
     // LDS for the per-bucket cursors is sized to F: more work-groups per CU.
     if ((uint64_t)K * p.parts > 0xFFFFFFFFull) return hipErrorInvalidConfiguration;
     dim3 grid((uint32_t)K * p.parts, 2);
     MSP_GRID_CHECK(grid, 1024);
-    // Threads per work-group, by the LDS that the bucket cursors leave.
-    // Index staging (12 pairs per thread): 512 for F <= 1024 (two groups per
-    // CU), 1024 for F = 2048 (one group of 16 waves), 256 for F = 4096.
-    // Whole one-word records (8 pairs per thread): 1024 (one group per CU;
-    // the largest batch, so the most records per bucket in each store).
-#define MSP_NT(MF) (W <= 1 ? 1024 : (MF) <= 1024 ? 512 : (MF) <= 2048 ? 1024 : 256)
+    // Threads per work-group (batch = 12 pairs per thread), by the LDS that
+    // the bucket cursors leave: 512 for F <= 1024 (two groups per CU), 1024
+    // for F = 2048 (one group of 16 waves), 256 for F = 4096.
+#define MSP_NT(MF) ((MF) <= 1024 ? 512 : (MF) <= 2048 ? 1024 : 256)
 #define MSP_STAGED(PERV, MF)                                                                    \
     hipLaunchKernelGGL((k_scatter_staged<W, PERV, MF, MSP_NT(MF)>), grid, dim3(MSP_NT(MF)), 0, \
                        st, p,                                                                   \
@@ -2107,10 +2243,64 @@ static hipError_t staged_impl(const Plan &p, const DevBufs &b, int64_t idx0, int
     return hipGetLastError();
 }
 
+template <int W, bool FP, bool SLICE>
+static hipError_t rec_impl(const Plan &p, const DevBufs &b, int64_t idx0, int32_t K,
+                           hipStream_t st) {
+    // Outer elements per thread per chunk: enough pairs (about Q_inner / T
+    // per outer element) to fill one batch, at most 4 (128 registers).
+    const uint64_t T = (uint64_t)1 << p.log2T;
+    const uint64_t qin = std::min((uint64_t)p.Q[1], (uint64_t)p.Q[3]);
+    const int F = 1 << p.log2F;
+    const uint64_t batch = (uint64_t)(F > 2048 ? 7 : 8) * kRecNT;
+    int per = 1;
+    while (per < 4 && (uint64_t)kRecNT * (2 * per) * qin <= batch * T) per *= 2;
+    if ((uint64_t)K * p.parts > 0xFFFFFFFFull) return hipErrorInvalidConfiguration;
+    dim3 grid((uint32_t)K * p.parts, 2);
+    MSP_GRID_CHECK(grid, kRecNT);
+#define MSP_REC(PERV, MF)                                                                       \
+    hipLaunchKernelGGL((k_scatter_rec<W, PERV, MF, FP, SLICE>), grid, dim3(kRecNT), 0, st, p,   \
+                       (const QRec<W> *)b.qsrt[0], (const QRec<W> *)b.qsrt[1], b.qcnt[1],       \
+                       (const QRec<W> *)b.qsrt[2], (const QRec<W> *)b.qsrt[3], b.qcnt[3],       \
+                       b.off[0], b.off[1], b.pre[0], b.pre[1], (Rec<W> *)b.rec[0],              \
+                       (Rec<W> *)b.rec[1], idx0)
+#define MSP_REC_PER(MF)                                                                         \
+    switch (per) {                                                                              \
+        case 1: MSP_REC(1, MF); break;                                                          \
+        case 2: MSP_REC(2, MF); break;                                                          \
+        default: MSP_REC(4, MF); break;                                                         \
+    }
+    if (F <= 1024) {
+        MSP_REC_PER(1024)
+    } else if (F <= 2048) {
+        MSP_REC_PER(2048)
+    } else {
+        MSP_REC_PER(kMaxFine)
+    }
+#undef MSP_REC_PER
+#undef MSP_REC
+    return hipGetLastError();
+}
+
 hipError_t launch_scatter(const Plan &p, const DevBufs &b, int64_t idx0, int32_t K,
                           hipStream_t st) {
-    MSP_DISPATCH_W(p.Wr, return staged_impl<WW>(p, b, idx0, K, st));
-    return hipSuccess;
+    const bool sl = p.slice_mod != 0;
+    if (p.Wr == 0)
+        return sl ? rec_impl<0, false, true>(p, b, idx0, K, st)
+                  : rec_impl<0, false, false>(p, b, idx0, K, st);
+    if (p.Wr == 1) {
+        if (p.fp)
+            return sl ? rec_impl<1, true, true>(p, b, idx0, K, st)
+                      : rec_impl<1, true, false>(p, b, idx0, K, st);
+        return sl ? rec_impl<1, false, true>(p, b, idx0, K, st)
+                  : rec_impl<1, false, false>(p, b, idx0, K, st);
+    }
+    switch (p.Wr) {
+        case 2: return staged_impl<2>(p, b, idx0, K, st);
+        case 3: return staged_impl<3>(p, b, idx0, K, st);
+        case 4: return staged_impl<4>(p, b, idx0, K, st);
+        case 5: return staged_impl<5>(p, b, idx0, K, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_exact_runs(const Plan &p, const DevBufs &b, int32_t K, hipStream_t st) {
