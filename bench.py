@@ -157,6 +157,11 @@ def _pct(xs, q):
 
 
 def run_stream(args):
+    out = stream_results(args.stream_count, not args.no_closed_loop)
+    print(json.dumps(out), flush=True)
+
+
+def stream_results(count, closed_loop=True):
     """Uneven stream (m in {5..8}, n = 10(m-1), r = m - 4, odd instances
     planted): plain one-at-a-time solves, one batched solve, and a served run
     with Poisson arrivals at twice the plain rate, plus a closed-loop served
@@ -169,7 +174,7 @@ def run_stream(args):
     def say(*a):                     # progress on stderr; the JSON line stays alone on stdout
         print(*a, file=sys.stderr, flush=True)
 
-    insts = stream_instances(args.stream_count)
+    insts = stream_instances(count)
     opts = []
     for i in insts:
         o = dict(key_rows=i.key_rows)
@@ -261,7 +266,7 @@ def run_stream(args):
     rate = 2.0 * plain["instances_per_s"]
     poisson = served(poisson_arrivals(len(insts), rate, seed=7))
     poisson["rate_per_s"] = rate
-    closed = served([0.0] * len(insts)) if not args.no_closed_loop else None
+    closed = served([0.0] * len(insts)) if closed_loop else None
     ms = [int(i.m) for i in insts]
     out = {
         "metric": "1-D hits verified/s (served stream) + p50/p99 latency",
@@ -277,7 +282,7 @@ def run_stream(args):
         "speedup_vs_plain": {"batched": t_plain / t_batch,
                              "served_closed": t_plain / closed["makespan_s"] if closed else None},
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def main():
@@ -288,6 +293,10 @@ def main():
     ap.add_argument("--workload", default="9_80", choices=sorted(WORKLOADS) + ["stream"])
     ap.add_argument("--no-whole", action="store_true",
                     help="skip the whole solve after the timed slice steps (9_80)")
+    ap.add_argument("--no-first", action="store_true",
+                    help="skip the time to the first solution of the planted twin (9_80)")
+    ap.add_argument("--no-stream", action="store_true",
+                    help="skip the 32-instance plain/batched/served stream (9_80)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--first-solution", action="store_true",
                     help="stop each solve at the first verified solution (time to first solution)")
@@ -448,6 +457,30 @@ def main():
     }
     if whole is not None:
         out["whole_solve"] = whole
+    if w.get("whole") and not args.no_first:
+        # Time to the first solution (Algorithm 2 returns the first x) on the
+        # planted twin of the same class: the paper's benchmark instances are
+        # feasible, and its table times are most likely times to a first x.
+        from paper_2507_05045_amd.inputs import make_instance
+        tw = make_instance(w["m"], w["n"], w["seeds"][0], planted=True, key_rows=w["key_rows"])
+        c = msp.Context(tw.A, tw.d)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        c.solve(**{**kw, "slice_mod": 0, "slice_res": 0, "verify_join": 0, "first_only": 1},
+                **plans[0])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter() - t1
+        st = c.stats()
+        sols = c.solutions()
+        out["time_to_first_solution"] = {
+            "instance": tw.name, "seconds": t1, "solutions": int(c.num_solutions()),
+            "planted_found": bool(any((x == tw.planted).all() for x in sols)),
+            "windows": f"{st['windows']}/{st['windows_total']}"}
+        c.close()
+    if w.get("whole") and not args.no_stream:
+        # Plain, batched and served solves of an uneven stream of 32 instances.
+        print("stream of 32 instances ...", file=sys.stderr, flush=True)
+        out["stream"] = stream_results(32, closed_loop=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, insts)
     print(json.dumps(out), flush=True)

@@ -106,7 +106,11 @@ typedef struct {
                                  rows themselves (2 rows per word); 0 = planner:
                                  the fingerprint when the rows take 2 or more words.
                                  Same H, |S| and solutions                        */
-    int32_t  reserved0;
+    int32_t  first_order;     /* with first_only: 0 = residue windows in decreasing
+                                 order of candidate pairs (sum over buckets of left x
+                                 right records, from one count pass over all windows;
+                                 for buckets of one key value, the window's 1-D hits),
+                                 so the densest windows come first; 1 = cell order */
 } msp_opts;
 
 /* Per-solve statistics; phase times are measured with HIP events on the
@@ -135,10 +139,14 @@ typedef struct {
                                  2 = one wavefront per bucket                        */
     int32_t  key_base;        /* the key radix used (msp_opts.key_base)              */
     int32_t  row_fingerprint; /* 1: half records carried a row fingerprint          */
-    uint64_t cells_done;      /* residue cells processed, in cell order: the cells
-                                 k_first + i * k_step, i < cells_done (k_step = 1 and
-                                 k_first = 0 without a slice); all of them unless
-                                 first_only stopped early                            */
+    uint64_t cells_done;      /* residue cells processed; in cell order (window_order
+                                 0) they are the cells k_first + i * k_step,
+                                 i < cells_done (k_step = 1 and k_first = 0 without a
+                                 slice); all of them unless first_only stopped early */
+    int32_t  window_order;    /* 1: first_only took windows in density order        */
+    int32_t  reserved1;
+    uint64_t first_cell;      /* window_order 1: index of the first cell of the first
+                                 window processed (the densest)                      */
 } msp_stats_t;
 
 /* Device memory from the caller, e.g. a torch-allocated arena, so that the

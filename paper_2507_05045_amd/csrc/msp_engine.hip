@@ -101,7 +101,7 @@ struct Sizes {
     uint64_t total = 0;      // workspace bytes
     // offsets into the workspace
     uint64_t o_qraw[4], o_qsrt[4], o_qcnt[4], o_qcur[4], o_cnt[2], o_off[2], o_rec[2];
-    uint64_t o_qvraw[4], o_qvsrt[4], o_pre[2], o_tot[2];
+    uint64_t o_qvraw[4], o_qvsrt[4], o_pre[2], o_tot[2], o_wscore = 0;
     uint64_t o_runs, o_tiles, o_sol, o_scal, o_scan, scan_bytes, o_colw, o_rows;
     uint64_t o_iruns, o_itiles, o_idx, n_iruns, o_heavy, idx_n;
     uint64_t o_vtab, vtab_slots;
@@ -307,6 +307,7 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
         if (!p.exact && per_bucket > 1100) p.gbig = 1;
     }
     if (o.verify_join < 0 || o.verify_join > 2) return MSP_E_INVALID;
+    if (o.first_order < 0 || o.first_order > 1) return MSP_E_INVALID;
     if (o.verify_join == 1) p.vjoin = 1;
     else if (o.verify_join == 2) p.vjoin = 0;
     else p.vjoin = expected_group_lg2(c, p) >= 4.0 ? 1 : 0;
@@ -402,6 +403,7 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
         if (p.vjoin && p.exact)
             while (z.vtab_slots < 2 * cap_rec) z.vtab_slots <<= 1;
         z.o_vtab = take(z.vtab_slots * 4);
+        z.o_wscore = take(((z.ncells + kw - 1) / kw) * 8 + 8);
         z.o_sol = take(z.sol_cap * 16);
         z.o_scal = take(S_COUNT * 8);
         z.scan_bytes = scan_tmp_bytes(std::max<uint64_t>(std::max<uint64_t>(T + 1, ncnt),
@@ -502,7 +504,7 @@ struct Arena {
 // kernels on the job's stream; the runner synchronises all jobs between
 // calls, so concurrent jobs overlap on the device.
 // ---------------------------------------------------------------------------
-enum Action { A_BEGIN, A_COUNTED, A_JOINED, A_TILED, A_FINAL1, A_FINAL2, A_DONE };
+enum Action { A_BEGIN, A_ORDER, A_COUNTED, A_JOINED, A_TILED, A_FINAL1, A_FINAL2, A_DONE };
 enum Ev { E_Q0, E_Q1, E_C0, E_C1, E_C2, E_S0, E_S1, E_S2, E_V0, E_V1, E_COUNT };
 
 struct Job {
@@ -520,6 +522,13 @@ struct Job {
     bool hs_pinned = false;
     Action next = A_BEGIN;
     uint64_t idx = 0, kw = 0, K = 0;
+    // First-solution mode in density order: planned windows (start cells)
+    // in processing order, the current one's cell range, and cells done.
+    bool ordered = false;
+    std::vector<uint64_t> order;
+    std::vector<uint64_t> scores;
+    size_t oi = 0;
+    uint64_t win_hi = 0, cells_done = 0;
     bool verify_pending = false;
     std::vector<uint64_t> solbuf;
     msp_stats_t st{};
@@ -589,6 +598,7 @@ void job_carve(Job &j) {
     j.b.iruns_cap = z.n_iruns;
     j.b.idx_cap = z.idx_n;
     j.b.sol = (uint64_t *)(ws + z.o_sol);
+    j.b.wscore = (uint64_t *)(ws + z.o_wscore);
     j.b.scal = (uint64_t *)(ws + z.o_scal);
     j.b.scan_tmp = ws + z.o_scan;
     j.b.scan_tmp_bytes = z.scan_bytes;
@@ -639,9 +649,53 @@ int job_step(Job &j) {
             JCHK(ev_rec(j, E_Q0));
             JCHK(launch_quarters(p, j.b, 0, j.s));
             JCHK(ev_rec(j, E_Q1));
-            j.idx = 0;
             j.kw = z.kwin;
+            j.cells_done = 0;
+            const uint64_t nwin = (z.ncells + z.kwin - 1) / z.kwin;
+            if (j.o.first_only && j.o.first_order == 0 && nwin > 1) {
+                // Algorithm 2 stops at the first solution; windows are taken
+                // in order of their count of candidate pairs (sum over
+                // buckets of left x right records; for buckets of one key
+                // value that is the window's number of 1-D hits), so the
+                // densest windows come first.  One count pass over every
+                // window gives the scores.
+                j.ordered = true;
+                JCHK(hipMemsetAsync(j.b.wscore, 0, nwin * 8, j.s));
+                for (uint64_t w = 0; w < nwin; ++w) {
+                    j.idx = w * z.kwin;
+                    j.K = std::min<uint64_t>(z.kwin, z.ncells - j.idx);
+                    JCHK(launch_count(p, j.b, (int64_t)j.idx, (int32_t)j.K, j.s));
+                    const uint64_t nbk = j.K << p.log2F;
+                    for (int sd = 0; sd < 2; ++sd)
+                        JCHK(scan_counts(j.b.cnt[sd], j.b.pre[sd], j.b.tot[sd], j.b.off[sd], nbk,
+                                         1u << p.log2F, (uint32_t)p.parts, nullptr, j.b.scan_tmp,
+                                         j.b.scan_tmp_bytes, j.s));
+                    JCHK(launch_window_score(j.b, nbk, j.b.wscore + w, j.s));
+                }
+                j.scores.assign(nwin, 0);
+                JCHK(hipMemcpyAsync(j.scores.data(), j.b.wscore, nwin * 8, hipMemcpyDeviceToHost,
+                                    j.s));
+                j.next = A_ORDER;
+                return MSP_OK;
+            }
+            j.idx = 0;
+            j.win_hi = z.ncells;
             j.K = std::min<uint64_t>(j.kw, z.ncells - j.idx);
+            int rc = enqueue_count(j);
+            if (rc) return rc;
+            j.next = A_COUNTED;
+            return MSP_OK;
+        }
+        case A_ORDER: {
+            const uint64_t nwin = j.scores.size();
+            j.order.resize(nwin);
+            std::iota(j.order.begin(), j.order.end(), (uint64_t)0);
+            std::stable_sort(j.order.begin(), j.order.end(),
+                             [&](uint64_t a, uint64_t bb) { return j.scores[a] > j.scores[bb]; });
+            j.oi = 0;
+            j.idx = j.order[0] * z.kwin;
+            j.win_hi = std::min<uint64_t>(j.idx + z.kwin, z.ncells);
+            j.K = j.win_hi - j.idx;
             int rc = enqueue_count(j);
             if (rc) return rc;
             j.next = A_COUNTED;
@@ -740,9 +794,21 @@ int job_step(Job &j) {
             }
             // Window done; move to the next one or finish.
             j.st.windows++;
+            j.cells_done += j.K;
             j.idx += j.K;
-            if (j.idx < z.ncells && !j.cancel) {
-                j.K = std::min<uint64_t>(j.kw, z.ncells - j.idx);
+            bool more;
+            if (j.ordered) {
+                if (j.idx >= j.win_hi && ++j.oi < j.order.size()) {   // next planned window
+                    j.idx = j.order[j.oi] * z.kwin;
+                    j.win_hi = std::min<uint64_t>(j.idx + z.kwin, z.ncells);
+                    j.kw = z.kwin;
+                }
+                more = j.oi < j.order.size();
+            } else {
+                more = j.idx < z.ncells;
+            }
+            if (more && !j.cancel) {
+                j.K = std::min<uint64_t>(j.kw, j.win_hi - j.idx);
                 int rc = enqueue_count(j);
                 if (rc) return rc;
                 j.next = A_COUNTED;
@@ -789,8 +855,10 @@ int job_step(Job &j) {
             c->h_lo = j.hs[S_H_LO];
             c->h_hi = j.hs[S_H_HI];
             c->nsol = j.hs[S_NSOL];
-            j.st.complete = j.idx >= z.ncells ? 1 : 0;
-            j.st.cells_done = std::min<uint64_t>(j.idx, z.ncells);
+            j.st.complete = j.cells_done >= z.ncells ? 1 : 0;
+            j.st.cells_done = j.cells_done;
+            j.st.window_order = j.ordered ? 1 : 0;
+            j.st.first_cell = j.ordered && !j.order.empty() ? j.order[0] * z.kwin : 0;
             j.st.ms_total = (now_s() - j.t_wall0) * 1e3;
             c->stats = j.st;
             c->have_result = true;

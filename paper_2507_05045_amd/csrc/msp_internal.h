@@ -103,6 +103,7 @@ struct DevBufs {
     uint32_t *vtab;                  // vector join table: left record index or ~0
     uint32_t vtab_mask;              // slots - 1 (a power of two, >= 2x the left records)
     uint64_t *sol;                   // solutions: (maskL, maskR) pairs
+    uint64_t *wscore;                // per planned window: candidate pairs (first-solution order)
     uint64_t *scal;                  // scalars (see Scal)
     void *scan_tmp;                  // scratch of the device-wide scan
     size_t scan_tmp_bytes;
@@ -130,6 +131,9 @@ hipError_t launch_hash_join(const Plan &p, const DevBufs &b, int32_t K, uint64_t
 // mode 0: exact run pairs, 1: key-checked run pairs, 2: indexed run pairs.
 hipError_t launch_verify(const Plan &p, const DevBufs &b, uint32_t nruns, uint32_t ntiles,
                          uint64_t sol_cap, int mode, hipStream_t st);
+// Adds sum over the nbk buckets of tot[0][b] * tot[1][b] (left x right
+// records) to *score.
+hipError_t launch_window_score(const DevBufs &b, uint64_t nbk, uint64_t *score, hipStream_t st);
 // Exact-bucket runs decided by a hash join on the packed non-key rows.
 hipError_t launch_vector_join(const Plan &p, const DevBufs &b, uint32_t nruns, uint64_t sol_cap,
                               hipStream_t st);

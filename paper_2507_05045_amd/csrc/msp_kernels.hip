@@ -2073,6 +2073,26 @@ hipError_t scan_counts(const uint32_t *cnt, uint32_t *pre, uint32_t *tot, uint32
     return scan_u32(tot, start, nbk, total64, tmp, tmp_bytes, st);
 }
 
+// Candidate pairs of a window: sum over buckets of left x right records.
+__global__ __launch_bounds__(256) void k_window_score(const uint32_t *__restrict__ totL,
+                                                      const uint32_t *__restrict__ totR,
+                                                      uint64_t nbk, uint64_t *score) {
+    __shared__ uint64_t s4[4];
+    uint64_t v = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < nbk;
+         i += (uint64_t)gridDim.x * 256)
+        v += (uint64_t)totL[i] * totR[i];
+    v = block_sum_u64(v, s4);
+    if (threadIdx.x == 0 && v) atomicAdd((unsigned long long *)score, (unsigned long long)v);
+}
+
+hipError_t launch_window_score(const DevBufs &b, uint64_t nbk, uint64_t *score, hipStream_t st) {
+    if (nbk == 0) return hipSuccess;
+    const dim3 g((uint32_t)std::min<uint64_t>((nbk + 255) / 256, 1024));
+    hipLaunchKernelGGL(k_window_score, g, dim3(256), 0, st, b.tot[0], b.tot[1], nbk, score);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------

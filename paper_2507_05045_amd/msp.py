@@ -39,7 +39,7 @@ class msp_opts(C.Structure):
                 ("workspace", C.c_void_p), ("workspace_bytes", C.c_uint64),
                 ("stream", C.c_void_p), ("first_only", C.c_int32), ("join_variant", C.c_int32),
                 ("verify_join", C.c_int32), ("key_base", C.c_int32),
-                ("row_fingerprint", C.c_int32), ("reserved0", C.c_int32)]
+                ("row_fingerprint", C.c_int32), ("first_order", C.c_int32)]
 
 
 class msp_stats_t(C.Structure):
@@ -53,7 +53,8 @@ class msp_stats_t(C.Structure):
                 ("words", C.c_int32), ("complete", C.c_int32), ("vector_join", C.c_int32),
                 ("windows_total", C.c_uint64), ("join_grouped", C.c_int32),
                 ("key_base", C.c_int32), ("row_fingerprint", C.c_int32),
-                ("cells_done", C.c_uint64)]
+                ("cells_done", C.c_uint64), ("window_order", C.c_int32), ("reserved1", C.c_int32),
+                ("first_cell", C.c_uint64)]
 
 
 class msp_batch_opts(C.Structure):

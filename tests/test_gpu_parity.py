@@ -397,10 +397,11 @@ def _first_only_vs_oracle(inst, r, **kw):
     oracle's over the cells it processed (classes k_L mod T below cells_done)."""
     from paper_2507_05045_amd import msp
     ctx = msp.Context(inst.A, inst.d)
-    ctx.solve(key_rows=r, first_only=1, **kw)
+    ctx.solve(key_rows=r, first_only=1, first_order=1, **kw)
     first = ctx.result()
     st = first.stats
     ctx.close()
+    assert st["window_order"] == 0
     assert first.nsol >= 1
     assert st["windows"] <= st["windows_total"] and st["cells_done"] >= 1
     ref = O.mitm(inst.A, inst.d, r, st["log2_cells"], 0, st["cells_done"])
@@ -420,7 +421,42 @@ def test_first_solution_mode():
     # (8,70): the returned solutions satisfy Ax = d and lie in the full set.
     inst = make_instance(8, 70, 0, planted=True)
     full = gsolve(inst.A, inst.d, key_rows=4)
-    g = gsolve(inst.A, inst.d, key_rows=4, first_only=1, window_records=1 << 28)
-    assert 1 <= g.nsol <= full.nsol and g.H <= full.H
-    assert satisfies(inst.A, inst.d, g.solutions)
-    assert {bytes(x) for x in g.solutions} <= {bytes(x) for x in full.solutions}
+    for order in (0, 1):
+        g = gsolve(inst.A, inst.d, key_rows=4, first_only=1, first_order=order,
+                   window_records=1 << 28)
+        assert 1 <= g.nsol <= full.nsol and g.H <= full.H
+        assert satisfies(inst.A, inst.d, g.solutions)
+        assert {bytes(x) for x in g.solutions} <= {bytes(x) for x in full.solutions}
+        assert g.stats["window_order"] == (1 - order)
+
+
+def test_first_solution_density_order():
+    """First-solution mode takes the windows with the most candidate pairs
+    first.  With one key row every bucket is one key value, so a window's
+    score is its number of 1-D hits: the first window processed must be the
+    one the oracle finds with the most hits, and what it returns must be the
+    oracle's result over that window when it holds a solution."""
+    from paper_2507_05045_amd import msp
+    for m, n, seed in ((5, 40, 0), (5, 40, 3)):
+        inst = make_instance(m, n, seed, planted=True)
+        kw = dict(key_rows=1, verify_join=2, window_records=1 << 14)
+        ctx = msp.Context(inst.A, inst.d)
+        plan = ctx.plan(**kw)
+        assert plan["exact_buckets"] == 1 and plan["windows"] > 4, plan
+        ctx.solve(first_only=1, **kw)
+        g = ctx.result()
+        st = g.stats
+        ctx.close()
+        kwin, cells, lc = plan["cells_per_window"], plan["cells"], plan["log2_cells"]
+        hw = [O.mitm(inst.A, inst.d, 1, lc, w * kwin, min((w + 1) * kwin, cells)).H
+              for w in range((cells + kwin - 1) // kwin)]
+        best = max(range(len(hw)), key=lambda w: (hw[w], -w))
+        say("density order", inst.name, "windows", len(hw), "first", st["first_cell"] // kwin,
+            "best", best, "done", st["windows"])
+        assert st["window_order"] == 1 and st["first_cell"] == best * kwin
+        assert satisfies(inst.A, inst.d, g.solutions) and g.nsol >= 1
+        full = O.ss_heap(inst.A, inst.d, key_rows=1)
+        assert {bytes(x) for x in g.solutions} <= full.solution_set()
+        if st["cells_done"] == min(kwin, cells - best * kwin):      # stopped after one window
+            ref = O.mitm(inst.A, inst.d, 1, lc, best * kwin, min((best + 1) * kwin, cells))
+            same(g, ref, f"{inst.name} densest window")
