@@ -103,7 +103,7 @@ struct Sizes {
     uint64_t o_qraw[4], o_qsrt[4], o_qcnt[4], o_qcur[4], o_cnt[2], o_off[2], o_rec[2];
     uint64_t o_qvraw[4], o_qvsrt[4], o_pre[2], o_tot[2], o_wscore = 0;
     uint64_t o_runs, o_tiles, o_sol, o_scal, o_scan, scan_bytes, o_colw, o_rows;
-    uint64_t o_iruns, o_itiles, o_idx, n_iruns, o_heavy, idx_n;
+    uint64_t o_iruns, o_itiles, o_idx, n_iruns, o_heavy, o_heavy2, idx_n;
     uint64_t o_vtab, vtab_slots;
     uint64_t max_items = 0;  // largest launch of a window, work-items
 };
@@ -398,6 +398,7 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
         z.o_itiles = take((nI + 1) * 4);
         z.o_idx = take(idx_n * 4);
         z.o_heavy = take(p.exact ? 4 : kw * F * 4);
+        z.o_heavy2 = take(p.exact ? 4 : kw * F * 4);
         // Vector join table: at most half full, so every probe ends.
         z.vtab_slots = 1;
         if (p.vjoin && p.exact)
@@ -593,6 +594,7 @@ void job_carve(Job &j) {
     j.b.itiles = (uint32_t *)(ws + z.o_itiles);
     j.b.idx = (uint32_t *)(ws + z.o_idx);
     j.b.heavy = (uint32_t *)(ws + z.o_heavy);
+    j.b.heavy2 = (uint32_t *)(ws + z.o_heavy2);
     j.b.vtab = (uint32_t *)(ws + z.o_vtab);
     j.b.vtab_mask = (uint32_t)(z.vtab_slots - 1);
     j.b.iruns_cap = z.n_iruns;
@@ -733,7 +735,7 @@ int job_step(Job &j) {
             j.st.records_left += totL;
             j.st.records_right += totR;
             JCHK(hipMemsetAsync(&j.b.scal[S_NRUNS], 0, 8, j.s));
-            JCHK(hipMemsetAsync(&j.b.scal[S_NIRUNS], 0, 4 * 8, j.s));   // NIRUNS, TOT_ITILES, IDX, NHEAVY
+            JCHK(hipMemsetAsync(&j.b.scal[S_NIRUNS], 0, 5 * 8, j.s));   // NIRUNS .. NHEAVY2
             JCHK(ev_rec(j, E_S0));
             JCHK(launch_scatter(p, j.b, (int64_t)j.idx, (int32_t)j.K, j.s));
             JCHK(ev_rec(j, E_S1));

@@ -99,6 +99,7 @@ struct DevBufs {
     uint32_t *itiles;                // tile offsets of iruns (+1)
     uint32_t *idx;                   // record indices of large equal-key groups
     uint32_t *heavy;                 // buckets deferred to the heavy join
+    uint32_t *heavy2;                // ... and those the big-bucket pass defers again
     uint64_t iruns_cap, idx_cap;     // capacities of iruns and idx
     uint32_t *vtab;                  // vector join table: left record index or ~0
     uint32_t vtab_mask;              // slots - 1 (a power of two, >= 2x the left records)
@@ -114,9 +115,11 @@ struct DevBufs {
 // Slots of DevBufs::scal.
 // S_OVF is set by the count pass when one work-group enumerates 2^32 or more
 // pairs (its 32-bit bucket counters would wrap).
+// S_NHEAVY2 counts the buckets the second join pass (big-bucket groups)
+// defers to the heavy kernels.
 enum Scal {
     S_H_LO = 0, S_H_HI, S_NSOL, S_NRUNS, S_TOT_L, S_TOT_R, S_TOT_TILES, S_STORED,
-    S_NIRUNS, S_TOT_ITILES, S_IDX, S_NHEAVY, S_OVF, S_COUNT
+    S_NIRUNS, S_TOT_ITILES, S_IDX, S_NHEAVY, S_NHEAVY2, S_OVF, S_COUNT
 };
 
 // Launchers (kernels.hip).  All asynchronous on `st`.

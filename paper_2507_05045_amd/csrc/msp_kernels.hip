@@ -1102,14 +1102,14 @@ __device__ __forceinline__ uint32_t kv_hash(int64_t key, const uint32_t *v) {
 // are read only where the first matches.  NTJ threads per work-group and
 // CAP left records at most (SLOTS table entries): 256 / 1344 for buckets of
 // about a thousand records, 1024 / 4096 for buckets of a few thousand.
-template <int W, bool K32, bool VJ, int NTJ = 256, uint32_t CAP = kGroupCap,
-          uint32_t SLOTS = kGroupSlots>
-__global__ __launch_bounds__(NTJ) void k_join_grouped(Plan p, const uint32_t *__restrict__ offL,
-                                                   const uint32_t *__restrict__ offR,
-                                                   const Rec<W> *__restrict__ L,
-                                                   const Rec<W> *__restrict__ R, uint32_t *heavy,
-                                                   uint64_t *scal, uint64_t *sol, uint64_t cap,
-                                                   QPtrs<W> qs) {
+template <int W, bool K32, bool VJ, int NTJ, uint32_t CAP, uint32_t SLOTS>
+__device__ __forceinline__ void grouped_bucket(const Plan &p, const uint32_t *__restrict__ offL,
+                                               const uint32_t *__restrict__ offR,
+                                               const Rec<W> *__restrict__ L,
+                                               const Rec<W> *__restrict__ R, uint32_t *heavy,
+                                               int hslot, uint64_t *scal, uint64_t *sol,
+                                               uint64_t cap, const QPtrs<W> &qs,
+                                               const uint32_t b) {
     // s_tab[h] = (representative left index << 16) | count, then | group end.
     constexpr uint32_t kEmpty = 0xFFFF0000u;
     constexpr int WV = W > 0 ? W : 1;
@@ -1129,14 +1129,13 @@ __global__ __launch_bounds__(NTJ) void k_join_grouped(Plan p, const uint32_t *__
     __shared__ uint32_t s_w4[NW];
     __shared__ uint64_t s_s4[NW];
     __shared__ uint32_t s_gmax;
-    const uint32_t b = blockIdx.x;
     const uint32_t l0 = offL[b], l1 = offL[b + 1];
     const uint32_t r0 = offR[b], r1 = offR[b + 1];
     const uint32_t nl = l1 - l0, nr = r1 - r0;
     if (nl == 0 || nr == 0) return;                     // uniform across the block
     if (nl > kCap) {                                    // too big for LDS: heavy kernel
         if (threadIdx.x == 0)
-            heavy[atomicAdd((unsigned long long *)&scal[S_NHEAVY], 1ull)] = b;
+            heavy[atomicAdd((unsigned long long *)&scal[hslot], 1ull)] = b;
         return;
     }
     const int t = threadIdx.x;
@@ -1276,7 +1275,7 @@ __global__ __launch_bounds__(NTJ) void k_join_grouped(Plan p, const uint32_t *__
     // A left group larger than kLightGroup makes per-lane loops slow: the
     // whole bucket goes to the heavy kernel (tiled verify of big groups).
     if (s_gmax > (uint32_t)kLightGroup) {
-        if (t == 0) heavy[atomicAdd((unsigned long long *)&scal[S_NHEAVY], 1ull)] = b;
+        if (t == 0) heavy[atomicAdd((unsigned long long *)&scal[hslot], 1ull)] = b;
         return;
     }
     // Group left records by slot; afterwards the low half is the group end.
@@ -1370,6 +1369,41 @@ __global__ __launch_bounds__(NTJ) void k_join_grouped(Plan p, const uint32_t *__
     if (t == 0) add_u128(&scal[S_H_LO], &scal[S_H_HI], tot);
 }
 
+// One work-group per bucket of the window.
+template <int W, bool K32, bool VJ, int NTJ = 256, uint32_t CAP = kGroupCap,
+          uint32_t SLOTS = kGroupSlots>
+__global__ __launch_bounds__(NTJ) void k_join_grouped(Plan p, const uint32_t *__restrict__ offL,
+                                                   const uint32_t *__restrict__ offR,
+                                                   const Rec<W> *__restrict__ L,
+                                                   const Rec<W> *__restrict__ R, uint32_t *heavy,
+                                                   uint64_t *scal, uint64_t *sol, uint64_t cap,
+                                                   QPtrs<W> qs) {
+    grouped_bucket<W, K32, VJ, NTJ, CAP, SLOTS>(p, offL, offR, L, R, heavy, S_NHEAVY, scal, sol,
+                                                cap, qs, blockIdx.x);
+}
+
+// Second pass over the buckets the first deferred (list[0 .. scal[S_NHEAVY])):
+// 1024-thread groups for buckets of up to kGroupCapBig left records, which a
+// few dense keys make common when equal-key groups hold hundreds of records;
+// larger ones go on to the heavy kernels (heavy2, S_NHEAVY2).
+template <int W, bool K32, bool VJ>
+__global__ __launch_bounds__(1024) void k_join_grouped_list(Plan p,
+                                                         const uint32_t *__restrict__ offL,
+                                                         const uint32_t *__restrict__ offR,
+                                                         const Rec<W> *__restrict__ L,
+                                                         const Rec<W> *__restrict__ R,
+                                                         const uint32_t *__restrict__ list,
+                                                         uint32_t *heavy2, uint64_t *scal,
+                                                         uint64_t *sol, uint64_t cap,
+                                                         QPtrs<W> qs) {
+    const uint64_t n = scal[S_NHEAVY];
+    for (uint64_t i = blockIdx.x; i < n; i += gridDim.x) {
+        __syncthreads();                                 // the previous bucket is done with LDS
+        grouped_bucket<W, K32, VJ, 1024, kGroupCapBig, kGroupSlotsBig>(
+            p, offL, offR, L, R, heavy2, S_NHEAVY2, scal, sol, cap, qs, list[i]);
+    }
+}
+
 // Vector join of the buckets too large for k_join_grouped's LDS: left
 // chunks of kGroupCap records, each against the whole right side of the
 // bucket, with the same two LDS tables (key -> count for H, (key, rows) ->
@@ -1382,7 +1416,7 @@ __global__ __launch_bounds__(256) void k_join_heavy_vj(Plan p, const uint32_t *_
                                                       const Rec<W> *__restrict__ R,
                                                       const uint32_t *__restrict__ heavy,
                                                       uint64_t *scal, uint64_t *sol, uint64_t cap,
-                                                      QPtrs<W> qs) {
+                                                      QPtrs<W> qs, int hslot) {
     constexpr uint32_t kEmpty = 0xFFFF0000u;
     constexpr int WV = W > 0 ? W : 1;
     using KT = typename std::conditional<K32, uint32_t, int64_t>::type;
@@ -1394,7 +1428,7 @@ __global__ __launch_bounds__(256) void k_join_heavy_vj(Plan p, const uint32_t *_
     __shared__ uint32_t s_vt[kGroupSlots];               // (key, rows) -> left index
     __shared__ uint64_t s_s4[4];
     const int t = threadIdx.x;
-    const uint32_t nheavy = (uint32_t)scal[S_NHEAVY];
+    const uint32_t nheavy = (uint32_t)scal[hslot];
     uint64_t hits = 0;
     for (uint32_t hb = blockIdx.x; hb < nheavy; hb += gridDim.x) {
         const uint32_t b = heavy[hb];
@@ -1506,7 +1540,7 @@ __global__ __launch_bounds__(256) void k_join_heavy(Plan p, const uint32_t *__re
                                                    RunPair *iruns, uint32_t *idx,
                                                    uint64_t *scal, uint64_t *sol, uint64_t cap,
                                                    uint64_t iruns_cap, uint64_t idx_cap,
-                                                   QPtrs<W> qs) {
+                                                   QPtrs<W> qs, int hslot) {
     // s_tab[h] = (representative left index << 16) | count, then | group end.
     constexpr uint32_t kEmpty = 0xFFFF0000u;
     constexpr int WV = W > 0 ? W : 1;
@@ -1523,7 +1557,7 @@ __global__ __launch_bounds__(256) void k_join_heavy(Plan p, const uint32_t *__re
     __shared__ uint32_t s_w4[4];
     __shared__ uint64_t s_s4[4];
     const int t = threadIdx.x;
-    const uint32_t nheavy = (uint32_t)scal[S_NHEAVY];
+    const uint32_t nheavy = (uint32_t)scal[hslot];
     uint64_t hits = 0;
     for (uint32_t hb = blockIdx.x; hb < nheavy; hb += gridDim.x) {
     const uint32_t b = heavy[hb];
@@ -2383,19 +2417,41 @@ static hipError_t join_impl(const Plan &p, const DevBufs &b, int32_t K, uint64_t
 #undef MSP_GROUPED
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // Buckets deferred by the light join (count read on the device).
+    // Second pass over the buckets the 256-thread grouped join deferred:
+    // 1024-thread groups for those of up to kGroupCapBig left records.
+    bool second = false;
+    if constexpr (W <= 1) {
+        if ((p.vjoin || p.join_grouped == 1) && !p.gbig) {
+            second = true;
+            const dim3 g2(std::min<uint32_t>(nb, 512));
+#define MSP_LIST(K32V, VJV)                                                                      \
+    hipLaunchKernelGGL((k_join_grouped_list<W, K32V, VJV>), g2, dim3(1024), 0, st, p, b.off[0],  \
+                       b.off[1], L, R, b.heavy, b.heavy2, b.scal, b.sol, cap, sorted_quarters<W>(b))
+            if (p.vjoin && p.khb <= 32) MSP_LIST(true, true);
+            else if (p.vjoin) MSP_LIST(false, true);
+            else if (p.khb <= 32) MSP_LIST(true, false);
+            else MSP_LIST(false, false);
+#undef MSP_LIST
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+    }
+    // Buckets deferred once more go to the heavy kernels (count read on the
+    // device).
+    uint32_t *hl = second ? b.heavy2 : b.heavy;
+    const int hs = second ? (int)S_NHEAVY2 : (int)S_NHEAVY;
     if (p.vjoin && p.khb <= 32)
         hipLaunchKernelGGL((k_join_heavy_vj<W, true>), dim3(std::min<uint32_t>(nb, 2048)), dim3(256),
-                           0, st, p, b.off[0], b.off[1], L, R, b.heavy, b.scal, b.sol, cap,
-                           sorted_quarters<W>(b));
+                           0, st, p, b.off[0], b.off[1], L, R, hl, b.scal, b.sol, cap,
+                           sorted_quarters<W>(b), hs);
     else if (p.vjoin)
         hipLaunchKernelGGL((k_join_heavy_vj<W, false>), dim3(std::min<uint32_t>(nb, 2048)),
-                           dim3(256), 0, st, p, b.off[0], b.off[1], L, R, b.heavy, b.scal, b.sol,
-                           cap, sorted_quarters<W>(b));
+                           dim3(256), 0, st, p, b.off[0], b.off[1], L, R, hl, b.scal, b.sol,
+                           cap, sorted_quarters<W>(b), hs);
     else
         hipLaunchKernelGGL(k_join_heavy<W>, dim3(std::min<uint32_t>(nb, 2048)), dim3(256), 0, st,
-                           p, b.off[0], b.off[1], L, R, b.heavy, b.iruns, b.idx, b.scal, b.sol, cap,
-                           b.iruns_cap, b.idx_cap, sorted_quarters<W>(b));
+                           p, b.off[0], b.off[1], L, R, hl, b.iruns, b.idx, b.scal, b.sol, cap,
+                           b.iruns_cap, b.idx_cap, sorted_quarters<W>(b), hs);
     return hipGetLastError();
 }
 
