@@ -303,6 +303,9 @@ def main():
     ap.add_argument("--verify-join", action="store_true",
                     help="decide exact-bucket runs by the vector hash join; the metric becomes "
                          "1-D hits covered/s (pairs decided, not compared one by one)")
+    ap.add_argument("--planner-join", action="store_true",
+                    help="let the planner choose how runs are decided (the vector join for large "
+                         "equal-key groups); the metric becomes hits covered/s where it does")
     ap.add_argument("--stream-count", type=int, default=64,
                     help="instances of the uneven stream for --workload stream")
     ap.add_argument("--no-closed-loop", action="store_true",
@@ -340,7 +343,7 @@ def main():
               first_only=1 if args.first_solution else 0,
               # The timed steps check every 1-D hit pair by pair (the metric
               # is hits verified); --verify-join decides runs by the hash join.
-              verify_join=1 if args.verify_join else 2)
+              verify_join=1 if args.verify_join else 0 if args.planner_join else 2)
     # The plan (modulus, cells, parts, join variant) the autotuner picked for
     # each instance class; the planner's defaults where it has no entry.
     plans = [autotune.lookup(i.A, w["key_rows"], w.get("key_base", 0)) or {} for i in insts]
@@ -359,8 +362,10 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     all_stats = []
-    for _ in range(args.steps):
+    for k in range(args.steps):
         all_stats.append(step())
+        if args.steps > 1:
+            print(f"step {k + 1}/{args.steps}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     hits = sum(c.hits() for c in ctxs)
@@ -421,7 +426,9 @@ def main():
                 "algorithmic": "1 int32 compare per 1-D hit"}
     else:
         join_k = ("k_join_light", "k_join_grouped", "k_join_pairs")[flat[0]["join_grouped"]]
-        key = {"ms_scatter": "k_scatter_staged", "ms_join": join_k,
+        # One-word records (fingerprint or one packed word) take k_scatter_rec.
+        scat_k = "k_scatter_rec" if flat[0]["record_bytes"] <= 12 else "k_scatter_staged"
+        key = {"ms_scatter": scat_k, "ms_join": join_k,
                "ms_count": "k_count", "ms_quarters": "k_quarter_gen"}.get(dom, dom)
         bytes_per_launch = records * rec_bytes / max(windows, 1)
         avg_s = tot[dom] / 1e3 / max(windows, 1)
