@@ -73,6 +73,17 @@ WORKLOADS = {
                        desc="(9,80) seed 0 whole solve per step, key rows 1-4 (base 8000)"),
     "10_90s": dict(m=10, n=90, key_rows=4, seeds=[0], planted=False, slice_mod=64,
                    desc="(10,90) seed 0, residue slice k_L mod 64 = 0, key rows 1-4 (base 9000)"),
+    # The largest class of Section 4, (11,100): 2^50 pairs per half.  Four
+    # key rows (base 10000) need a modulus of 2^40 in the record header, so
+    # 2^28 residue cells and unequal quarters (q_A = 22, q_B = 28).
+    "11_100s": dict(m=11, n=100, key_rows=4, seeds=[0], planted=False, slice_mod=65536,
+                    desc="(11,100) seed 0, residue slice k_L mod 65536 = 0, key rows 1-4 "
+                         "(base 10000)"),
+    # Five key rows at (10,90) in the mixed radix (a 60-bit key): modulus
+    # 2^41, 2^29 residue cells, unequal quarters (q_A = 17, q_B = 28).
+    "10_90_r5s": dict(m=10, n=90, key_rows=5, key_base=1, seeds=[0], planted=False,
+                      slice_mod=512, desc="(10,90) seed 0, residue slice k_L mod 512 = 0, key "
+                                          "rows 1-5 in mixed radix rowsum+1"),
     # Coefficient range K (Section 4's classes K = 50, 100, 200): a_ij in [0, K).
     "6_50_K50": dict(m=6, n=50, key_rows=1, seeds=[0], planted=True, slice_mod=0, K=50,
                      desc="(6,50) K=50 seed 0 + planted twin, key row 1"),
@@ -137,7 +148,7 @@ def cpu_baseline(w, insts, budget_s=30.0):
                 "sample": f"{inst.name}: whole solve by the heap Schroeppel-Shamir oracle, "
                           f"H={r.H}, {dt:.2f} s", **host_cpu()}
     inst = insts[0]
-    lm = {70: 20, 80: 24, 90: 26}.get(w["n"], 20)
+    lm = {70: 20, 80: 24, 90: 26, 100: 30}.get(w["n"], 20)
     t = time.perf_counter()
     H, k = 0, 0
     while time.perf_counter() - t < budget_s and k < 64:

@@ -47,7 +47,7 @@ extern "C" {
 #define MSP_E_INVALID      (-1)  /* null pointer, m<1, n<1, a_ij<0, d_i<0, bad option */
 #define MSP_E_RANGE        (-2)  /* some row sum exceeds 65534 (uint16 row packing)    */
 #define MSP_E_KEY_OVERFLOW (-3)  /* largest key (all rows at their row sums) >= 2^63   */
-#define MSP_E_UNSUPPORTED  (-4)  /* m > 16, n > 92, m - r > 10, or > 2^24 cells needed */
+#define MSP_E_UNSUPPORTED  (-4)  /* m > 16, n > 100, m - r > 10, or > 2^29 cells needed*/
 #define MSP_E_NOMEM        (-5)  /* device workspace does not fit the budget            */
 #define MSP_E_DEVICE       (-6)  /* HIP runtime error; the context is poisoned          */
 #define MSP_E_CANCELLED    (-7)  /* solve cancelled                                     */
@@ -111,6 +111,14 @@ typedef struct {
                                  right records, from one count pass over all windows;
                                  for buckets of one key value, the window's 1-D hits),
                                  so the densest windows come first; 1 = cell order */
+    int32_t  log2_outer;      /* q_A, variables of the left outer quarter: 0 = the
+                                 planner's choice; ceil(hL / 2) (hL = ceil(n / 2)) =
+                                 equal quarters as in Algorithm 1; smaller moves
+                                 s = ceil(hL / 2) - q_A variables of each half from
+                                 its outer quarter to its inner one (same pairs,
+                                 fewer outer elements per residue cell).  Same H,
+                                 |S| and solutions                                  */
+    int32_t  reserved0;
 } msp_opts;
 
 /* Per-solve statistics; phase times are measured with HIP events on the
@@ -144,7 +152,7 @@ typedef struct {
                                  i < cells_done (k_step = 1 and k_first = 0 without a
                                  slice); all of them unless first_only stopped early */
     int32_t  window_order;    /* 1: first_only took windows in density order        */
-    int32_t  reserved1;
+    int32_t  log2_outer;      /* q_A used (msp_opts.log2_outer)                      */
     uint64_t first_cell;      /* window_order 1: index of the first cell of the first
                                  window processed (the densest)                      */
 } msp_stats_t;
@@ -258,6 +266,8 @@ typedef struct {
     int32_t  key_base;         /* key radix (msp_opts.key_base)                          */
     int32_t  infeasible;       /* 1: a key row cannot hold; no GPU work is done          */
     int32_t  row_fingerprint;  /* 1: half records carry a row fingerprint               */
+    int32_t  log2_outer;       /* q_A: variables of the left outer quarter               */
+    int32_t  log2_inner;       /* q_B: variables of the left inner quarter               */
     uint64_t cells;            /* residue cells visited (all, or those of the slice)     */
     uint64_t cells_per_window; /* planned; the count pass may halve it                   */
     uint64_t windows;          /* planned windows                                        */

@@ -19,13 +19,15 @@ typedef unsigned __int128 u128;
 #define ORC_ESIZE    (-4)
 #define ORC_ENOMEM   (-5)
 
+#define ORC_MAXN     128   /* variables per instance */
+
 /* ------------------------------------------------------------------------ */
 /* Validation and the surrogate key (Section 1, eq. surrogate).              */
 /* ------------------------------------------------------------------------ */
 
 static int validate(const int32_t *A, const int32_t *d, int m, int n, int key_rows)
 {
-    if (!A || !d || m < 1 || n < 1 || n > 96 || key_rows < 1 || key_rows > m || key_rows > 96)
+    if (!A || !d || m < 1 || n < 1 || n > ORC_MAXN || key_rows < 1 || key_rows > m)
         return ORC_EINVAL;
     for (int i = 0; i < m; ++i) {
         int64_t s = 0;
@@ -56,7 +58,7 @@ int orc_key_setup(const int32_t *A, const int32_t *d, int m, int n, int key_rows
      * is what makes the key exact.  Place values: the product of the radices
      * of the rows below.  The largest key, sum_i place_i rowsum_i, must
      * stay below 2^63. */
-    int64_t rowsum[96], place[96];
+    int64_t rowsum[ORC_MAXN], place[ORC_MAXN];
     __int128 kmax = 0, p = 1;
     *infeasible = 0;
     for (int i = 0; i < key_rows; ++i) {
@@ -122,7 +124,7 @@ int orc_brute(const int32_t *A, const int32_t *d, int m, int n, int key_rows, in
               int64_t slice_mod, int64_t slice_res, uint64_t *hr,
               uint8_t *sol, uint64_t capacity, orc_result *res)
 {
-    int64_t base, kd, w[96];
+    int64_t base, kd, w[ORC_MAXN];
     int infeasible;
     int rc = orc_key_setup(A, d, m, n, key_rows, key_base, &base, &kd, w, &infeasible);
     if (rc) return rc;
@@ -134,7 +136,7 @@ int orc_brute(const int32_t *A, const int32_t *d, int m, int n, int key_rows, in
     const int hL = half_left(n);
     int64_t sums[16] = {0};
     int64_t kleft = 0;                    /* key of x restricted to the left half */
-    uint8_t x[96] = {0};
+    uint8_t x[ORC_MAXN] = {0};
     const uint64_t total = (uint64_t)1 << n;
     /* Gray-code walk: step g flips bit ctz(g), so every x is visited once. */
     for (uint64_t g = 0; g < total; ++g) {
@@ -423,7 +425,7 @@ int orc_ss_heap(const int32_t *A, const int32_t *d, int m, int n, int key_rows, 
                 int64_t slice_mod, int64_t slice_res,
                 uint8_t *sol, uint64_t capacity, orc_result *res)
 {
-    int64_t base, kd, w[96];
+    int64_t base, kd, w[ORC_MAXN];
     int infeasible;
     int rc = orc_key_setup(A, d, m, n, key_rows, key_base, &base, &kd, w, &infeasible);
     if (rc) return rc;
@@ -568,7 +570,7 @@ int orc_mitm_residues(const int32_t *A, const int32_t *d, int m, int n,
                       int64_t slice_mod, int64_t slice_res,
                       uint8_t *sol, uint64_t capacity, orc_result *res)
 {
-    int64_t base, kd, w[96];
+    int64_t base, kd, w[ORC_MAXN];
     int infeasible;
     int rc = orc_key_setup(A, d, m, n, key_rows, key_base, &base, &kd, w, &infeasible);
     if (rc) return rc;

@@ -1,5 +1,6 @@
 """Autotuner for the solve plan: residue modulus M = 2^log2_m, residue cells
-T = 2^log2_cells and work-groups per cell (parts).
+T = 2^log2_cells, work-groups per cell (parts) and the quarter split
+(log2_outer).
 
 For an instance class (m, n, key rows r, coefficient bound) it times a few
 candidates around the planner's default on a residue slice of a
@@ -85,6 +86,7 @@ def tune(A, d, key_rows: int = 1, max_seconds: float = 20.0, slice_bits: Optiona
     base = ctx.stats()
     full_ms = base["ms_total"]
     lm, lc, parts = base["log2_m"], base["log2_cells"], base["parts"]
+    qa = base["log2_outer"]
     if slice_bits is None:
         # Aim at ~0.2 s per timed solve; the slice must stay a set of cells.
         s = 0
@@ -96,13 +98,19 @@ def tune(A, d, key_rows: int = 1, max_seconds: float = 20.0, slice_bits: Optiona
     for dm in ((0,) if base["exact_buckets"] else (0, -1, 1)):
         for dc in (0, -1, 1):
             m2, c2 = lm + dm, lc + dc
-            if c2 < max(slice_bits, 0) or c2 > m2 or m2 - c2 > 12 or c2 > 23 or m2 < 1:
+            if c2 < max(slice_bits, 0) or c2 > m2 or m2 - c2 > 12 or c2 > 29 or m2 < 1:
                 continue
             # multiples of 8 let the kernels map whole parts to each XCD
             for p2 in sorted({parts, parts * 2, parts * 4, 16, 32, 64}):
                 for jv in ((0,) if base["exact_buckets"] else (1, 2, 3)):
                     cands.append(dict(log2_m=m2, log2_cells=c2, parts=min(p2, 256),
                                       join_variant=jv))
+            # One or two variables moved to the inner quarters: more cells
+            # for the same outer re-reads.
+            for q2 in (qa - 1, qa - 2):
+                if q2 >= 1 and dc >= 0:
+                    cands.append(dict(log2_m=m2, log2_cells=c2, parts=parts, join_variant=0,
+                                      log2_outer=q2))
     t_end = time.time() + max_seconds
     best, best_t, ref_h = None, float("inf"), None
     for c in cands:
@@ -129,7 +137,8 @@ def tune(A, d, key_rows: int = 1, max_seconds: float = 20.0, slice_bits: Optiona
             best, best_t = c, dt
     ctx.close()
     if best is None:
-        best = dict(log2_m=lm, log2_cells=lc, parts=parts, join_variant=0)   # planner's choice
+        best = dict(log2_m=lm, log2_cells=lc, parts=parts, join_variant=0,
+                    log2_outer=qa)                                     # planner's choice
     cache = _load()
     cache[key] = {"opts": best, "slice_bits": slice_bits, "ms_slice": best_t * 1e3,
                   "default": dict(log2_m=lm, log2_cells=lc, parts=parts)}

@@ -119,7 +119,7 @@ struct Prepared {
 // Instance-level checks shared by msp_create and the plan.
 int validate(const int32_t *A, const int32_t *d, int m, int n) {
     if (!A || !d || m < 1 || n < 1) return MSP_E_INVALID;
-    if (m > 16 || n > 92) return MSP_E_UNSUPPORTED;
+    if (m > 16 || n > kMaxN) return MSP_E_UNSUPPORTED;
     for (int i = 0; i < m; ++i) {
         if (d[i] < 0) return MSP_E_INVALID;
         int64_t s = 0;
@@ -169,6 +169,11 @@ double expected_group_lg2(const msp_ctx *c, const Plan &p) {
 
 // The plan: surrogate key (Section 1, eq. surrogate), quarter widths
 // (Algorithm 1's partition, contiguous), residue modulus, cells, windows.
+// Widest inner quarter: 2^28 subsets (4 GiB of quarter records at most);
+// at most 2^29 residue cells (cell tables of 2 GiB per quarter and copy).
+constexpr int kMaxQuarterBits = 28;
+constexpr int kMaxCellBits = 29;
+
 int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
     Plan &p = P.p;
     const int m = c->m, n = c->n;
@@ -178,12 +183,25 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
     if (o.slice_mod < 0 || (o.slice_mod > 0 && ((o.slice_mod & (o.slice_mod - 1)) != 0 ||
                                                 o.slice_res < 0 || o.slice_res >= o.slice_mod)))
         return MSP_E_INVALID;
-    if (o.log2_m < 0 || o.log2_m > 62 || o.log2_cells < 0 || o.log2_cells > 24 || o.parts < 0)
+    if (o.log2_m < 0 || o.log2_m > 62 || o.log2_cells < 0 || o.log2_cells > kMaxCellBits ||
+        o.parts < 0)
         return MSP_E_INVALID;
     p.m = m; p.n = n; p.r = r; p.nv = m - r; p.W = (p.nv + 1) / 2;
     p.hL = (n + 1) / 2;
-    p.qa = (p.hL + 1) / 2; p.qb = p.hL / 2;
-    p.qc = (n - p.hL + 1) / 2; p.qd = (n - p.hL) / 2;
+    // Quarters: Algorithm 1 splits each half into two lists of equal size.
+    // log2_outer = q_A < ceil(hL / 2) moves s = ceil(hL / 2) - q_A variables
+    // of each half from its outer quarter (A, C) to its inner one (B, D):
+    // the same pairs, fewer outer elements per residue cell, so more cells
+    // (and fewer fine buckets per cell) cost the same outer re-reads.
+    {
+        const int qa0 = (p.hL + 1) / 2;
+        if (o.log2_outer < 0 || o.log2_outer > qa0) return MSP_E_INVALID;
+        const int s = o.log2_outer ? qa0 - o.log2_outer : 0;
+        p.qa = qa0 - s; p.qb = p.hL - p.qa;
+        p.qc = (n - p.hL + 1) / 2 - s; p.qd = (n - p.hL) - p.qc;
+        if (p.qa < 1 || p.qc < 1) return MSP_E_INVALID;
+        if (p.qb > kMaxQuarterBits || p.qd > kMaxQuarterBits) return MSP_E_UNSUPPORTED;
+    }
     p.Q[0] = 1u << p.qa; p.Q[1] = 1u << p.qb; p.Q[2] = 1u << p.qc; p.Q[3] = 1u << p.qd;
 
     // Key (Section 1, eq. surrogate): digit i is the row sum a_i.x, radix
@@ -276,7 +294,20 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
     }
     log2T = std::min(log2T, log2M);
     if (log2M - log2T > 12) return MSP_E_INVALID;       // fine buckets per cell <= 4096
-    if (log2T > 24) return MSP_E_UNSUPPORTED;
+    if (log2T > kMaxCellBits) return MSP_E_UNSUPPORTED;
+    // More cells than the equal quarters have inner elements (a modulus
+    // forced up by the key room: n near 100, five key rows at n = 90): the
+    // planner moves variables to the inner quarters until a cell holds about
+    // one inner element, so the outer quarter is not re-read for every one or
+    // two records (measured at (10,90), four key rows: 2^23 cells, q_B 22 ->
+    // 23, count and scatter 3.2 -> 2.2 s per 1/512 slice).
+    if (!o.log2_outer && log2T > p.qb) {
+        const int s = std::min({log2T - p.qb, kMaxQuarterBits - p.qb, p.qc - 1, p.qa - 1});
+        if (s > 0) {
+            p.qa -= s; p.qb += s; p.qc -= s; p.qd += s;
+            p.Q[0] = 1u << p.qa; p.Q[1] = 1u << p.qb; p.Q[2] = 1u << p.qc; p.Q[3] = 1u << p.qd;
+        }
+    }
     p.log2M = log2M; p.log2T = log2T; p.log2F = log2M - log2T;
     p.khb = std::max(0, lgKd - log2M);
     p.slice_mod = o.slice_mod;
@@ -896,6 +927,7 @@ void job_init_stats(Job &j) {
     j.st.words = p.W;
     j.st.record_bytes = rec_bytes(p.Wr);
     j.st.row_fingerprint = p.fp;
+    j.st.log2_outer = p.qa;
     j.st.vector_join = p.vjoin;
     j.st.join_grouped = p.exact ? 0 : p.join_grouped;
     j.st.key_base = j.o.key_base;
@@ -1250,6 +1282,8 @@ int msp_plan(const msp_ctx *c, const msp_opts *opts, msp_plan_t *out) {
     t.window_records = z.cap_rec;
     t.record_bytes = rec_bytes(p.Wr);
     t.row_fingerprint = p.fp;
+    t.log2_outer = p.qa;
+    t.log2_inner = p.qb;
     t.workspace_bytes = z.total;
     t.max_grid_items = z.max_items;
     *out = t;

@@ -8,6 +8,7 @@
 namespace msp {
 
 constexpr int kMaxWords = 5;        // packed uint16 non-key rows: up to 10 rows
+constexpr int kMaxN = 100;          // variables per instance (two halves of <= 50)
 constexpr int kMaxFine = 4096;      // fine buckets per residue cell (LDS counters)
 constexpr int kJoinCap = 1536;      // left records per bucket held in LDS by the join
 constexpr int kJoinSlots = 4096;    // LDS hash slots of the join (power of two)

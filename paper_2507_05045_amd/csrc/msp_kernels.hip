@@ -131,8 +131,8 @@ template <int W>
 __global__ __launch_bounds__(256) void k_quarter_gen(Plan p, const int64_t *__restrict__ colw,
                                                      const uint16_t *__restrict__ rows,
                                                      QPtrs<W> out, UPtrs cnt, UPtrs qvec) {
-    __shared__ int64_t s_w[96];
-    __shared__ uint16_t s_rows[kMaxWords * 2 * 96];
+    __shared__ int64_t s_w[kMaxN];
+    __shared__ uint16_t s_rows[kMaxWords * 2 * kMaxN];
     for (int i = threadIdx.x; i < p.n; i += blockDim.x) s_w[i] = colw[i];
     for (int i = threadIdx.x; i < p.nv * p.n; i += blockDim.x) s_rows[i] = rows[i];
     __syncthreads();

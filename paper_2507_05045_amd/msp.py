@@ -39,7 +39,8 @@ class msp_opts(C.Structure):
                 ("workspace", C.c_void_p), ("workspace_bytes", C.c_uint64),
                 ("stream", C.c_void_p), ("first_only", C.c_int32), ("join_variant", C.c_int32),
                 ("verify_join", C.c_int32), ("key_base", C.c_int32),
-                ("row_fingerprint", C.c_int32), ("first_order", C.c_int32)]
+                ("row_fingerprint", C.c_int32), ("first_order", C.c_int32),
+                ("log2_outer", C.c_int32), ("reserved0", C.c_int32)]
 
 
 class msp_stats_t(C.Structure):
@@ -53,7 +54,7 @@ class msp_stats_t(C.Structure):
                 ("words", C.c_int32), ("complete", C.c_int32), ("vector_join", C.c_int32),
                 ("windows_total", C.c_uint64), ("join_grouped", C.c_int32),
                 ("key_base", C.c_int32), ("row_fingerprint", C.c_int32),
-                ("cells_done", C.c_uint64), ("window_order", C.c_int32), ("reserved1", C.c_int32),
+                ("cells_done", C.c_uint64), ("window_order", C.c_int32), ("log2_outer", C.c_int32),
                 ("first_cell", C.c_uint64)]
 
 
@@ -66,6 +67,7 @@ class msp_plan_t(C.Structure):
                 ("log2_fine", C.c_int32), ("parts", C.c_int32), ("exact_buckets", C.c_int32),
                 ("words", C.c_int32), ("join_variant", C.c_int32), ("vector_join", C.c_int32),
                 ("key_base", C.c_int32), ("infeasible", C.c_int32), ("row_fingerprint", C.c_int32),
+                ("log2_outer", C.c_int32), ("log2_inner", C.c_int32),
                 ("cells", C.c_uint64), ("cells_per_window", C.c_uint64), ("windows", C.c_uint64),
                 ("window_records", C.c_uint64), ("record_bytes", C.c_uint64),
                 ("workspace_bytes", C.c_uint64), ("max_grid_items", C.c_uint64)]

@@ -2,7 +2,9 @@
 workloads, computed only by the CPU oracle (oracle/).  Run from the repo
 root:  python tests/golden/make_golden.py
 With --batch it writes tests/golden/oracle_batch.json instead: the instances
-of the batched and served tests, solved whole by the heap oracle.
+of the batched and served tests, solved whole by the heap oracle.  With
+--wide, tests/golden/oracle_wide.json: sampled classes of (11,100) and of
+(10,90) with five key rows.
 
 Small workloads are solved whole with the heap Schroeppel-Shamir oracle;
 the large ones are sampled: the meet-in-the-middle oracle solves single
@@ -167,8 +169,42 @@ def batch_main():
     print("wrote", path, f"{time.time() - t0:.1f}s")
 
 
+def _wide_job(job):
+    (m, n), K, planted, r, kb, lm, rho = job
+    inst = make_instance(m, n, 0, planted=planted, K=K)
+    if planted:
+        rho = O.left_key(inst.A, inst.d, inst.planted, r, key_base=kb) % (1 << lm)
+    res = O.mitm(inst.A, inst.d, r, lm, rho, rho + 1, key_base=kb)
+    return entry(inst, r, res, 1 << lm, rho, routine=f"mitm mod 2^{lm}", K=K, key_base=kb)
+
+
+def wide_main():
+    """tests/golden/oracle_wide.json: residue classes of the plans whose
+    modulus the key room forces up (more cells than equal quarters have
+    inner elements): (11,100) with four key rows (Section 4's largest
+    class, K = 100 and K = 50), and (10,90) with five key rows in the mixed
+    radix.  Planted twins sample the class of x*."""
+    import multiprocessing as mp
+    jobs = [((11, 100), 100, False, 4, 0, 30, 12345),
+            ((11, 100), 100, True, 4, 0, 30, None),
+            ((11, 100), 50, False, 4, 0, 30, 777),
+            ((10, 90), 100, False, 5, 1, 24, 12345),
+            ((10, 90), 100, True, 5, 1, 24, None)]
+    t0 = time.time()
+    with mp.get_context("fork").Pool(2) as pool:
+        out = pool.map(_wide_job, jobs)
+    for e in out:
+        print(e["name"], e["slice_res"], e["H"], e["nsol"], flush=True)
+    path = os.path.join(os.path.dirname(OUT), "oracle_wide.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print("wrote", path, f"{time.time() - t0:.1f}s")
+
+
 if __name__ == "__main__":
     if sys.argv[1:] == ["--batch"]:
         batch_main()
+    elif sys.argv[1:] == ["--wide"]:
+        wide_main()
     else:
         main()

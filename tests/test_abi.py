@@ -39,7 +39,7 @@ def test_create_validates():
         msp.Context(np.full((1, 3), 30000), [1])
     assert e.value.code == -2
     with pytest.raises(msp.MspError) as e:
-        msp.Context(np.ones((2, 93)), [1, 1])
+        msp.Context(np.ones((2, 101)), [1, 1])
     assert e.value.code == -4
     ctx = msp.Context(np.ones((2, 5)), [2, 2])
     with pytest.raises(msp.MspError) as e:
@@ -143,6 +143,9 @@ LARGE_PLANS = [
     ((10, 90), dict(key_rows=4, slice_mod=64, verify_join=1)),
     ((6, 50), dict(key_rows=1)),
     ((6, 50), dict(key_rows=1, verify_join=2)),
+    ((11, 100), dict(key_rows=4, slice_mod=4096)),
+    ((11, 100), dict(key_rows=4)),
+    ((10, 90), dict(key_rows=5, key_base=1, slice_mod=64)),
 ]
 
 
@@ -188,3 +191,39 @@ def test_set_allocator_rejects_half_a_pair():
     a = msp.ALLOC_FN(lambda n, u: None)
     assert msp.lib.msp_set_allocator(a, msp.RELEASE_FN(), None) == -1
     assert msp.lib.msp_set_allocator(msp.ALLOC_FN(), msp.RELEASE_FN(), None) == 0
+
+
+def test_quarter_split_plans():
+    """log2_outer moves variables from each half's outer quarter to its
+    inner one; the planner does so itself when the key room forces more
+    residue cells than the equal quarters have inner elements."""
+    from paper_2507_05045_amd import msp
+    from paper_2507_05045_amd.inputs import make_instance
+    i = make_instance(9, 80, 0)
+    ctx = msp.Context(i.A, i.d)
+    p = ctx.plan(key_rows=4)
+    assert (p["log2_outer"], p["log2_inner"]) == (20, 20)
+    p = ctx.plan(key_rows=4, log2_outer=18, log2_m=30, log2_cells=21)
+    assert (p["log2_outer"], p["log2_inner"], p["log2_fine"]) == (18, 22, 9)
+    for bad in (21, -1):
+        with pytest.raises(msp.MspError) as e:
+            ctx.plan(key_rows=4, log2_outer=bad)
+        assert e.value.code == -1
+    with pytest.raises(msp.MspError) as e:
+        ctx.plan(key_rows=4, log2_cells=30)
+    assert e.value.code == -1
+    ctx.close()
+    # (11,100), four key rows: 50 position bits leave 14 key bits in a
+    # record header, so M = 2^40, 2^28 cells and q_B = 28.
+    i = make_instance(11, 100, 0)
+    ctx = msp.Context(i.A, i.d)
+    p = ctx.plan(key_rows=4, slice_mod=4096)
+    assert (p["log2_m"], p["log2_cells"], p["log2_outer"], p["log2_inner"]) == (40, 28, 22, 28)
+    ctx.close()
+    # (10,90), five key rows in the mixed radix: a 60-bit key, 19 key bits
+    # per header, M = 2^41, 2^29 cells.
+    i = make_instance(10, 90, 0)
+    ctx = msp.Context(i.A, i.d)
+    p = ctx.plan(key_rows=5, key_base=1)
+    assert (p["log2_m"], p["log2_cells"], p["log2_outer"], p["log2_inner"]) == (41, 29, 17, 28)
+    ctx.close()

@@ -460,3 +460,82 @@ def test_first_solution_density_order():
         if st["cells_done"] == min(kwin, cells - best * kwin):      # stopped after one window
             ref = O.mitm(inst.A, inst.d, 1, lc, best * kwin, min((best + 1) * kwin, cells))
             same(g, ref, f"{inst.name} densest window")
+
+
+WIDE_GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                           "oracle_wide.json")
+
+
+def test_quarter_split_vs_oracle():
+    """Unequal quarters (log2_outer below the balanced q_A) give the oracle's
+    result: the (6,50) pair solved whole with one and five key rows, and the
+    multi-cell (8,70) slice with the shipped plan's modulus and more cells."""
+    from paper_2507_05045_amd import autotune
+    for e in _golden():
+        if (e["m"], e["n"], e.get("K", 100)) == (6, 50, 100):
+            inst = _golden_instance(e)
+            r, kb = e["key_rows"], e.get("key_base", 0)
+            for lo in (12, 10, 8):
+                for vj in (0, 2):
+                    g = gsolve(inst.A, inst.d, key_rows=r, key_base=kb, log2_outer=lo,
+                               verify_join=vj)
+                    say("split", e["name"], r, lo, vj, g.stats["log2_cells"])
+                    assert g.stats["log2_outer"] == lo
+                    same(g, _golden_result(e, 50), f"{e['name']} r={r} q_A={lo} vj={vj}")
+        elif (e["m"], e["n"], e["slice_mod"]) == (8, 70, 256):
+            inst = _golden_instance(e)
+            plan = dict(autotune.lookup(inst.A, 4) or {})
+            plan.pop("log2_outer", None)
+            for lo, dc in ((17, 1), (16, 2), (15, 2)):
+                kw = dict(plan, log2_cells=plan.get("log2_cells", 15) + dc)
+                kw["log2_m"] = max(kw.get("log2_m", 0), kw["log2_cells"])
+                g = gsolve(inst.A, inst.d, key_rows=4, slice_mod=256, slice_res=e["slice_res"],
+                           log2_outer=lo, **kw)
+                say("split", e["name"], lo, kw, g.stats["windows"])
+                same(g, _golden_result(e, 70), f"{e['name']} q_A={lo} {kw}")
+
+
+def test_more_cells_than_2_24_vs_oracle():
+    """2^25 - 2^27 residue cells (cell indices past 2^24) on (6,50) with two
+    key rows, inner quarters of 2^19 - 2^21 subsets: a residue slice against
+    the MITM oracle."""
+    for planted in (False, True):
+        inst = make_instance(6, 50, 0, planted=planted)
+        rho = O.left_key(inst.A, inst.d, inst.planted, 2) % 4096 if planted else 77
+        ref = O.mitm(inst.A, inst.d, 2, 12, rho, rho + 1)
+        for lc, lo in ((25, 6), (27, 4)):
+            g = gsolve(inst.A, inst.d, key_rows=2, log2_m=lc + 10, log2_cells=lc, log2_outer=lo,
+                       slice_mod=4096, slice_res=rho)
+            say("cells", inst.name, lc, lo, g.H, ref.H, g.stats["windows"])
+            assert g.stats["log2_cells"] == lc and g.stats["log2_outer"] == lo
+            same(g, ref, f"{inst.name} 2^{lc} cells q_A={lo}")
+            if planted:
+                assert any(np.array_equal(s, inst.planted) for s in g.solutions)
+
+
+def test_forced_modulus_plans_sampled_classes():
+    """(11,100) with four key rows and (10,90) with five (mixed radix): the
+    key room forces a modulus of 2^40 - 2^41, hence 2^28 - 2^29 cells and
+    unequal quarters.  Sampled residue classes against the MITM oracle
+    (tests/golden/oracle_wide.json), with the planner's plan."""
+    from paper_2507_05045_amd import msp
+    with open(WIDE_GOLDEN) as f:
+        gold = json.load(f)
+    assert len(gold) == 5
+    for e in gold:
+        inst = make_instance(e["m"], e["n"], e["seed"], planted=e["planted"], K=e["K"])
+        assert inst.name == e["name"]
+        r, kb = e["key_rows"], e["key_base"]
+        ctx = msp.Context(inst.A, inst.d)
+        plan = ctx.plan(key_rows=r, key_base=kb)
+        assert plan["log2_cells"] >= 28 and plan["log2_outer"] < plan["log2_inner"], plan
+        for vj in ((0, 2) if r == 4 else (0,)):
+            ctx.solve(key_rows=r, key_base=kb, slice_mod=e["slice_mod"],
+                      slice_res=e["slice_res"], verify_join=vj)
+            st = ctx.stats()
+            say("forced", e["name"], r, e["slice_res"], vj, ctx.hits(), e["H"],
+                st["log2_m"], st["log2_cells"], st["log2_outer"], st["ms_total"])
+            same(ctx.result(), _golden_result(e, e["n"]), f"{e['name']} r={r} vj={vj}")
+            if inst.planted is not None:
+                assert any(np.array_equal(s, inst.planted) for s in ctx.solutions())
+        ctx.close()
