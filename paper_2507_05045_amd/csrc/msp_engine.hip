@@ -199,7 +199,7 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
         const int s = o.log2_outer ? qa0 - o.log2_outer : 0;
         p.qa = qa0 - s; p.qb = p.hL - p.qa;
         p.qc = (n - p.hL + 1) / 2 - s; p.qd = (n - p.hL) - p.qc;
-        if (p.qa < 1 || p.qc < 1) return MSP_E_INVALID;
+        if (p.qa < 0 || p.qc < 0) return MSP_E_INVALID;
         if (p.qb > kMaxQuarterBits || p.qd > kMaxQuarterBits) return MSP_E_UNSUPPORTED;
     }
     p.Q[0] = 1u << p.qa; p.Q[1] = 1u << p.qb; p.Q[2] = 1u << p.qc; p.Q[3] = 1u << p.qd;

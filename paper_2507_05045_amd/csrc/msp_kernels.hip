@@ -540,6 +540,37 @@ __device__ __forceinline__ void scatter_rec_body(
     const int64_t smod1 = p.slice_mod - 1, sres = p.slice_res, Kd = p.Kd;
     const int qa = p.qa, hsh = p.hsh, lm = p.log2M, lt = p.log2T;
     const uint32_t hd = p.hd, dp0 = p.dpk[0];
+    // Sort the nb staged records by fine bucket and store each bucket's run
+    // at its cursor.  Staged slots past nb are stale and never read.
+    auto flush = [&](uint32_t nb) {
+        for (int f = t; f < Fs; f += NT) s_cnt[f] = 0;
+        __syncthreads();                          // staging and zeroing done
+        for (uint32_t o = t; o < nb; o += NT)
+            if (s_f[o] != 0xFFFF) atomicAdd(&s_cnt[s_f[o]], 1u);
+        __syncthreads();
+        const uint32_t nvalid = block_excl_scan_rt<uint32_t, NT>(s_cnt, Fs, s_w4);
+        // Rank within the batch; afterwards s_cnt[f] = end of group f.
+        for (uint32_t o = t; o < nb; o += NT) {
+            const uint32_t f = s_f[o];
+            if (f != 0xFFFF) s_perm[atomicAdd(&s_cnt[f], 1u)] = (uint16_t)o;
+        }
+        __syncthreads();
+        for (uint32_t o = t; o < nvalid; o += NT) {
+            const uint32_t slot = s_perm[o];
+            const uint32_t f = s_f[slot];
+            const uint32_t start = f ? s_cnt[f - 1] : 0u;
+            Rec<W> r;
+            r.hdr = s_hdr[slot];
+            r.vec[0] = s_wd[slot];
+            rec[s_cur[f] + (o - start)] = r;
+        }
+        __syncthreads();
+        for (int f = t; f < F; f += NT) s_cur[f] += s_cnt[f] - (f ? s_cnt[f - 1] : 0u);
+        __syncthreads();
+    };
+    // Records are staged across chunks until a batch is full, so chunks of
+    // few pairs (cells that hold about one inner element) share one sort.
+    uint32_t fill = 0;
     for (uint64_t c0 = lo; c0 < hi; c0 += (uint64_t)NT * PER) {
         // This thread's outer elements (PER of them, NT apart so that a wave
         // reads consecutive records) and the offsets of their pairs in the
@@ -576,10 +607,14 @@ __device__ __forceinline__ void scatter_rec_body(
             if (w < (t >> 6)) myoff += s_w4[w];
             total += s_w4[w];
         }
-        for (uint32_t P0 = 0; P0 < total; P0 += BATCH) {
-            const uint32_t nb = min((uint32_t)BATCH, total - P0);
-            for (int f = t; f < Fs; f += NT) s_cnt[f] = 0;
-            // Stage my pairs whose index falls in [P0, P0 + nb), records whole.
+        if (fill > 0 && fill + total > (uint32_t)BATCH) {   // block-uniform
+            flush(fill);
+            fill = 0;
+        }
+        for (uint32_t P0 = 0; P0 < total;) {
+            const uint32_t nb = min((uint32_t)BATCH - fill, total - P0);
+            // Stage my pairs whose index falls in [P0, P0 + nb), records
+            // whole, at slots fill + (index - P0).
             uint32_t off = myoff;
 #pragma unroll
             for (int e = 0; e < PER; ++e) {
@@ -594,7 +629,7 @@ __device__ __forceinline__ void scatter_rec_body(
                     const int64_t key = SIDE ? akey[e] - bk : akey[e] + bk;
                     bool keep = SIDE ? key >= 0 : key <= Kd;
                     if (SLICE) keep = keep && ((key & smod1) == sres);
-                    const uint32_t o = off + q - P0;
+                    const uint32_t o = fill + off + q - P0;
                     s_hdr[o] = ai | (qi << qa) | ((uint64_t)(key >> lm) << hsh);
                     uint32_t wd;
                     if (FP) wd = SIDE ? hd - aw[e] - bw : aw[e] + bw;
@@ -605,31 +640,15 @@ __device__ __forceinline__ void scatter_rec_body(
                 }
                 off += n;
             }
-            __syncthreads();
-            for (uint32_t o = t; o < nb; o += NT)
-                if (s_f[o] != 0xFFFF) atomicAdd(&s_cnt[s_f[o]], 1u);
-            __syncthreads();
-            const uint32_t nvalid = block_excl_scan_rt<uint32_t, NT>(s_cnt, Fs, s_w4);
-            // Rank within the batch; afterwards s_cnt[f] = end of group f.
-            for (uint32_t o = t; o < nb; o += NT) {
-                const uint32_t f = s_f[o];
-                if (f != 0xFFFF) s_perm[atomicAdd(&s_cnt[f], 1u)] = (uint16_t)o;
+            fill += nb;
+            P0 += nb;
+            if (fill == (uint32_t)BATCH) {
+                flush(fill);
+                fill = 0;
             }
-            __syncthreads();
-            for (uint32_t o = t; o < nvalid; o += NT) {
-                const uint32_t slot = s_perm[o];
-                const uint32_t f = s_f[slot];
-                const uint32_t start = f ? s_cnt[f - 1] : 0u;
-                Rec<W> r;
-                r.hdr = s_hdr[slot];
-                r.vec[0] = s_wd[slot];
-                rec[s_cur[f] + (o - start)] = r;
-            }
-            __syncthreads();
-            for (int f = t; f < F; f += NT) s_cur[f] += s_cnt[f] - (f ? s_cnt[f - 1] : 0u);
-            __syncthreads();
         }
     }
+    if (fill > 0) flush(fill);
 }
 
 template <int W, int PER, int MAXF, bool FP, bool SLICE>

@@ -227,3 +227,13 @@ def test_quarter_split_plans():
     p = ctx.plan(key_rows=5, key_base=1)
     assert (p["log2_m"], p["log2_cells"], p["log2_outer"], p["log2_inner"]) == (41, 29, 17, 28)
     ctx.close()
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5])
+def test_tiny_instances_plan(n):
+    """Halves of one variable leave an empty right quarter (one subset)."""
+    from paper_2507_05045_amd import msp
+    ctx = msp.Context(np.ones((2, n)), [1, 1])
+    p = ctx.plan(key_rows=1)
+    assert p["log2_outer"] + p["log2_inner"] == (n + 1) // 2 and p["workspace_bytes"] > 0
+    ctx.close()
