@@ -52,7 +52,10 @@ def measured_traffic(workload: str, kernel: str):
     except (OSError, ValueError):
         return None
     e = t.get("workloads", {}).get(workload)
-    if not e or e.get("kernel") != kernel or t.get("kernel_sources_sha256") != kernel_sources_sha256():
+    if not e or t.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return None
+    e = e.get("kernels", {}).get(kernel)
+    if not e:
         return None
     cal = t["calibration"]
     return (e["fetch_kib_per_launch"] * cal["FETCH_SIZE"]
