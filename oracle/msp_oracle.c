@@ -41,8 +41,14 @@ static int validate(const int32_t *A, const int32_t *d, int m, int n, int key_ro
     return 0;
 }
 
-int orc_key_setup(const int32_t *A, const int32_t *d, int m, int n, int key_rows,
-                  int key_base, int64_t *base, int64_t *kd, int64_t *w, int *infeasible)
+/* The key's place values, K_d and the column weights w_j.  With wide != NULL
+ * a key past int64 is allowed: every value is then kept modulo 2^64 (the
+ * bit pattern in an int64), which is exact for residues modulo 2^k, and
+ * *wide = 1; equality of two such keys is decided on the key rows' sums
+ * instead (see orc_mitm_residues).  wide == NULL: overflow is ORC_EKEY. */
+static int key_setup_impl(const int32_t *A, const int32_t *d, int m, int n, int key_rows,
+                          int key_base, int64_t *base, int64_t *kd, int64_t *w, int *infeasible,
+                          int *wide)
 {
     int rc = validate(A, d, m, n, key_rows);
     if (rc) return rc;
@@ -58,30 +64,53 @@ int orc_key_setup(const int32_t *A, const int32_t *d, int m, int n, int key_rows
      * is what makes the key exact.  Place values: the product of the radices
      * of the rows below.  The largest key, sum_i place_i rowsum_i, must
      * stay below 2^63. */
-    int64_t rowsum[ORC_MAXN], place[ORC_MAXN];
-    __int128 kmax = 0, p = 1;
+    int64_t rowsum[ORC_MAXN];
+    uint64_t place[ORC_MAXN];                  /* modulo 2^64 */
+    unsigned __int128 kmax = 0, p = 1;
+    int over = 0;                               /* the key does not fit int64 */
     *infeasible = 0;
     for (int i = 0; i < key_rows; ++i) {
         rowsum[i] = 0;
         for (int j = 0; j < n; ++j) rowsum[i] += A[(size_t)i * n + j];
         if (d[i] > rowsum[i]) *infeasible = 1;     /* row i can never hold */
-        place[i] = (int64_t)p;
-        kmax += p * rowsum[i];
-        if (kmax >= ((__int128)1 << 63)) return ORC_EKEY;
-        p *= key_base ? rowsum[i] + 1 : B;
-        if (i + 1 < key_rows && p >= ((__int128)1 << 63)) return ORC_EKEY;
+        place[i] = (uint64_t)p;
+        if (!over) {
+            kmax += p * (unsigned __int128)rowsum[i];
+            if (kmax >= ((unsigned __int128)1 << 63)) over = 1;
+        }
+        if (!over) {
+            p *= (unsigned __int128)(key_base ? rowsum[i] + 1 : B);
+            if (i + 1 < key_rows && p >= ((unsigned __int128)1 << 63)) over = 1;
+        } else {
+            p = (uint64_t)p * (uint64_t)(key_base ? rowsum[i] + 1 : B);
+        }
     }
-    int64_t k = 0;
+    if (over && !wide) return ORC_EKEY;
+    if (wide) *wide = over;
+    uint64_t k = 0;
     for (int i = 0; i < key_rows; ++i)
-        if (!*infeasible) k += place[i] * (int64_t)d[i];
+        if (!*infeasible) k += place[i] * (uint64_t)d[i];
     for (int j = 0; j < n; ++j) {
-        int64_t s = 0;
-        for (int i = 0; i < key_rows; ++i) s += place[i] * (int64_t)A[(size_t)i * n + j];
-        w[j] = s;
+        uint64_t s = 0;
+        for (int i = 0; i < key_rows; ++i) s += place[i] * (uint64_t)A[(size_t)i * n + j];
+        w[j] = (int64_t)s;
     }
     *base = key_base ? rowsum[0] + 1 : B;
-    *kd = *infeasible ? -1 : k;
+    *kd = *infeasible ? -1 : (int64_t)k;
     return 0;
+}
+
+int orc_key_setup(const int32_t *A, const int32_t *d, int m, int n, int key_rows,
+                  int key_base, int64_t *base, int64_t *kd, int64_t *w, int *infeasible)
+{
+    return key_setup_impl(A, d, m, n, key_rows, key_base, base, kd, w, infeasible, NULL);
+}
+
+int orc_key_setup_wide(const int32_t *A, const int32_t *d, int m, int n, int key_rows,
+                       int key_base, int64_t *base, int64_t *kd, int64_t *w, int *infeasible,
+                       int *wide)
+{
+    return key_setup_impl(A, d, m, n, key_rows, key_base, base, kd, w, infeasible, wide);
 }
 
 static int64_t pos_mod(int64_t x, int64_t mod)
@@ -125,17 +154,19 @@ int orc_brute(const int32_t *A, const int32_t *d, int m, int n, int key_rows, in
               uint8_t *sol, uint64_t capacity, orc_result *res)
 {
     int64_t base, kd, w[ORC_MAXN];
-    int infeasible;
-    int rc = orc_key_setup(A, d, m, n, key_rows, key_base, &base, &kd, w, &infeasible);
+    int infeasible, wide;
+    int rc = key_setup_impl(A, d, m, n, key_rows, key_base, &base, &kd, w, &infeasible, &wide);
     if (rc) return rc;
     if (n > 30) return ORC_ESIZE;
     if (slice_mod < 0 || (slice_mod > 0 && (slice_res < 0 || slice_res >= slice_mod)))
         return ORC_EINVAL;
+    /* A key past int64 is known modulo 2^64 only: slices by powers of two. */
+    if (wide && slice_mod > 0 && (slice_mod & (slice_mod - 1))) return ORC_EINVAL;
     memset(res, 0, sizeof *res);
     for (int i = 0; i < m; ++i) hr[i] = 0;
     const int hL = half_left(n);
     int64_t sums[16] = {0};
-    int64_t kleft = 0;                    /* key of x restricted to the left half */
+    uint64_t kleft = 0;                   /* key of x restricted to the left half, mod 2^64 */
     uint8_t x[ORC_MAXN] = {0};
     const uint64_t total = (uint64_t)1 << n;
     /* Gray-code walk: step g flips bit ctz(g), so every x is visited once. */
@@ -145,9 +176,11 @@ int orc_brute(const int32_t *A, const int32_t *d, int m, int n, int key_rows, in
             int sgn = x[j] ? -1 : 1;
             x[j] ^= 1u;
             for (int i = 0; i < m; ++i) sums[i] += sgn * (int64_t)A[(size_t)i * n + j];
-            if (j < hL) kleft += sgn * w[j];
+            if (j < hL) kleft += sgn > 0 ? (uint64_t)w[j] : -(uint64_t)w[j];
         }
-        if (slice_mod > 0 && pos_mod(kleft, slice_mod) != slice_res) continue;
+        if (slice_mod > 0 && !wide && pos_mod((int64_t)kleft, slice_mod) != slice_res) continue;
+        if (slice_mod > 0 && wide && (int64_t)(kleft & (uint64_t)(slice_mod - 1)) != slice_res)
+            continue;
         int k = 0;
         while (k < m && sums[k] == d[k]) ++k;     /* rows 1..k hold */
         for (int i = 0; i < k; ++i) hr[i]++;
@@ -258,15 +291,15 @@ static int quarter_build(quarter *q, const int32_t *A, int m, int n, const int64
         return ORC_ENOMEM;
     }
     for (uint64_t u = 0; u < q->size; ++u) {
-        int64_t k = 0;
+        uint64_t k = 0;                          /* modulo 2^64 (exact below 2^63) */
         for (int i = 0; i < m; ++i) q->vec[u * m + i] = 0;
         for (int b = 0; b < width; ++b) {
             if (!((u >> b) & 1u)) continue;
             int j = col0 + b;
-            k += w[j];
+            k += (uint64_t)w[j];
             for (int i = 0; i < m; ++i) q->vec[u * m + i] += A[(size_t)i * n + j];
         }
-        q->key[u] = k;
+        q->key[u] = (int64_t)k;
     }
     return 0;
 }
@@ -565,14 +598,37 @@ static uint64_t lower_res(const int64_t *r, uint64_t n, int64_t t)
     return lo;
 }
 
+/* Pairs (l, r) whose first k row entries agree (left sums against d minus
+ * right sums): both lists sorted on those entries, equal runs multiplied. */
+static u128 count_row_matches(half_rec *L, uint64_t nl, half_rec *R, uint64_t nr, int k)
+{
+    g_cmp_m = k;
+    qsort(L, nl, sizeof *L, cmp_vec);
+    qsort(R, nr, sizeof *R, cmp_vec);
+    u128 h = 0;
+    uint64_t i = 0, j = 0;
+    while (i < nl && j < nr) {
+        const int c = cmp_vec(&L[i], &R[j]);
+        if (c < 0) { ++i; continue; }
+        if (c > 0) { ++j; continue; }
+        uint64_t i2 = i, j2 = j;
+        while (i2 < nl && cmp_vec(&L[i2], &L[i]) == 0) ++i2;
+        while (j2 < nr && cmp_vec(&R[j2], &R[j]) == 0) ++j2;
+        h += (u128)(i2 - i) * (j2 - j);
+        i = i2;
+        j = j2;
+    }
+    return h;
+}
+
 int orc_mitm_residues(const int32_t *A, const int32_t *d, int m, int n,
                       int key_rows, int key_base, int log2_m, int64_t rho_lo, int64_t rho_hi,
                       int64_t slice_mod, int64_t slice_res,
                       uint8_t *sol, uint64_t capacity, orc_result *res)
 {
     int64_t base, kd, w[ORC_MAXN];
-    int infeasible;
-    int rc = orc_key_setup(A, d, m, n, key_rows, key_base, &base, &kd, w, &infeasible);
+    int infeasible, wide;
+    int rc = key_setup_impl(A, d, m, n, key_rows, key_base, &base, &kd, w, &infeasible, &wide);
     if (rc) return rc;
     if (m > 16 || log2_m < 0 || log2_m > 40) return ORC_EINVAL;
     const int64_t M = (int64_t)1 << log2_m;
@@ -599,12 +655,12 @@ int orc_mitm_residues(const int32_t *A, const int32_t *d, int m, int n,
         uint64_t nl = 0, nr = 0;
         /* L(rho): every (a, b) with k_a + k_b = rho (mod M). */
         for (uint64_t a = 0; a < qA->size; ++a) {
-            int64_t t = pos_mod(rho - qA->key[a], M);
+            int64_t t = (int64_t)(((uint64_t)rho - (uint64_t)qA->key[a]) & (uint64_t)(M - 1));
             for (uint64_t p = lower_res(rB, qB->size, t); p < qB->size && rB[p] == t; ++p) {
                 uint64_t b = pB[p];
                 if ((rc = grow(&L, &cl, nl + 1))) goto done;
                 half_rec *h = &L[nl++];
-                h->key = qA->key[a] + qB->key[b];
+                h->key = (int64_t)((uint64_t)qA->key[a] + (uint64_t)qB->key[b]);
                 h->m1 = a;
                 h->m2 = b;
                 for (int i = 0; i < m; ++i) h->v[i] = qA->vec[a * m + i] + qB->vec[b * m + i];
@@ -612,19 +668,26 @@ int orc_mitm_residues(const int32_t *A, const int32_t *d, int m, int n,
         }
         /* R(rho): every (c, e) with K_d - (k_c + k_e) = rho (mod M). */
         for (uint64_t c = 0; c < qC->size; ++c) {
-            int64_t t = pos_mod(kd - qC->key[c] - rho, M);
+            int64_t t = (int64_t)(((uint64_t)kd - (uint64_t)qC->key[c] - (uint64_t)rho) &
+                                  (uint64_t)(M - 1));
             for (uint64_t p = lower_res(rD, qD->size, t); p < qD->size && rD[p] == t; ++p) {
                 uint64_t e = pD[p];
                 if ((rc = grow(&R, &cr, nr + 1))) goto done;
                 half_rec *h = &R[nr++];
-                h->key = qC->key[c] + qD->key[e];
+                h->key = (int64_t)((uint64_t)qC->key[c] + (uint64_t)qD->key[e]);
                 h->m1 = c;
                 h->m2 = e;
                 for (int i = 0; i < m; ++i)
                     h->v[i] = d[i] - (qC->vec[c * m + i] + qD->vec[e * m + i]);
             }
         }
-        /* H: pairs with k_L + k_R = K_d, counted run by run. */
+        /* H: pairs with k_L + k_R = K_d, counted run by run.  A key past
+         * int64 (known modulo 2^64 only) is compared through what it encodes:
+         * k_L + k_R = K_d exactly when rows 1..r hold (eq. surrogate), i.e.
+         * when the left sums of the key rows equal d minus the right sums. */
+        if (wide) {
+            add_h(res, count_row_matches(L, nl, R, nr, key_rows));
+        } else {
         qsort(L, nl, sizeof *L, cmp_key);
         qsort(R, nr, sizeof *R, cmp_key);
         uint64_t i = 0, j = nr;   /* R scanned from the top: k_R descending */
@@ -638,6 +701,7 @@ int orc_mitm_residues(const int32_t *A, const int32_t *d, int m, int n,
             add_h(res, (u128)(i2 - i) * (j - j2));
             i = i2;
             j = j2;
+        }
         }
         /* S: exact join of full row vectors. */
         join_vectors(L, nl, R, nr, m, Q, sol, capacity, res, n);

@@ -17,6 +17,12 @@
  * radix, so the key stays exact with a smaller K_d; key_base = 0 is the
  * paper's choice.
  *
+ * A key past int64 (six or more rows in radix n*D at n >= 20, say): orc_brute
+ * and orc_mitm_residues keep every key value modulo 2^64 (exact for residues
+ * modulo 2^k, so slices must be powers of two) and decide k_L + k_R = K_d on
+ * what the key encodes, the equality of the key rows' sums; orc_key_setup
+ * and orc_ss_heap return -3 for such keys.
+ *
  * H ("1-D hits") = #{x : key(x) = K_d} = #{x : rows 1..r hold}.
  * S = the full solution set.  Slice (optional): only x whose left-half key
  * k_L(x) = key of x restricted to columns 0..ceil(n/2)-1 satisfies
@@ -34,7 +40,11 @@
  * instance and its planted twin (r = 1, 2, 3; moduli 2^9..2^12 and a split
  * class range; also r = 1 against the row-1 counting DP), of the (6,50)
  * planted twin with five key rows in the mixed radix, and of the (5,40) pair
- * with r = 2 (two moduli, a split range, and the 2-row counting DP).  Its
+ * with r = 2 (two moduli, a split range, and the 2-row counting DP).  With
+ * keys past int64 (tests/test_oracle_wide.py) it equals brute force (r = 6, 7
+ * at n = 22, two moduli, a split range), the mixed radix on the same rows
+ * (where the key fits int64 and keys are compared directly), and its slices
+ * partition the solve.  Its
  * results for the n = 70..90 classes are parity unpinned beyond that: they
  * rest on the same code being right at larger n.
  *
@@ -96,6 +106,12 @@ int orc_mitm_residues(const int32_t *A, const int32_t *d, int m, int n,
  * *infeasible is set when some key row has d_i > row sum (then H = 0). */
 int orc_key_setup(const int32_t *A, const int32_t *d, int m, int n, int key_rows,
                   int key_base, int64_t *base, int64_t *kd, int64_t *w, int *infeasible);
+
+/* orc_key_setup that also takes a key past int64: then *wide = 1 and K_d
+ * and w are the values modulo 2^64 (as int64 bit patterns). */
+int orc_key_setup_wide(const int32_t *A, const int32_t *d, int m, int n, int key_rows,
+                       int key_base, int64_t *base, int64_t *kd, int64_t *w, int *infeasible,
+                       int *wide);
 
 #ifdef __cplusplus
 }

@@ -75,8 +75,11 @@ def _load():
                                           u8p, C.c_uint64, C.POINTER(_Res)]
         lib.orc_key_setup.argtypes = [i32p, i32p, C.c_int, C.c_int, C.c_int, C.c_int, i64p, i64p,
                                       i64p, C.POINTER(C.c_int)]
+        lib.orc_key_setup_wide.argtypes = [i32p, i32p, C.c_int, C.c_int, C.c_int, C.c_int, i64p,
+                                           i64p, i64p, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         for f in (lib.orc_brute, lib.orc_dp_count_row, lib.orc_dp_count_2rows,
-                  lib.orc_ss_heap, lib.orc_mitm_residues, lib.orc_key_setup):
+                  lib.orc_ss_heap, lib.orc_mitm_residues, lib.orc_key_setup,
+                  lib.orc_key_setup_wide):
             f.restype = C.c_int
         _lib = lib
     return _lib
@@ -192,9 +195,26 @@ def key_setup(A, d, key_rows=1, key_base=0):
     return base.value, kd.value, w, bool(inf.value)
 
 
+def key_setup_wide(A, d, key_rows=1, key_base=0):
+    """key_setup that also takes keys past int64: then (radix of row 1, K_d
+    mod 2^64, weights mod 2^64, infeasible, True); the int64 values are the
+    bit patterns of those residues."""
+    A, d = _prep(A, d)
+    m, n = A.shape
+    base, kd = C.c_int64(), C.c_int64()
+    w = np.zeros(n, dtype=np.int64)
+    inf, wide = C.c_int(), C.c_int()
+    _check(_load().orc_key_setup_wide(_ptr(A, C.c_int32), _ptr(d, C.c_int32), m, n, key_rows,
+                                      key_base, C.byref(base), C.byref(kd), _ptr(w, C.c_int64),
+                                      C.byref(inf), C.byref(wide)))
+    return base.value, kd.value, w, bool(inf.value), bool(wide.value)
+
+
 def left_key(A, d, x, key_rows=1, key_base=0) -> int:
-    """k_L(x): the 1-D key of x restricted to the left half of the columns."""
-    _, _, w, _ = key_setup(A, d, key_rows, key_base)
+    """k_L(x): the 1-D key of x restricted to the left half of the columns
+    (modulo 2^64 when the key does not fit int64: exact for residues mod 2^k)."""
+    _, _, w, _, wide = key_setup_wide(A, d, key_rows, key_base)
     n = len(w)
     hl = (n + 1) // 2
-    return int(sum(int(w[j]) for j in range(hl) if x[j]))
+    k = int(sum(int(w[j]) for j in range(hl) if x[j]))
+    return k % (1 << 64) if wide else k
