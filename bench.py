@@ -82,11 +82,17 @@ WORKLOADS = {
     "11_100s": dict(m=11, n=100, key_rows=4, seeds=[0], planted=False, slice_mod=65536,
                     desc="(11,100) seed 0, residue slice k_L mod 65536 = 0, key rows 1-4 "
                          "(base 10000)"),
-    # Five key rows at (10,90) in the mixed radix (a 60-bit key): modulus
-    # 2^41, 2^29 residue cells, unequal quarters (q_A = 17, q_B = 28).
+    # Five key rows at (10,90) in the mixed radix (a 60-bit key): with two
+    # key words per record the modulus stays 2^35 (one word would force
+    # 2^41: 2^29 residue cells, unequal quarters q_A = 17, q_B = 28).
     "10_90_r5s": dict(m=10, n=90, key_rows=5, key_base=1, seeds=[0], planted=False,
                       slice_mod=512, desc="(10,90) seed 0, residue slice k_L mod 512 = 0, key "
                                           "rows 1-5 in mixed radix rowsum+1"),
+    # Six key rows at (10,90) in the mixed radix: a 73-bit key (128-bit sums,
+    # two key words per record).
+    "10_90_r6s": dict(m=10, n=90, key_rows=6, key_base=1, seeds=[0], planted=False,
+                      slice_mod=64, desc="(10,90) seed 0, residue slice k_L mod 64 = 0, key "
+                                         "rows 1-6 in mixed radix rowsum+1 (73-bit key)"),
     # Coefficient range K (Section 4's classes K = 50, 100, 200): a_ij in [0, K).
     "6_50_K50": dict(m=6, n=50, key_rows=1, seeds=[0], planted=True, slice_mod=0, K=50,
                      desc="(6,50) K=50 seed 0 + planted twin, key row 1"),

@@ -10,7 +10,10 @@
  * max a_ij + 1) and base B = n*D, key(x) = sum_{i<r} B^i (a_i . x) and
  * K_d = sum_{i<r} B^i d_i; key(x) = K_d holds exactly when rows 1..r hold.
  * msp_opts.key_base = 1 gives row i the mixed radix rowsum_i + 1 instead of
- * B (the same exactness with a smaller key, so more rows fit in int64).
+ * B (the same exactness with a smaller key).  Keys up to 96 bits are exact:
+ * past 63 bits the sums are carried in 128 bits and the half records keep
+ * a second key word (msp_opts.key_words).  A slice selects on the left
+ * key modulo slice_mod, exact for any key width.
  * Every solution of that 1-D subset-sum problem (a "1-D hit") is enumerated
  * with a Schroeppel-Shamir style four-list meet in the middle (Algorithm 1,
  * with the heaps replaced by residue classes of the key), and every hit is
@@ -27,7 +30,8 @@
  *
  * Column partition (Algorithm 1 leaves it open): contiguous quarters,
  * h_L = ceil(n/2), q_A = ceil(h_L/2), q_B = floor(h_L/2),
- * q_C = ceil((n-h_L)/2), q_D = floor((n-h_L)/2).
+ * q_C = ceil((n-h_L)/2), q_D = floor((n-h_L)/2), or unequal ones
+ * (msp_opts.log2_outer).
  *
  * Threading: one context is used by one host thread at a time; distinct
  * contexts may be used concurrently.  All calls return MSP_OK (0) or a
@@ -46,7 +50,7 @@ extern "C" {
 #define MSP_OK               0
 #define MSP_E_INVALID      (-1)  /* null pointer, m<1, n<1, a_ij<0, d_i<0, bad option */
 #define MSP_E_RANGE        (-2)  /* some row sum exceeds 65534 (uint16 row packing)    */
-#define MSP_E_KEY_OVERFLOW (-3)  /* largest key (all rows at their row sums) >= 2^63   */
+#define MSP_E_KEY_OVERFLOW (-3)  /* largest key >= 2^96, or >= 2^63 with key_words = 1 */
 #define MSP_E_UNSUPPORTED  (-4)  /* m > 16, n > 100, m - r > 10, or > 2^29 cells needed*/
 #define MSP_E_NOMEM        (-5)  /* device workspace does not fit the budget            */
 #define MSP_E_DEVICE       (-6)  /* HIP runtime error; the context is poisoned          */
@@ -118,7 +122,18 @@ typedef struct {
                                  its outer quarter to its inner one (same pairs,
                                  fewer outer elements per residue cell).  Same H,
                                  |S| and solutions                                  */
-    int32_t  reserved0;
+    int32_t  key_words;       /* what a half record keeps of key >> log2_m (Section 1,
+                                 eq. surrogate): 1 = the bits above the two quarter
+                                 positions of its 64-bit header (64 - ceil(n/2)),
+                                 the modulus raised until they suffice; 2 = a
+                                 second key word of 32 more bits (records carry
+                                 the row fingerprint and that word, 16 bytes),
+                                 needed for keys past int64 (up to 96 bits; more
+                                 key rows, e.g. six at n = 90); 0 = the planner's
+                                 choice: two words for keys past int64 or when one
+                                 word would force the modulus up.  Two words
+                                 need row_fingerprint != 2.  Same H, |S| and
+                                 solutions                                          */
 } msp_opts;
 
 /* Per-solve statistics; phase times are measured with HIP events on the
@@ -155,6 +170,8 @@ typedef struct {
     int32_t  log2_outer;      /* q_A used (msp_opts.log2_outer)                      */
     uint64_t first_cell;      /* window_order 1: index of the first cell of the first
                                  window processed (the densest)                      */
+    int32_t  key_words;       /* 1 or 2 (msp_opts.key_words)                         */
+    int32_t  key_bits;        /* bits of K_d + 1: up to 96                           */
 } msp_stats_t;
 
 /* Device memory from the caller, e.g. a torch-allocated arena, so that the
@@ -276,6 +293,8 @@ typedef struct {
     uint64_t workspace_bytes;  /* device workspace of the plan                           */
     uint64_t max_grid_items;   /* largest work-item count of the window's launches whose
                                   size the plan fixes (< 2^32)                           */
+    int32_t  key_words;        /* 1 or 2: key words per half record (msp_opts.key_words) */
+    int32_t  key_bits;         /* bits of K_d + 1                                        */
 } msp_plan_t;
 int  msp_plan(const msp_ctx *ctx, const msp_opts *opts, msp_plan_t *out);
 

@@ -103,6 +103,7 @@ struct Sizes {
     uint64_t o_qraw[4], o_qsrt[4], o_qcnt[4], o_qcur[4], o_cnt[2], o_off[2], o_rec[2];
     uint64_t o_qvraw[4], o_qvsrt[4], o_pre[2], o_tot[2], o_wscore = 0;
     uint64_t o_runs, o_tiles, o_sol, o_scal, o_scan, scan_bytes, o_colw, o_rows;
+    uint64_t o_colwh = 0, o_qkhraw[4] = {}, o_qkhsrt[4] = {};
     uint64_t o_iruns, o_itiles, o_idx, n_iruns, o_heavy, o_heavy2, idx_n;
     uint64_t o_vtab, vtab_slots;
     uint64_t max_items = 0;  // largest launch of a window, work-items
@@ -110,9 +111,10 @@ struct Sizes {
 
 struct Prepared {
     Plan p{};
-    std::vector<int64_t> colw;
+    std::vector<int64_t> colw, colwh;       // column weights: low and high words
     std::vector<uint16_t> rows;
     bool infeasible = false;
+    int key_bits = 0;                       // bits of K_d + 1
     Sizes z;
 };
 
@@ -211,32 +213,41 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
     // int64 holds more rows.  Either way 0 <= a_i.x <= rowsum_i < rad_i, so
     // key(x) = K_d exactly when rows 1..r hold.
     if (o.key_base < 0 || o.key_base > 1) return MSP_E_INVALID;
+    if (o.key_words < 0 || o.key_words > 2) return MSP_E_INVALID;
     int32_t amax = 0;
     for (int32_t a : c->A) amax = std::max(amax, a);
     const int64_t D = std::max<int64_t>(100, (int64_t)amax + 1);
-    std::vector<int64_t> pw(r, 1);                  // place value of digit i
-    __int128 kmax = 0, place = 1;
+    // The key in 128 bits: past int64 the quarters carry a high word (kw)
+    // and the records a second key word.  Keys stay below 2^96.
+    using u128 = unsigned __int128;
+    const u128 kKeyLimit = (u128)1 << 96;
+    std::vector<u128> pw(r, 1);                     // place value of digit i
+    u128 kmax = 0, place = 1;
     P.infeasible = false;
     for (int i = 0; i < r; ++i) {
         int64_t rs = 0;
         for (int j = 0; j < n; ++j) rs += c->A[(size_t)i * n + j];
         if (c->d[i] > rs) P.infeasible = true;      // row i can never hold: H = 0
-        pw[i] = (int64_t)place;
-        kmax += place * rs;
-        if (kmax >= ((__int128)1 << 63)) return MSP_E_KEY_OVERFLOW;
-        place *= o.key_base ? rs + 1 : (int64_t)n * D;
-        if (i + 1 < r && place >= ((__int128)1 << 63)) return MSP_E_KEY_OVERFLOW;
+        pw[i] = place;
+        kmax += place * (u128)rs;
+        if (kmax >= kKeyLimit) return MSP_E_KEY_OVERFLOW;
+        place *= (u128)(o.key_base ? rs + 1 : (int64_t)n * D);
+        if (i + 1 < r && place >= kKeyLimit) return MSP_E_KEY_OVERFLOW;
     }
+    p.kw = kmax >= ((u128)1 << 63) ? 1 : 0;
     // d_i <= rowsum_i on every key row keeps K_d below the largest key.
-    int64_t kd = 0;
+    u128 kd = 0;
     if (!P.infeasible)
-        for (int i = 0; i < r; ++i) kd += pw[i] * (int64_t)c->d[i];
-    p.Kd = kd;
+        for (int i = 0; i < r; ++i) kd += pw[i] * (u128)c->d[i];
+    p.Kd = (int64_t)(uint64_t)kd;
+    p.Kdh = (int64_t)(uint64_t)(kd >> 64);
     P.colw.assign(n, 0);
+    P.colwh.assign(n, 0);
     for (int j = 0; j < n; ++j) {
-        int64_t s = 0;
-        for (int i = 0; i < r; ++i) s += pw[i] * (int64_t)c->A[(size_t)i * n + j];
-        P.colw[j] = s;
+        u128 sw = 0;
+        for (int i = 0; i < r; ++i) sw += pw[i] * (u128)c->A[(size_t)i * n + j];
+        P.colw[j] = (int64_t)(uint64_t)sw;
+        P.colwh[j] = (int64_t)(uint64_t)(sw >> 64);
     }
     P.rows.assign((size_t)std::max(p.nv, 1) * n, 0);
     for (int v = 0; v < p.nv; ++v)
@@ -254,11 +265,16 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
     p.Wr = p.fp ? 1 : p.W;
     p.hd = 0;
     for (int v = 0; v < p.nv; ++v) p.hd += kFpMul[v] * (uint32_t)c->d[r + v];
-    for (int x = 0; x < 4; ++x) p.qv[x] = nullptr;
+    for (int x = 0; x < 4; ++x) {
+        p.qv[x] = nullptr;
+        p.qkh[x] = nullptr;
+    }
 
     // Residue modulus M and cells T.  Exact buckets when M can exceed K_d
     // cheaply (small keys, e.g. one key row); else buckets of ~1K records.
-    const int lgKd = lg2ceil((uint64_t)p.Kd + 1);
+    int lgKd = 0;                                   // bits of K_d + 1
+    while (lgKd < 127 && ((u128)1 << lgKd) < kd + 1) ++lgKd;
+    P.key_bits = lgKd;
     int log2M, log2T;
     if (o.log2_m) {
         log2M = o.log2_m;
@@ -267,17 +283,33 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
     } else {
         log2M = std::max(p.qa + p.qb - 10, 1);
     }
-    // Records keep key >> log2M in the bits above the two quarter positions.
+    // Records keep key >> log2M in the bits above the two quarter positions,
+    // and with a second key word (p.wide) in 32 more bits of the record.
+    // The planner takes the second word for keys past int64, and when the
+    // header alone would force the modulus up (more cells than the quarters
+    // have inner elements, each outer element yielding a record or two):
+    // 4 more bytes per record against a much slower enumeration.
     p.hsh = p.qa + p.qb;
     {
-        const int key_room = 64 - p.hsh;
-        const int need = lgKd - key_room;          // smallest log2M that fits
+        const int room1 = 64 - p.hsh;
+        const int room2 = std::min(64, room1 + 32);
+        int words = o.key_words;
+        if (!words)
+            words = (p.kw || lgKd - log2M > room1) && o.row_fingerprint != 2 ? 2 : 1;
+        if (words == 1 && p.kw) return MSP_E_KEY_OVERFLOW;
+        if (words == 2 && o.row_fingerprint == 2) return MSP_E_UNSUPPORTED;
+        p.wide = words == 2 ? 1 : 0;
+        const int need = lgKd - (p.wide ? room2 : room1);   // smallest log2M that fits
         if (log2M < need) {
             if (o.log2_m) return MSP_E_INVALID;
             log2M = need;
         }
     }
-    p.exact = (((uint64_t)1 << std::min(log2M, 62)) > (uint64_t)p.Kd) ? 1 : 0;
+    if (p.wide) {                                   // fingerprint + second key word
+        p.fp = 1;
+        p.Wr = 2;
+    }
+    p.exact = (!p.kw && ((uint64_t)1 << std::min(log2M, 62)) > (uint64_t)p.Kd) ? 1 : 0;
     if (o.log2_cells) {
         log2T = o.log2_cells;
     } else {
@@ -405,6 +437,8 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
         for (int x = 0; x < 4; ++x) z.o_qsrt[x] = take((uint64_t)p.Q[x] * qb);
         for (int x = 0; x < 4; ++x) z.o_qvraw[x] = take((uint64_t)p.Q[x] * qvb + 4);
         for (int x = 0; x < 4; ++x) z.o_qvsrt[x] = take((uint64_t)p.Q[x] * qvb + 4);
+        for (int x = 0; x < 4; ++x) z.o_qkhraw[x] = take(p.kw ? (uint64_t)p.Q[x] * 8 : 8);
+        for (int x = 0; x < 4; ++x) z.o_qkhsrt[x] = take(p.kw ? (uint64_t)p.Q[x] * 8 : 8);
         for (int x = 0; x < 4; ++x) z.o_qcnt[x] = take((T + 1) * 4);
         for (int x = 0; x < 4; ++x) z.o_qcur[x] = take((T + 1) * 4);
         const uint64_t ncnt = kw * F * (uint64_t)parts + 1;
@@ -442,6 +476,7 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
                                                          std::max<uint64_t>(kw * F + 1, nI + 1)));
         z.o_scan = take(z.scan_bytes);
         z.o_colw = take((uint64_t)n * 8);
+        z.o_colwh = take((uint64_t)n * 8);
         z.o_rows = take(P.rows.size() * 2);
         return off;
     };
@@ -611,6 +646,9 @@ void job_carve(Job &j) {
         j.b.qvraw[x] = (uint32_t *)(ws + z.o_qvraw[x]);
         j.b.qvsrt[x] = (uint32_t *)(ws + z.o_qvsrt[x]);
         j.P.p.qv[x] = j.P.p.fp ? j.b.qvsrt[x] : nullptr;
+        j.b.qkhraw[x] = (int64_t *)(ws + z.o_qkhraw[x]);
+        j.b.qkhsrt[x] = (int64_t *)(ws + z.o_qkhsrt[x]);
+        j.P.p.qkh[x] = j.P.p.kw ? j.b.qkhsrt[x] : nullptr;
     }
     for (int sd = 0; sd < 2; ++sd) {
         j.b.cnt[sd] = (uint32_t *)(ws + z.o_cnt[sd]);
@@ -636,6 +674,7 @@ void job_carve(Job &j) {
     j.b.scan_tmp = ws + z.o_scan;
     j.b.scan_tmp_bytes = z.scan_bytes;
     j.b.colw = (int64_t *)(ws + z.o_colw);
+    j.b.colwh = (int64_t *)(ws + z.o_colwh);
     j.b.rows = (uint16_t *)(ws + z.o_rows);
 }
 
@@ -676,6 +715,7 @@ int job_step(Job &j) {
         case A_BEGIN: {
             const uint64_t T = (uint64_t)1 << p.log2T;
             JCHK(hipMemcpyAsync(j.b.colw, j.P.colw.data(), j.P.colw.size() * 8, hipMemcpyHostToDevice, j.s));
+            JCHK(hipMemcpyAsync(j.b.colwh, j.P.colwh.data(), j.P.colwh.size() * 8, hipMemcpyHostToDevice, j.s));
             JCHK(hipMemcpyAsync(j.b.rows, j.P.rows.data(), j.P.rows.size() * 2, hipMemcpyHostToDevice, j.s));
             JCHK(hipMemsetAsync(j.b.scal, 0, S_COUNT * 8, j.s));
             for (int x = 0; x < 4; ++x) JCHK(hipMemsetAsync(j.b.qcnt[x], 0, (T + 1) * 4, j.s));
@@ -858,7 +898,7 @@ int job_step(Job &j) {
             }
             if (j.cancel) return MSP_E_CANCELLED;
             const uint64_t stored =
-                std::min<uint64_t>(z.sol_cap, p.W == 0 ? j.hs[S_STORED] : j.hs[S_NSOL]);
+                std::min<uint64_t>(z.sol_cap, p.Wr == 0 ? j.hs[S_STORED] : j.hs[S_NSOL]);
             j.solbuf.resize(stored * 2);
             if (stored)
                 JCHK(hipMemcpyAsync(j.solbuf.data(), j.b.sol, stored * 16, hipMemcpyDeviceToHost, j.s));
@@ -928,6 +968,8 @@ void job_init_stats(Job &j) {
     j.st.record_bytes = rec_bytes(p.Wr);
     j.st.row_fingerprint = p.fp;
     j.st.log2_outer = p.qa;
+    j.st.key_words = p.wide ? 2 : 1;
+    j.st.key_bits = j.P.key_bits;
     j.st.vector_join = p.vjoin;
     j.st.join_grouped = p.exact ? 0 : p.join_grouped;
     j.st.key_base = j.o.key_base;
@@ -1284,6 +1326,8 @@ int msp_plan(const msp_ctx *c, const msp_opts *opts, msp_plan_t *out) {
     t.row_fingerprint = p.fp;
     t.log2_outer = p.qa;
     t.log2_inner = p.qb;
+    t.key_words = p.wide ? 2 : 1;
+    t.key_bits = P.key_bits;
     t.workspace_bytes = z.total;
     t.max_grid_items = z.max_items;
     *out = t;

@@ -42,7 +42,10 @@ struct Plan {
     int32_t gbig;                    // grouped join with 1024-thread groups (big buckets)
     int32_t vjoin;                   // exact runs decided by the vector hash join
     int32_t khb;                     // bits of key >> log2M (every stored key is in [0, K_d])
-    int64_t Kd;                      // target key
+    int32_t kw;                      // 1: keys past int64 (a high word per quarter subset)
+    int32_t wide;                    // 1: half records carry a second key word, vec[Wr - 1]
+    int64_t Kd;                      // target key (its low 64 bits when kw)
+    int64_t Kdh;                     // kw: high word of the target key
     int64_t slice_mod, slice_res;    // slice on the left key (0 = none)
     int64_t kstep, kfirst;           // cell k = kfirst + idx * kstep
     uint32_t dpk[kMaxWords];         // packed non-key right-hand sides
@@ -51,6 +54,7 @@ struct Plan {
     int32_t Wr;                      // 32-bit words per half record and quarter record (1 with fp)
     uint32_t hd;                     // fingerprint of the non-key right-hand sides
     const uint32_t *qv[4];           // with fp: packed rows (W words) of the sorted quarters
+    const int64_t *qkh[4];           // kw: high key words of the sorted quarters
 };
 
 // A quarter subset: 1-D key (for quarter C: K_d - key), subset mask, packed
@@ -67,8 +71,10 @@ struct __attribute__((packed, aligned(4))) QRec {
 // (key K_d - k_c - k_d, packed d' - row sums with 0xFFFF for negatives).
 // hdr = outer position | inner position << qa | (key >> log2M) << (qa + qb):
 // the low log2M key bits are the bucket's residue, and the subset masks are
-// read back from the sorted quarter lists only for solutions.  Packed at
-// 4-byte alignment like QRec: 12 + 4W bytes, so odd W costs no padding.
+// read back from the sorted quarter lists only for solutions.  With a second
+// key word (Plan::wide), key >> log2M continues in vec[W - 1]: its bits past
+// the 64 - (qa + qb) that the header holds.  Packed at 4-byte alignment like
+// QRec: 12 + 4W bytes, so odd W costs no padding.
 template <int W>
 struct __attribute__((packed, aligned(4))) Rec {
     uint64_t hdr;
@@ -109,7 +115,10 @@ struct DevBufs {
     uint64_t *scal;                  // scalars (see Scal)
     void *scan_tmp;                  // scratch of the device-wide scan
     size_t scan_tmp_bytes;
-    int64_t *colw;                   // per-column key weight (n)
+    int64_t *colw;                   // per-column key weight (n; its low word when kw)
+    int64_t *colwh;                  // kw: high words of the column weights (n)
+    int64_t *qkhraw[4];              // kw: high key words of the quarter subsets, raw order
+    int64_t *qkhsrt[4];              // ... and in sorted order
     uint16_t *rows;                  // non-key rows, nv x n
 };
 

@@ -106,12 +106,28 @@ __device__ __forceinline__ uint32_t resid_word(uint32_t dp, uint32_t c, uint32_t
 template <int W>
 struct QPtrs { QRec<W> *q[4]; };
 struct UPtrs { uint32_t *q[4]; };
+struct KPtrs { int64_t *q[4]; };
 
-// Key bits above the residue, and the subset masks of a half record.
+// A record's key above the residue, key >> log2M: the header's high bits
+// and, with a second key word (p.wide), their continuation in the record's
+// last word.  Equal for two records exactly when their keys are equal.
+__device__ __forceinline__ uint64_t hkey(const Plan &p, uint64_t hdr, uint32_t kx) {
+    uint64_t k = hdr >> p.hsh;
+    if (p.wide) k |= (uint64_t)kx << (64 - p.hsh);
+    return k;
+}
+
+template <int W>
+__device__ __forceinline__ uint32_t kword(const uint32_t *v) {
+    return W >= 2 ? v[W - 1] : 0u;
+}
+
 template <int W>
 __device__ __forceinline__ int64_t rkey(const Plan &p, const Rec<W> &r) {
-    return (int64_t)(r.hdr >> p.hsh);
+    return (int64_t)hkey(p, r.hdr, kword<W>(r.vec));
 }
+
+// The subset masks of a half record (outer | inner << width of the outer).
 template <int W>
 __device__ __forceinline__ uint64_t half_mask(const Plan &p, const QPtrs<W> &qs, int side,
                                               uint64_t hdr) {
@@ -129,11 +145,17 @@ __device__ __forceinline__ uint64_t half_mask(const Plan &p, const QPtrs<W> &qs,
 // sums of the non-key rows, and its residue cell (counted).
 template <int W>
 __global__ __launch_bounds__(256) void k_quarter_gen(Plan p, const int64_t *__restrict__ colw,
+                                                     const int64_t *__restrict__ colwh,
                                                      const uint16_t *__restrict__ rows,
-                                                     QPtrs<W> out, UPtrs cnt, UPtrs qvec) {
+                                                     QPtrs<W> out, UPtrs cnt, UPtrs qvec,
+                                                     KPtrs qkh) {
     __shared__ int64_t s_w[kMaxN];
+    __shared__ int64_t s_wh[kMaxN];
     __shared__ uint16_t s_rows[kMaxWords * 2 * kMaxN];
-    for (int i = threadIdx.x; i < p.n; i += blockDim.x) s_w[i] = colw[i];
+    for (int i = threadIdx.x; i < p.n; i += blockDim.x) {
+        s_w[i] = colw[i];
+        s_wh[i] = p.kw ? colwh[i] : 0;
+    }
     for (int i = threadIdx.x; i < p.nv * p.n; i += blockDim.x) s_rows[i] = rows[i];
     __syncthreads();
     uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -143,22 +165,31 @@ __global__ __launch_bounds__(256) void k_quarter_gen(Plan p, const int64_t *__re
     const int col0 = x == 0 ? 0 : x == 1 ? p.qa : x == 2 ? p.hL : p.hL + p.qc;
     const int width = x == 0 ? p.qa : x == 1 ? p.qb : x == 2 ? p.qc : p.qd;
     const uint32_t u = (uint32_t)g;
-    int64_t key = 0;
+    // Key in 128 bits (lo, hi) when it does not fit int64 (p.kw), else lo.
+    uint64_t klo = 0;
+    int64_t khi = 0;
     uint32_t s[kMaxWords * 2];
 #pragma unroll
     for (int v = 0; v < kMaxWords * 2; ++v) s[v] = 0;
     for (int b = 0; b < width; ++b) {
         if (!((u >> b) & 1u)) continue;
         const int j = col0 + b;
-        key += s_w[j];
+        const uint64_t wl = (uint64_t)s_w[j];
+        klo += wl;
+        khi += s_wh[j] + (klo < wl ? 1 : 0);
 #pragma unroll
         for (int v = 0; v < kMaxWords * 2; ++v)
             if (v < p.nv) s[v] += s_rows[v * p.n + j];
     }
-    if (x == 2) key = p.Kd - key;        // quarter C carries K_d - k_c
+    if (x == 2) {                        // quarter C carries K_d - k_c
+        const uint64_t kl = (uint64_t)p.Kd;
+        khi = p.Kdh - khi - (kl < klo ? 1 : 0);
+        klo = kl - klo;
+    }
     QRec<W> r;
-    r.key = key;
+    r.key = (int64_t)klo;
     r.mask = u;
+    if (p.kw) qkh.q[x][u] = khi;
     if (p.fp) {
         // Fingerprint: sum_v kFpMul[v] * s_v mod 2^32 (linear, so the halves
         // add up); the packed rows go to their own array for exact checks.
@@ -166,6 +197,8 @@ __global__ __launch_bounds__(256) void k_quarter_gen(Plan p, const int64_t *__re
 #pragma unroll
         for (int v = 0; v < kMaxWords * 2; ++v) h += kFpMul[v] * s[v];
         r.vec[0] = h;
+#pragma unroll
+        for (int w = 1; w < (W > 0 ? W : 1); ++w) r.vec[w] = 0;
         for (int w = 0; w < p.W; ++w) qvec.q[x][(size_t)u * p.W + w] = s[2 * w] | (s[2 * w + 1] << 16);
     } else {
 #pragma unroll
@@ -173,13 +206,14 @@ __global__ __launch_bounds__(256) void k_quarter_gen(Plan p, const int64_t *__re
     }
     out.q[x][u] = r;
     const uint32_t T = 1u << p.log2T;
-    atomicAdd(&cnt.q[x][(uint32_t)key & (T - 1)], 1u);
+    atomicAdd(&cnt.q[x][(uint32_t)klo & (T - 1)], 1u);
 }
 
 // Counting-sort scatter of each quarter by residue cell.
 template <int W>
 __global__ __launch_bounds__(256) void k_quarter_sort(Plan p, QPtrs<W> raw, QPtrs<W> srt,
-                                                      UPtrs cur, UPtrs vraw, UPtrs vsrt) {
+                                                      UPtrs cur, UPtrs vraw, UPtrs vsrt,
+                                                      KPtrs khraw, KPtrs khsrt) {
     uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int x = 0;
     while (x < 4 && g >= p.Q[x]) { g -= p.Q[x]; ++x; }
@@ -188,6 +222,7 @@ __global__ __launch_bounds__(256) void k_quarter_sort(Plan p, QPtrs<W> raw, QPtr
     const uint32_t T = 1u << p.log2T;
     const uint32_t pos = atomicAdd(&cur.q[x][(uint32_t)r.key & (T - 1)], 1u);
     srt.q[x][pos] = r;
+    if (p.kw) khsrt.q[x][pos] = khraw.q[x][g];
     if (p.fp)
         for (int w = 0; w < p.W; ++w)
             vsrt.q[x][(size_t)pos * p.W + w] = vraw.q[x][(size_t)g * p.W + w];
@@ -226,12 +261,30 @@ __device__ __forceinline__ void cell_part(uint32_t b, uint32_t K, uint32_t P, in
 // elements per outer element of a cell, so few loads are wasted).  The side
 // and the slice filter are compile-time.  Out-of-range lanes load a valid
 // record and ignore it, so every step issues the same loads.
-template <int W, int PER, int KU, bool SLICE, int SIDE>
+// A pair's key in 128 bits (keys past int64, KW): low word `lo` from the two
+// quarters' low words, the filter (left key <= K_d, right key >= 0) on the
+// full value.  Returns whether the pair can meet the other side.
+template <int SIDE>
+__device__ __forceinline__ bool key128(const Plan &p, uint64_t a, int64_t ah, uint64_t b,
+                                       int64_t bh, uint64_t &lo, int64_t &hi) {
+    if (SIDE) {
+        lo = a - b;
+        hi = ah - bh - (a < b ? 1 : 0);
+        return hi >= 0;
+    }
+    lo = a + b;
+    hi = ah + bh + (lo < a ? 1 : 0);
+    return hi < p.Kdh || (hi == p.Kdh && lo <= (uint64_t)p.Kd);
+}
+
+template <int W, int PER, int KU, bool SLICE, int SIDE, bool KW>
 __device__ __forceinline__ void count_body(const Plan &p, const QRec<W> *__restrict__ outer,
                                            const QRec<W> *__restrict__ inner,
                                            const uint32_t *__restrict__ ioff, uint64_t Qo,
                                            uint32_t *cnt, int64_t idx0, uint64_t *scal,
-                                           uint32_t *s_f, unsigned long long *s_pairs) {
+                                           uint32_t *s_f, unsigned long long *s_pairs,
+                                           const int64_t *__restrict__ okh,
+                                           const int64_t *__restrict__ ikh) {
     const int P = p.parts;
     int cw, part;
     cell_part(blockIdx.x, gridDim.x / P, P, cw, part);
@@ -248,12 +301,13 @@ __device__ __forceinline__ void count_body(const Plan &p, const QRec<W> *__restr
     const uint32_t fmask = (uint32_t)F - 1;
     uint64_t npairs = 0;                 // pairs this thread enumerates
     for (uint64_t c0 = lo; c0 < hi; c0 += (uint64_t)256 * PER) {
-        int64_t ak[PER];
+        int64_t ak[PER], akh[PER];
         uint32_t b0[PER], b1[PER];
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
             const uint64_t i = c0 + (uint64_t)e * 256 + t;
             ak[e] = outer[i < hi ? i : lo].key;
+            akh[e] = KW ? okh[i < hi ? i : lo] : 0;
         }
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
@@ -267,16 +321,28 @@ __device__ __forceinline__ void count_body(const Plan &p, const QRec<W> *__restr
             if (c0 + (uint64_t)e * 256 + t >= hi) b1[e] = b0[e];
             npairs += b1[e] - b0[e];
             for (uint32_t q0 = b0[e]; q0 < b1[e]; q0 += KU) {
-                int64_t bk[KU];
+                int64_t bk[KU], bkh[KU];
 #pragma unroll
-                for (int u = 0; u < KU; ++u) bk[u] = inner[min(q0 + u, b1[e] - 1)].key;
+                for (int u = 0; u < KU; ++u) {
+                    bk[u] = inner[min(q0 + u, b1[e] - 1)].key;
+                    bkh[u] = KW ? ikh[min(q0 + u, b1[e] - 1)] : 0;
+                }
 #pragma unroll
                 for (int u = 0; u < KU; ++u) {
                     if (q0 + u >= b1[e]) break;
-                    const int64_t key = SIDE ? ak[e] - bk[u] : ak[e] + bk[u];
-                    bool keep = SIDE ? key >= 0 : key <= Kd;   // only these can meet
+                    int64_t key;
+                    bool keep;
+                    if (KW) {
+                        uint64_t l;
+                        int64_t h;
+                        keep = key128<SIDE>(p, (uint64_t)ak[e], akh[e], (uint64_t)bk[u], bkh[u], l, h);
+                        key = (int64_t)l;
+                    } else {
+                        key = SIDE ? ak[e] - bk[u] : ak[e] + bk[u];
+                        keep = SIDE ? key >= 0 : key <= Kd;   // only these can meet
+                    }
                     if (SLICE) keep = keep && ((key & smod1) == sres);
-                    if (keep) atomicAdd(&s_f[(uint32_t)(key >> lt) & fmask], 1u);
+                    if (keep) atomicAdd(&s_f[(uint32_t)((uint64_t)key >> lt) & fmask], 1u);
                 }
             }
         }
@@ -290,7 +356,7 @@ __device__ __forceinline__ void count_body(const Plan &p, const QRec<W> *__restr
     if (t == 0 && *s_pairs > 0xFFFFFFFFull) atomicOr((unsigned long long *)&scal[S_OVF], 1ull);
 }
 
-template <int W, int PER, int KU, bool SLICE>
+template <int W, int PER, int KU, bool SLICE, bool KW>
 __global__ __launch_bounds__(256) void k_count(Plan p, const QRec<W> *__restrict__ A,
                                                const QRec<W> *__restrict__ B,
                                                const uint32_t *__restrict__ offB,
@@ -302,9 +368,11 @@ __global__ __launch_bounds__(256) void k_count(Plan p, const QRec<W> *__restrict
     __shared__ uint32_t s_f[kMaxFine];
     __shared__ unsigned long long s_pairs;
     if (blockIdx.y == 0)
-        count_body<W, PER, KU, SLICE, 0>(p, A, B, offB, p.Q[0], cntL, idx0, scal, s_f, &s_pairs);
+        count_body<W, PER, KU, SLICE, 0, KW>(p, A, B, offB, p.Q[0], cntL, idx0, scal, s_f,
+                                             &s_pairs, p.qkh[0], p.qkh[1]);
     else
-        count_body<W, PER, KU, SLICE, 1>(p, Cq, Dq, offD, p.Q[2], cntR, idx0, scal, s_f, &s_pairs);
+        count_body<W, PER, KU, SLICE, 1, KW>(p, Cq, Dq, offD, p.Q[2], cntR, idx0, scal, s_f,
+                                             &s_pairs, p.qkh[2], p.qkh[3]);
 }
 
 // Exclusive scan of a[0 .. n) in LDS by an NT-thread block (n a multiple of
@@ -516,15 +584,26 @@ __global__ __launch_bounds__(NT) void k_scatter_staged(Plan p, const QRec<W> *__
 // loop carries no selects between them.
 constexpr int kRecNT = 1024;
 
-template <int W, int PER, int MAXF, bool FP, bool SLICE, int SIDE>
+// Records staged per batch: 16 bytes each (20 with a second key word) beside
+// the bucket cursors, within one CU's 160 KB of LDS.
+template <int W, int MAXF>
+constexpr int rec_batch() {
+    return (W == 2 ? (MAXF > 2048 ? 6 : 7) : (MAXF > 2048 ? 7 : 8)) * kRecNT;
+}
+
+// W = 2: records with a second key word (vec[0] the fingerprint, vec[1] the
+// bits of key >> log2M past the header's); KW: keys past int64, whose high
+// words come from p.qkh.
+template <int W, int PER, int MAXF, bool FP, bool SLICE, int SIDE, bool KW>
 __device__ __forceinline__ void scatter_rec_body(
     const Plan &p, const QRec<W> *__restrict__ outer, const QRec<W> *__restrict__ inner,
     const uint32_t *__restrict__ ioff, uint64_t Qo, const uint32_t *__restrict__ bst,
     const uint32_t *__restrict__ pre, Rec<W> *rec, int64_t idx0, uint32_t *s_cur,
-    uint32_t *s_cnt, uint64_t *s_hdr, uint32_t *s_wd, uint16_t *s_f, uint16_t *s_perm,
-    uint32_t *s_w4) {
+    uint32_t *s_cnt, uint64_t *s_hdr, uint32_t *s_wd, uint32_t *s_kx, uint16_t *s_f,
+    uint16_t *s_perm, uint32_t *s_w4, const int64_t *__restrict__ okh,
+    const int64_t *__restrict__ ikh) {
     constexpr int NT = kRecNT;
-    constexpr int BATCH = (MAXF > 2048 ? 7 : 8) * NT;
+    constexpr int BATCH = rec_batch<W, MAXF>();
     constexpr int NW = NT / 64;
     const int P = p.parts;
     int cw, part;
@@ -562,6 +641,7 @@ __device__ __forceinline__ void scatter_rec_body(
             Rec<W> r;
             r.hdr = s_hdr[slot];
             r.vec[0] = s_wd[slot];
+            if constexpr (W == 2) r.vec[1] = s_kx[slot];
             rec[s_cur[f] + (o - start)] = r;
         }
         __syncthreads();
@@ -576,7 +656,7 @@ __device__ __forceinline__ void scatter_rec_body(
         // reads consecutive records) and the offsets of their pairs in the
         // chunk.  Past the end a lane reads element lo and ignores it, so all
         // loads of an element are issued together.
-        int64_t akey[PER];
+        int64_t akey[PER], akh[PER];
         uint32_t aw[PER], b0[PER], nn[PER], c1[PER];
         uint32_t mysum = 0;
 #pragma unroll
@@ -584,6 +664,7 @@ __device__ __forceinline__ void scatter_rec_body(
             const uint64_t i = c0 + (uint64_t)e * NT + t;
             akey[e] = outer[i < hi ? i : lo].key;
             aw[e] = outer[i < hi ? i : lo].vec[0];
+            akh[e] = KW ? okh[i < hi ? i : lo] : 0;
         }
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
@@ -626,16 +707,29 @@ __device__ __forceinline__ void scatter_rec_body(
                     const uint64_t qi = b0[e] + q;
                     const int64_t bk = inner[qi].key;
                     const uint32_t bw = inner[qi].vec[0];
-                    const int64_t key = SIDE ? akey[e] - bk : akey[e] + bk;
-                    bool keep = SIDE ? key >= 0 : key <= Kd;
+                    int64_t key;
+                    bool keep;
+                    uint64_t c;                   // key >> log2M
+                    if (KW) {
+                        uint64_t l;
+                        int64_t h;
+                        keep = key128<SIDE>(p, (uint64_t)akey[e], akh[e], (uint64_t)bk, ikh[qi], l, h);
+                        key = (int64_t)l;
+                        c = (l >> lm) | ((uint64_t)h << (64 - lm));
+                    } else {
+                        key = SIDE ? akey[e] - bk : akey[e] + bk;
+                        keep = SIDE ? key >= 0 : key <= Kd;
+                        c = (uint64_t)key >> lm;
+                    }
                     if (SLICE) keep = keep && ((key & smod1) == sres);
                     const uint32_t o = fill + off + q - P0;
-                    s_hdr[o] = ai | (qi << qa) | ((uint64_t)(key >> lm) << hsh);
+                    s_hdr[o] = ai | (qi << qa) | (c << hsh);
+                    if constexpr (W == 2) s_kx[o] = (uint32_t)(c >> (64 - hsh));
                     uint32_t wd;
                     if (FP) wd = SIDE ? hd - aw[e] - bw : aw[e] + bw;
                     else wd = SIDE ? resid_word(dp0, aw[e], bw) : aw[e] + bw;
                     s_wd[o] = wd;
-                    s_f[o] = keep ? (uint16_t)((uint32_t)(key >> lt) & (uint32_t)(F - 1))
+                    s_f[o] = keep ? (uint16_t)((uint32_t)((uint64_t)key >> lt) & (uint32_t)(F - 1))
                                   : (uint16_t)0xFFFF;
                 }
                 off += n;
@@ -651,7 +745,7 @@ __device__ __forceinline__ void scatter_rec_body(
     if (fill > 0) flush(fill);
 }
 
-template <int W, int PER, int MAXF, bool FP, bool SLICE>
+template <int W, int PER, int MAXF, bool FP, bool SLICE, bool KW>
 __global__ __launch_bounds__(kRecNT) void k_scatter_rec(Plan p, const QRec<W> *__restrict__ A,
                                                        const QRec<W> *__restrict__ B,
                                                        const uint32_t *__restrict__ offB,
@@ -663,23 +757,26 @@ __global__ __launch_bounds__(kRecNT) void k_scatter_rec(Plan p, const QRec<W> *_
                                                        const uint32_t *__restrict__ preL,
                                                        const uint32_t *__restrict__ preR,
                                                        Rec<W> *recL, Rec<W> *recR, int64_t idx0) {
-    static_assert(W <= 1, "one-word records");
-    constexpr int BATCH = (MAXF > 2048 ? 7 : 8) * kRecNT;
+    static_assert(W <= 2, "one-word records, or two with a second key word");
+    constexpr int BATCH = rec_batch<W, MAXF>();
     static_assert(BATCH <= 65536, "batch slots must fit 16 bits");
     __shared__ uint32_t s_cur[MAXF];
     __shared__ uint32_t s_cnt[MAXF > kRecNT ? MAXF : kRecNT];
     __shared__ uint64_t s_hdr[BATCH];
     __shared__ uint32_t s_wd[BATCH];
+    __shared__ uint32_t s_kx[W == 2 ? BATCH : 1];
     __shared__ uint16_t s_f[BATCH];
     __shared__ uint16_t s_perm[BATCH];
     __shared__ uint32_t s_w4[kRecNT / 64];
     if (blockIdx.y == 0)
-        scatter_rec_body<W, PER, MAXF, FP, SLICE, 0>(p, A, B, offB, p.Q[0], offL, preL, recL, idx0,
-                                                     s_cur, s_cnt, s_hdr, s_wd, s_f, s_perm, s_w4);
+        scatter_rec_body<W, PER, MAXF, FP, SLICE, 0, KW>(p, A, B, offB, p.Q[0], offL, preL, recL,
+                                                         idx0, s_cur, s_cnt, s_hdr, s_wd, s_kx,
+                                                         s_f, s_perm, s_w4, p.qkh[0], p.qkh[1]);
     else
-        scatter_rec_body<W, PER, MAXF, FP, SLICE, 1>(p, Cq, Dq, offD, p.Q[2], offR, preR, recR,
-                                                     idx0, s_cur, s_cnt, s_hdr, s_wd, s_f, s_perm,
-                                                     s_w4);
+        scatter_rec_body<W, PER, MAXF, FP, SLICE, 1, KW>(p, Cq, Dq, offD, p.Q[2], offR, preR,
+                                                         recR, idx0, s_cur, s_cnt, s_hdr, s_wd,
+                                                         s_kx, s_f, s_perm, s_w4, p.qkh[2],
+                                                         p.qkh[3]);
 }
 
 // ---------------------------------------------------------------------------
@@ -941,7 +1038,7 @@ __global__ __launch_bounds__(256) void k_join_light(Plan p, const uint32_t *__re
             for (int u = 0; u < kLU; ++u) {
                 const uint32_t i = t + 256 * u;
                 if (i < nl) {
-                    s_key[i] = (KT)(cur.lh[u] >> p.hsh);
+                    s_key[i] = (KT)hkey(p, cur.lh[u], kword<W>(cur.lv[u]));
 #pragma unroll
                     for (int w = 0; w < WV; ++w) s_vec[w][i] = cur.lv[u][w];
                 }
@@ -987,7 +1084,7 @@ __global__ __launch_bounds__(256) void k_join_light(Plan p, const uint32_t *__re
 #pragma unroll
                 for (int e = 0; e < kPre; ++e) {
                     const uint32_t j = t + 256 * e;
-                    if (j < nr) probe((int64_t)(cur.rh[e] >> p.hsh), cur.rv[e], j);
+                    if (j < nr) probe((int64_t)hkey(p, cur.rh[e], kword<W>(cur.rv[e])), cur.rv[e], j);
                 }
                 for (uint32_t j = t + 256 * kPre; j < nr; j += 256) {
                     uint32_t v[WV];
@@ -1048,12 +1145,12 @@ __global__ __launch_bounds__(256) void k_join_pairs(Plan p, const uint32_t *__re
         }
         for (uint32_t i0 = 0; i0 < nl; i0 += 64) {
             const uint32_t ni = min(64u, nl - i0);
-            const KT lk = (KT)(L[l0 + i0 + min(lane, ni - 1)].hdr >> p.hsh);
+            const KT lk = (KT)rkey(p, L[l0 + i0 + min(lane, ni - 1)]);
             for (uint32_t j0 = 0; j0 < nr; j0 += 64) {
                 const bool rin = j0 + lane < nr;
                 const uint32_t rj = r0 + j0 + min(lane, nr - j0 - 1);
                 const uint64_t rh = R[rj].hdr;
-                const KT rk = (KT)(rh >> p.hsh);
+                const KT rk = (KT)rkey(p, R[rj]);
                 for (uint32_t i = 0; i < ni; ++i) {
                     const KT k = wave_bcast(lk, i);
                     if (rin && k == rk) {
@@ -1197,7 +1294,7 @@ __device__ __forceinline__ void grouped_bucket(const Plan &p, const uint32_t *__
         for (int u = 0; u < kLU; ++u) {
             const uint32_t i = t + NTJ * u;
             if (i < nl) {
-                s_key[i] = (KT)(lh[u] >> p.hsh);
+                s_key[i] = (KT)hkey(p, lh[u], kword<W>(lv[u]));
 #pragma unroll
                 for (int w = 0; w < WV; ++w) s_vec[w][i] = lv[u][w];
             }
@@ -1255,7 +1352,7 @@ __device__ __forceinline__ void grouped_bucket(const Plan &p, const uint32_t *__
 #pragma unroll
         for (int q = 0; q < kPre; ++q) {
             const uint32_t j = t + NTJ * q;
-            if (j < nr) probe_vj((int64_t)(rh[q] >> p.hsh), rv[q], j);
+            if (j < nr) probe_vj((int64_t)hkey(p, rh[q], kword<W>(rv[q])), rv[q], j);
         }
         for (uint32_t j = t + NTJ * kPre; j < nr; j += NTJ) {
             uint32_t v[WV];
@@ -1376,7 +1473,7 @@ __device__ __forceinline__ void grouped_bucket(const Plan &p, const uint32_t *__
 #pragma unroll
     for (int e = 0; e < kPre; ++e) {
         const uint32_t j = t + NTJ * e;
-        if (j < nr) probe((int64_t)(rh[e] >> p.hsh), rv[e], j);
+        if (j < nr) probe((int64_t)hkey(p, rh[e], kword<W>(rv[e])), rv[e], j);
     }
     for (uint32_t j = t + NTJ * kPre; j < nr; j += NTJ) {
         uint32_t v[WV];
@@ -1477,7 +1574,7 @@ __global__ __launch_bounds__(256) void k_join_heavy_vj(Plan p, const uint32_t *_
             for (int u = 0; u < kLU; ++u) {
                 const uint32_t i = t + 256 * u;
                 if (i < nl) {
-                    s_key[i] = (KT)(lh[u] >> p.hsh);
+                    s_key[i] = (KT)hkey(p, lh[u], kword<W>(lv[u]));
 #pragma unroll
                     for (int w = 0; w < WV; ++w) s_vec[w][i] = lv[u][w];
                 }
@@ -1521,7 +1618,7 @@ __global__ __launch_bounds__(256) void k_join_heavy_vj(Plan p, const uint32_t *_
                 if (j0 + 256u * u >= nr) break;
                 const uint64_t rhdr = rhs[u];
                 const uint32_t *v = rvs[u];
-                const int64_t key = (int64_t)(rhdr >> p.hsh);
+                const int64_t key = (int64_t)hkey(p, rhdr, kword<W>(v));
                 uint32_t h = key_hash(key) & smask;
                 bool found = false;
                 for (;;) {
@@ -1613,7 +1710,7 @@ __global__ __launch_bounds__(256) void k_join_heavy(Plan p, const uint32_t *__re
         for (int u = 0; u < kLU; ++u) {
             const uint32_t i = t + 256 * u;
             if (i < nl) {
-                s_key[i] = (int64_t)(lh[u] >> p.hsh);
+                s_key[i] = (int64_t)hkey(p, lh[u], kword<W>(lv[u]));
 #pragma unroll
                 for (int w = 0; w < WV; ++w) s_vec[w][i] = lv[u][w];
             }
@@ -1696,12 +1793,17 @@ __global__ __launch_bounds__(256) void k_join_heavy(Plan p, const uint32_t *__re
     constexpr int kRU = 4;
     for (uint32_t j0 = t; j0 < nr; j0 += 256 * kRU) {
         uint64_t rh[kRU];
+        uint32_t rx[kRU];
 #pragma unroll
-        for (int u = 0; u < kRU; ++u) rh[u] = R[r0 + min(j0 + 256u * u, nr - 1)].hdr;
+        for (int u = 0; u < kRU; ++u) {
+            const uint32_t rj = r0 + min(j0 + 256u * u, nr - 1);
+            rh[u] = R[rj].hdr;
+            rx[u] = kword<W>(R[rj].vec);
+        }
 #pragma unroll
         for (int u = 0; u < kRU; ++u) {
             if (j0 + 256u * u >= nr) break;
-            const uint32_t h = find((int64_t)(rh[u] >> p.hsh));
+            const uint32_t h = find((int64_t)hkey(p, rh[u], rx[u]));
             if (h != 0xFFFFu) {
                 const uint32_t g = (s_tab[h] & 0xFFFFu) - gstart(h);
                 hits += g;
@@ -1740,12 +1842,17 @@ __global__ __launch_bounds__(256) void k_join_heavy(Plan p, const uint32_t *__re
     }
     for (uint32_t j0 = t; j0 < nr; j0 += 256 * kRU) {
     uint64_t rh[kRU];
+    uint32_t rx[kRU];
 #pragma unroll
-    for (int u = 0; u < kRU; ++u) rh[u] = R[r0 + min(j0 + 256u * u, nr - 1)].hdr;
+    for (int u = 0; u < kRU; ++u) {
+        const uint32_t rj = r0 + min(j0 + 256u * u, nr - 1);
+        rh[u] = R[rj].hdr;
+        rx[u] = kword<W>(R[rj].vec);
+    }
     for (int u = 0; u < kRU; ++u) {
         const uint32_t j = j0 + 256u * u;
         if (j >= nr) break;
-        const uint32_t h = find((int64_t)(rh[u] >> p.hsh));
+        const uint32_t h = find((int64_t)hkey(p, rh[u], rx[u]));
         if (h == 0xFFFFu) continue;
         const uint32_t bi = s_bigidx[h];
         if (bi != 0xFFu) {
@@ -2208,8 +2315,13 @@ static hipError_t quarters_impl(const Plan &p, const DevBufs &b, hipStream_t st)
         vraw.q[x] = b.qvraw[x];
         vsrt.q[x] = b.qvsrt[x];
     }
-    hipLaunchKernelGGL(k_quarter_gen<W>, dim3(grid), dim3(256), 0, st, p, b.colw, b.rows, raw, cnt,
-                       vraw);
+    KPtrs khraw, khsrt;
+    for (int x = 0; x < 4; ++x) {
+        khraw.q[x] = b.qkhraw[x];
+        khsrt.q[x] = b.qkhsrt[x];
+    }
+    hipLaunchKernelGGL(k_quarter_gen<W>, dim3(grid), dim3(256), 0, st, p, b.colw, b.colwh, b.rows,
+                       raw, cnt, vraw, khraw);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t T = (size_t)1 << p.log2T;
@@ -2220,7 +2332,7 @@ static hipError_t quarters_impl(const Plan &p, const DevBufs &b, hipStream_t st)
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_quarter_sort<W>, dim3(grid), dim3(256), 0, st, p, raw, srt, cur, vraw,
-                       vsrt);
+                       vsrt, khraw, khsrt);
     return hipGetLastError();
 }
 
@@ -2240,25 +2352,36 @@ static hipError_t count_impl(const Plan &p, const DevBufs &b, int64_t idx0, int3
     dim3 grid((uint32_t)K * p.parts, 2);
     MSP_GRID_CHECK(grid, 256);
     const bool sl = p.slice_mod != 0;
-#define MSP_COUNT(PERV, KUV)                                                                    \
+#define MSP_COUNT_K(PERV, KUV, KWV)                                                             \
     do {                                                                                        \
         if (sl)                                                                                 \
-            hipLaunchKernelGGL((k_count<W, PERV, KUV, true>), grid, dim3(256), 0, st, p,        \
+            hipLaunchKernelGGL((k_count<W, PERV, KUV, true, KWV>), grid, dim3(256), 0, st, p,   \
                                (const QRec<W> *)b.qsrt[0], (const QRec<W> *)b.qsrt[1],          \
                                b.qcnt[1], (const QRec<W> *)b.qsrt[2],                           \
                                (const QRec<W> *)b.qsrt[3], b.qcnt[3], b.cnt[0], b.cnt[1], idx0, \
                                b.scal);                                                         \
         else                                                                                    \
-            hipLaunchKernelGGL((k_count<W, PERV, KUV, false>), grid, dim3(256), 0, st, p,       \
+            hipLaunchKernelGGL((k_count<W, PERV, KUV, false, KWV>), grid, dim3(256), 0, st, p,  \
                                (const QRec<W> *)b.qsrt[0], (const QRec<W> *)b.qsrt[1],          \
                                b.qcnt[1], (const QRec<W> *)b.qsrt[2],                           \
                                (const QRec<W> *)b.qsrt[3], b.qcnt[3], b.cnt[0], b.cnt[1], idx0, \
                                b.scal);                                                         \
     } while (0)
+    // Keys past int64 come with second-key-word records (two words).
+    if constexpr (W == 2) {
+        if (p.kw) {
+            if (qin >= 16 * T) MSP_COUNT_K(1, 8, true);
+            else if (qin > 2 * T) MSP_COUNT_K(4, 4, true);
+            else MSP_COUNT_K(4, 2, true);
+            return hipGetLastError();
+        }
+    }
+#define MSP_COUNT(PERV, KUV) MSP_COUNT_K(PERV, KUV, false)
     if (qin >= 16 * T) MSP_COUNT(1, 8);
     else if (qin > 2 * T) MSP_COUNT(4, 4);
     else MSP_COUNT(4, 2);
 #undef MSP_COUNT
+#undef MSP_COUNT_K
     return hipGetLastError();
 }
 
@@ -2316,7 +2439,7 @@ static hipError_t staged_impl(const Plan &p, const DevBufs &b, int64_t idx0, int
     return hipGetLastError();
 }
 
-template <int W, bool FP, bool SLICE>
+template <int W, bool FP, bool SLICE, bool KW = false>
 static hipError_t rec_impl(const Plan &p, const DevBufs &b, int64_t idx0, int32_t K,
                            hipStream_t st) {
     // Outer elements per thread per chunk: enough pairs (about Q_inner / T
@@ -2324,14 +2447,15 @@ static hipError_t rec_impl(const Plan &p, const DevBufs &b, int64_t idx0, int32_
     const uint64_t T = (uint64_t)1 << p.log2T;
     const uint64_t qin = std::min((uint64_t)p.Q[1], (uint64_t)p.Q[3]);
     const int F = 1 << p.log2F;
-    const uint64_t batch = (uint64_t)(F > 2048 ? 7 : 8) * kRecNT;
+    const uint64_t batch = F > 2048 ? rec_batch<W, 4096>() : rec_batch<W, 2048>();
     int per = 1;
     while (per < 4 && (uint64_t)kRecNT * (2 * per) * qin <= batch * T) per *= 2;
     if ((uint64_t)K * p.parts > 0xFFFFFFFFull) return hipErrorInvalidConfiguration;
     dim3 grid((uint32_t)K * p.parts, 2);
     MSP_GRID_CHECK(grid, kRecNT);
 #define MSP_REC(PERV, MF)                                                                       \
-    hipLaunchKernelGGL((k_scatter_rec<W, PERV, MF, FP, SLICE>), grid, dim3(kRecNT), 0, st, p,   \
+    hipLaunchKernelGGL((k_scatter_rec<W, PERV, MF, FP, SLICE, KW>), grid, dim3(kRecNT), 0, st,  \
+                       p,                                                                       \
                        (const QRec<W> *)b.qsrt[0], (const QRec<W> *)b.qsrt[1], b.qcnt[1],       \
                        (const QRec<W> *)b.qsrt[2], (const QRec<W> *)b.qsrt[3], b.qcnt[3],       \
                        b.off[0], b.off[1], b.pre[0], b.pre[1], (Rec<W> *)b.rec[0],              \
@@ -2357,6 +2481,14 @@ static hipError_t rec_impl(const Plan &p, const DevBufs &b, int64_t idx0, int32_
 hipError_t launch_scatter(const Plan &p, const DevBufs &b, int64_t idx0, int32_t K,
                           hipStream_t st) {
     const bool sl = p.slice_mod != 0;
+    if (p.wide) {                        // fingerprint + second key word
+        if (p.Wr != 2 || !p.fp) return hipErrorInvalidValue;
+        if (p.kw)
+            return sl ? rec_impl<2, true, true, true>(p, b, idx0, K, st)
+                      : rec_impl<2, true, false, true>(p, b, idx0, K, st);
+        return sl ? rec_impl<2, true, true, false>(p, b, idx0, K, st)
+                  : rec_impl<2, true, false, false>(p, b, idx0, K, st);
+    }
     if (p.Wr == 0)
         return sl ? rec_impl<0, false, true>(p, b, idx0, K, st)
                   : rec_impl<0, false, false>(p, b, idx0, K, st);

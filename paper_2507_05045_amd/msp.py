@@ -40,7 +40,7 @@ class msp_opts(C.Structure):
                 ("stream", C.c_void_p), ("first_only", C.c_int32), ("join_variant", C.c_int32),
                 ("verify_join", C.c_int32), ("key_base", C.c_int32),
                 ("row_fingerprint", C.c_int32), ("first_order", C.c_int32),
-                ("log2_outer", C.c_int32), ("reserved0", C.c_int32)]
+                ("log2_outer", C.c_int32), ("key_words", C.c_int32)]
 
 
 class msp_stats_t(C.Structure):
@@ -55,7 +55,7 @@ class msp_stats_t(C.Structure):
                 ("windows_total", C.c_uint64), ("join_grouped", C.c_int32),
                 ("key_base", C.c_int32), ("row_fingerprint", C.c_int32),
                 ("cells_done", C.c_uint64), ("window_order", C.c_int32), ("log2_outer", C.c_int32),
-                ("first_cell", C.c_uint64)]
+                ("first_cell", C.c_uint64), ("key_words", C.c_int32), ("key_bits", C.c_int32)]
 
 
 class msp_batch_opts(C.Structure):
@@ -70,7 +70,8 @@ class msp_plan_t(C.Structure):
                 ("log2_outer", C.c_int32), ("log2_inner", C.c_int32),
                 ("cells", C.c_uint64), ("cells_per_window", C.c_uint64), ("windows", C.c_uint64),
                 ("window_records", C.c_uint64), ("record_bytes", C.c_uint64),
-                ("workspace_bytes", C.c_uint64), ("max_grid_items", C.c_uint64)]
+                ("workspace_bytes", C.c_uint64), ("max_grid_items", C.c_uint64),
+                ("key_words", C.c_int32), ("key_bits", C.c_int32)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)

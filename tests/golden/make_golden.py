@@ -172,6 +172,9 @@ def batch_main():
 def _wide_job(job):
     (m, n), K, planted, r, kb, lm, rho = job
     inst = make_instance(m, n, 0, planted=planted, K=K)
+    if rho == "whole":                  # every class: the whole solve
+        res = O.mitm(inst.A, inst.d, r, lm, key_base=kb)
+        return entry(inst, r, res, routine=f"mitm whole, classes mod 2^{lm}", K=K, key_base=kb)
     if planted:
         rho = O.left_key(inst.A, inst.d, inst.planted, r, key_base=kb) % (1 << lm)
     res = O.mitm(inst.A, inst.d, r, lm, rho, rho + 1, key_base=kb)
@@ -179,20 +182,27 @@ def _wide_job(job):
 
 
 def wide_main():
-    """tests/golden/oracle_wide.json: residue classes of the plans whose
-    modulus the key room forces up (more cells than equal quarters have
-    inner elements): (11,100) with four key rows (Section 4's largest
-    class, K = 100 and K = 50), and (10,90) with five key rows in the mixed
-    radix.  Planted twins sample the class of x*."""
+    """tests/golden/oracle_wide.json: residue classes of (11,100) with four
+    key rows (Section 4's largest class, K = 100 and K = 50) and of (10,90)
+    with five key rows in the mixed radix (keys that one header word holds
+    only with a modulus of 2^40 - 2^41), of (10,90) with six (a 73-bit key),
+    and the (6,50) pair with six rows in radix n*D (72 bits) solved whole.
+    Planted twins sample the class of x*."""
     import multiprocessing as mp
     jobs = [((11, 100), 100, False, 4, 0, 30, 12345),
             ((11, 100), 100, True, 4, 0, 30, None),
             ((11, 100), 50, False, 4, 0, 30, 777),
             ((10, 90), 100, False, 5, 1, 24, 12345),
-            ((10, 90), 100, True, 5, 1, 24, None)]
+            ((10, 90), 100, True, 5, 1, 24, None),
+            # keys past int64: six mixed-radix rows at (10,90) (73 bits), and
+            # the (6,50) pair with six rows in radix n*D (72 bits), whole
+            ((10, 90), 100, False, 6, 1, 24, 12345),
+            ((10, 90), 100, True, 6, 1, 24, None),
+            ((6, 50), 100, False, 6, 0, 10, "whole"),
+            ((6, 50), 100, True, 6, 0, 10, "whole")]
     t0 = time.time()
-    with mp.get_context("fork").Pool(2) as pool:
-        out = pool.map(_wide_job, jobs)
+    with mp.get_context("fork").Pool(3) as pool:
+        out = pool.map(_wide_job, jobs, chunksize=1)
     for e in out:
         print(e["name"], e["slice_res"], e["H"], e["nsol"], flush=True)
     path = os.path.join(os.path.dirname(OUT), "oracle_wide.json")

@@ -52,7 +52,11 @@ def test_workspace_query_and_key_overflow():
     from paper_2507_05045_amd import msp
     ctx = msp.Context(np.full((9, 90), 99), [4455] * 9)
     assert ctx.workspace_bytes(msp.msp_default_opts(key_rows=4)) > 0
-    assert ctx.workspace_bytes(msp.msp_default_opts(key_rows=5)) == 0   # key overflows int64
+    # Five rows in radix 9000: a 66-bit key, past int64: two key words only.
+    assert ctx.workspace_bytes(msp.msp_default_opts(key_rows=5, key_words=1)) == 0
+    assert ctx.workspace_bytes(msp.msp_default_opts(key_rows=5)) > 0
+    # Eight rows: 105 bits, past the 96 the records can hold.
+    assert ctx.workspace_bytes(msp.msp_default_opts(key_rows=8)) == 0
     # A budget too small to hold even the quarter lists cannot be met.
     assert ctx.workspace_bytes(msp.msp_default_opts(key_rows=4, workspace_bytes=1 << 20)) == 0
     ctx.close()
@@ -100,15 +104,30 @@ def test_binding_structs_match_the_header(tmp_path, struct):
 
 
 def test_mixed_radix_key_fits_a_fifth_row():
-    """key_base = 1 (radix rowsum_i + 1) holds five key rows at (9,80) where
-    the radix n*D overflows int64; an unknown key_base is rejected."""
+    """key_base = 1 (radix rowsum_i + 1) holds five key rows at (9,80) in
+    int64 where the radix n*D needs more (then two key words, 128-bit sums);
+    an unknown key_base is rejected."""
     from paper_2507_05045_amd import msp
     from paper_2507_05045_amd.inputs import make_instance
     inst = make_instance(9, 80, 0)
     ctx = msp.Context(inst.A, inst.d)
-    assert ctx.workspace_bytes(msp.msp_default_opts(key_rows=5)) == 0
-    assert ctx.workspace_bytes(msp.msp_default_opts(key_rows=5, key_base=1)) > 0
+    assert ctx.workspace_bytes(msp.msp_default_opts(key_rows=5, key_words=1)) == 0
+    p = ctx.plan(key_rows=5)
+    assert p["key_words"] == 2 and p["record_bytes"] == 16     # sums reach past 2^63
+    p = ctx.plan(key_rows=5, key_base=1)
+    assert p["key_bits"] <= 63
+    # 60 bits: one word would need M = 2^36 (24 key bits per header)...
+    p1 = ctx.plan(key_rows=5, key_base=1, key_words=1)
+    assert (p1["key_words"], p1["log2_m"], p1["record_bytes"]) == (1, 36, 12)
+    # ... the planner takes a second word instead and keeps M = 2^30.
+    assert (p["key_words"], p["log2_m"], p["record_bytes"]) == (2, 30, 16)
     assert ctx.workspace_bytes(msp.msp_default_opts(key_rows=4, key_base=2)) == 0
+    with pytest.raises(msp.MspError) as e:
+        ctx.plan(key_rows=5, key_words=2, row_fingerprint=2)
+    assert e.value.code == -4
+    with pytest.raises(msp.MspError) as e:
+        ctx.plan(key_rows=4, key_words=3)
+    assert e.value.code == -1
     ctx.close()
 
 
@@ -220,12 +239,15 @@ def test_quarter_split_plans():
     p = ctx.plan(key_rows=4, slice_mod=4096)
     assert (p["log2_m"], p["log2_cells"], p["log2_outer"], p["log2_inner"]) == (40, 28, 22, 28)
     ctx.close()
-    # (10,90), five key rows in the mixed radix: a 60-bit key, 19 key bits
-    # per header, M = 2^41, 2^29 cells.
+    # (10,90), five key rows in the mixed radix: a 60-bit key.  With one key
+    # word (19 key bits per header) M = 2^41, 2^29 cells; the planner's
+    # choice keeps M = 2^35 with a second key word.
     i = make_instance(10, 90, 0)
     ctx = msp.Context(i.A, i.d)
-    p = ctx.plan(key_rows=5, key_base=1)
+    p = ctx.plan(key_rows=5, key_base=1, key_words=1)
     assert (p["log2_m"], p["log2_cells"], p["log2_outer"], p["log2_inner"]) == (41, 29, 17, 28)
+    p = ctx.plan(key_rows=5, key_base=1)
+    assert (p["log2_m"], p["log2_cells"], p["key_words"]) == (35, 23, 2)
     ctx.close()
 
 

@@ -520,22 +520,101 @@ def test_forced_modulus_plans_sampled_classes():
     (tests/golden/oracle_wide.json), with the planner's plan."""
     from paper_2507_05045_amd import msp
     with open(WIDE_GOLDEN) as f:
-        gold = json.load(f)
+        gold = [e for e in json.load(f) if e["key_rows"] in (4, 5)]
     assert len(gold) == 5
     for e in gold:
         inst = make_instance(e["m"], e["n"], e["seed"], planted=e["planted"], K=e["K"])
         assert inst.name == e["name"]
         r, kb = e["key_rows"], e["key_base"]
         ctx = msp.Context(inst.A, inst.d)
-        plan = ctx.plan(key_rows=r, key_base=kb)
+        plan = ctx.plan(key_rows=r, key_base=kb, key_words=1)
         assert plan["log2_cells"] >= 28 and plan["log2_outer"] < plan["log2_inner"], plan
-        for vj in ((0, 2) if r == 4 else (0,)):
+        # One key word (the forced modulus), and for five rows also the
+        # planner's plan (a second key word, M = 2^35).
+        for vj, kwd in (((0, 1), (2, 1)) if r == 4 else ((0, 1), (0, 0))):
             ctx.solve(key_rows=r, key_base=kb, slice_mod=e["slice_mod"],
-                      slice_res=e["slice_res"], verify_join=vj)
+                      slice_res=e["slice_res"], verify_join=vj, key_words=kwd)
             st = ctx.stats()
-            say("forced", e["name"], r, e["slice_res"], vj, ctx.hits(), e["H"],
-                st["log2_m"], st["log2_cells"], st["log2_outer"], st["ms_total"])
-            same(ctx.result(), _golden_result(e, e["n"]), f"{e['name']} r={r} vj={vj}")
+            say("forced", e["name"], r, e["slice_res"], vj, kwd, ctx.hits(), e["H"],
+                st["log2_m"], st["log2_cells"], st["log2_outer"], st["key_words"], st["ms_total"])
+            same(ctx.result(), _golden_result(e, e["n"]), f"{e['name']} r={r} vj={vj} words={kwd}")
             if inst.planted is not None:
                 assert any(np.array_equal(s, inst.planted) for s in ctx.solutions())
+        ctx.close()
+
+
+WIDE_SMALL = [
+    dict(m=7, n=22, K=100, r=6),
+    dict(m=7, n=22, K=100, r=7),            # r = m: every 1-D hit is a solution
+    dict(m=8, n=22, K=2, r=7),              # 0/1 rows: large equal-key groups
+    dict(m=8, n=24, K=3, r=7),
+]
+
+
+@pytest.mark.parametrize("case", WIDE_SMALL, ids=lambda c: "m{m}n{n}K{K}r{r}".format(**c))
+def test_keys_past_int64_vs_brute_force(case):
+    """Six or seven key rows in radix n*D (65-80-bit keys): 128-bit sums in
+    the count and scatter passes, a second key word per record, every join
+    variant and run check, and slices, against brute force."""
+    m, n, r = case["m"], case["n"], case["r"]
+    for seed in range(2):
+        inst = random_small(m, n, 700 + seed, K=case["K"], planted=seed == 0)
+        ref = O.brute(inst.A, inst.d, r)
+        plans = [dict(), dict(verify_join=1), dict(verify_join=2),
+                 dict(log2_m=16, log2_cells=6, join_variant=1, verify_join=2),
+                 dict(log2_m=16, log2_cells=8, join_variant=2),
+                 dict(log2_m=18, log2_cells=7, join_variant=3, verify_join=2),
+                 dict(log2_m=16, log2_cells=5, parts=3, window_records=1 << 12)]
+        for kw in plans:
+            g = gsolve(inst.A, inst.d, key_rows=r, **kw)
+            assert g.stats["key_words"] == 2 and g.stats["key_bits"] > 63
+            same(g, ref, f"{inst.name} r={r} {kw}")
+        if seed == 0:
+            assert any(np.array_equal(s_, inst.planted) for s_ in ref.solutions)
+        tot = 0
+        for res in range(4):
+            b = O.brute(inst.A, inst.d, r, slice_mod=4, slice_res=res)
+            g = gsolve(inst.A, inst.d, key_rows=r, slice_mod=4, slice_res=res)
+            same(g, b, f"{inst.name} r={r} slice {res}")
+            tot += g.H
+        assert tot == ref.H
+
+
+def test_second_key_word_for_header_room_vs_one_word():
+    """Keys that fit int64 but not one header (five mixed-radix rows at
+    (6,50)): two key words at the default modulus and one word with the
+    modulus forced up give the oracle's result."""
+    for e in _golden():
+        if (e["m"], e["n"], e["key_rows"], e.get("K", 100)) != (6, 50, 5, 100):
+            continue
+        inst = _golden_instance(e)
+        for kwd in (1, 2, 0):
+            g = gsolve(inst.A, inst.d, key_rows=5, key_base=1, key_words=kwd)
+            assert g.stats["key_words"] == (kwd or 2)
+            same(g, _golden_result(e, 50), f"{e['name']} key words {kwd}")
+
+
+def test_keys_past_int64_vs_oracle():
+    """Six key rows: the (6,50) pair in radix n*D (72 bits) solved whole, and
+    (10,90) in the mixed radix (73 bits) on sampled classes, against the
+    residue MITM oracle (tests/golden/oracle_wide.json)."""
+    from paper_2507_05045_amd import msp
+    with open(WIDE_GOLDEN) as f:
+        gold = [e for e in json.load(f) if e["key_rows"] == 6]
+    assert len(gold) == 4
+    for e in gold:
+        inst = make_instance(e["m"], e["n"], e["seed"], planted=e["planted"], K=e["K"])
+        assert inst.name == e["name"]
+        kb = e["key_base"]
+        ctx = msp.Context(inst.A, inst.d)
+        for kw in (dict(), dict(verify_join=2), dict(verify_join=1)):
+            ctx.solve(key_rows=6, key_base=kb, slice_mod=e["slice_mod"], slice_res=e["slice_res"],
+                      **kw)
+            st = ctx.stats()
+            say("past int64", e["name"], e["slice_res"], kw, ctx.hits(), e["H"], st["log2_m"],
+                st["key_bits"], st["ms_total"])
+            assert st["key_words"] == 2 and st["key_bits"] > 63
+            same(ctx.result(), _golden_result(e, e["n"]), f"{e['name']} {kw}")
+            if inst.planted is not None:
+                assert any(np.array_equal(s_, inst.planted) for s_ in ctx.solutions())
         ctx.close()
