@@ -1647,6 +1647,127 @@ __global__ __launch_bounds__(256) void k_join_heavy_vj(Plan p, const uint32_t *_
     if (t == 0) add_u128(&scal[S_H_LO], &scal[S_H_HI], tot);
 }
 
+// Vector join of the buckets over the grouped kernels' LDS capacity (few
+// keys with thousands of records each, as at (11,100)): 1024 threads, left
+// chunks of kHeavyCap records (not kGroupCap), so the whole right side is
+// read once per 5461 left records.  Two LDS tables hold no left records: a
+// key table (key -> left count) gives every right record its |G_L| for H,
+// and a set of 32-bit tags of (key, words) flags the right records that may
+// match a left record exactly; only those scan the chunk's left records (in
+// global memory) for the equal ones.  Keys are stored as themselves, so the
+// all-ones word marks an empty slot: K32 needs key >> log2M < 2^31, the
+// 64-bit form < 2^63.
+constexpr uint32_t kHeavySlots = 8192;
+constexpr uint32_t kHeavyCap = kHeavySlots * 2 / 3;   // 5461
+
+template <int W>
+__device__ __forceinline__ uint32_t rec_tag(uint64_t key, const uint32_t *v) {
+    uint64_t h = key * 0x9E3779B97F4A7C15ull;
+#pragma unroll
+    for (int w = 0; w < (W > 0 ? W : 1); ++w) h = (h ^ v[w]) * 0xC2B2AE3D27D4EB4Full;
+    return (uint32_t)(h >> 32) | 1u;                  // 0 marks an empty slot
+}
+
+template <int W, bool K32>
+__global__ __launch_bounds__(1024) void k_join_heavy_vj2(Plan p,
+                                                        const uint32_t *__restrict__ offL,
+                                                        const uint32_t *__restrict__ offR,
+                                                        const Rec<W> *__restrict__ L,
+                                                        const Rec<W> *__restrict__ R,
+                                                        const uint32_t *__restrict__ heavy,
+                                                        uint64_t *scal, uint64_t *sol,
+                                                        uint64_t cap, QPtrs<W> qs, int hslot) {
+    using KT = typename std::conditional<K32, uint32_t, unsigned long long>::type;
+    constexpr KT kEmptyKey = (KT)~(KT)0;
+    constexpr uint32_t kMask = kHeavySlots - 1;
+    constexpr int WV = W > 0 ? W : 1;
+    __shared__ KT s_kk[kHeavySlots];
+    __shared__ uint32_t s_kc[kHeavySlots];
+    __shared__ uint32_t s_tag[kHeavySlots];
+    __shared__ uint64_t s_s[16];
+    const int t = threadIdx.x;
+    const uint32_t nheavy = (uint32_t)scal[hslot];
+    uint64_t hits = 0;
+    for (uint32_t hb = blockIdx.x; hb < nheavy; hb += gridDim.x) {
+        const uint32_t b = heavy[hb];
+        const uint32_t L0 = offL[b], L1 = offL[b + 1];
+        const uint32_t r0 = offR[b], nr = offR[b + 1] - r0;
+        for (uint32_t c0 = L0; c0 < L1; c0 += kHeavyCap) {
+            const uint32_t c1 = min(L1, c0 + kHeavyCap);
+            __syncthreads();                             // previous chunk done with LDS
+            for (uint32_t i = t; i < kHeavySlots; i += 1024) {
+                s_kk[i] = kEmptyKey;
+                s_kc[i] = 0;
+                s_tag[i] = 0;
+            }
+            __syncthreads();
+            for (uint32_t i = c0 + t; i < c1; i += 1024) {
+                const Rec<W> r = L[i];
+                const uint64_t k64 = hkey(p, r.hdr, kword<W>(r.vec));
+                const KT k = (KT)k64;
+                uint32_t h = khash((uint32_t)k64 ^ (uint32_t)(k64 >> 32)) & kMask;
+                for (;;) {                               // at most two-thirds full
+                    const KT cur = s_kk[h];
+                    if (cur == k) break;
+                    if (cur == kEmptyKey) {
+                        const KT old = atomicCAS(&s_kk[h], kEmptyKey, k);
+                        if (old == kEmptyKey || old == k) break;
+                    }
+                    h = (h + 1) & kMask;
+                }
+                atomicAdd(&s_kc[h], 1u);
+                const uint32_t tag = rec_tag<W>(k64, r.vec);
+                uint32_t g = tag & kMask;
+                for (;;) {
+                    const uint32_t cur = s_tag[g];
+                    if (cur == tag) break;
+                    if (cur == 0u) {
+                        const uint32_t old = atomicCAS(&s_tag[g], 0u, tag);
+                        if (old == 0u || old == tag) break;
+                    }
+                    g = (g + 1) & kMask;
+                }
+            }
+            __syncthreads();
+            for (uint32_t j = t; j < nr; j += 1024) {
+                const Rec<W> rr = R[r0 + j];
+                const uint64_t k64 = hkey(p, rr.hdr, kword<W>(rr.vec));
+                const KT k = (KT)k64;
+                uint32_t h = khash((uint32_t)k64 ^ (uint32_t)(k64 >> 32)) & kMask;
+                uint32_t cnt = 0;
+                for (;;) {
+                    const KT cur = s_kk[h];
+                    if (cur == k) { cnt = s_kc[h]; break; }
+                    if (cur == kEmptyKey) break;
+                    h = (h + 1) & kMask;
+                }
+                if (cnt == 0) continue;
+                hits += cnt;
+                const uint32_t tag = rec_tag<W>(k64, rr.vec);
+                bool cand = false;
+                for (uint32_t g = tag & kMask;; g = (g + 1) & kMask) {
+                    const uint32_t cur = s_tag[g];
+                    if (cur == tag) { cand = true; break; }
+                    if (cur == 0u) break;
+                }
+                if (!cand) continue;
+                // A possible exact match: the chunk's left records with the
+                // same key and words (rare: solutions and fingerprint ties).
+                for (uint32_t i = c0; i < c1; ++i) {
+                    const Rec<W> l = L[i];
+                    if (hkey(p, l.hdr, kword<W>(l.vec)) != k64) continue;
+                    bool ok = true;
+#pragma unroll
+                    for (int w = 0; w < WV; ++w) ok = ok && (l.vec[w] == rr.vec[w]);
+                    if (ok) emit_pair(p, qs, sol, cap, &scal[S_NSOL], l.hdr, rr.hdr);
+                }
+            }
+        }
+    }
+    const uint64_t tot = block_sum_u64<1024>(hits, s_s);
+    if (t == 0 && tot) add_u128(&scal[S_H_LO], &scal[S_H_HI], tot);
+}
+
 template <int W>
 __global__ __launch_bounds__(256) void k_join_heavy(Plan p, const uint32_t *__restrict__ offL,
                                                    const uint32_t *__restrict__ offR,
@@ -2530,7 +2651,7 @@ static hipError_t join_impl(const Plan &p, const DevBufs &b, int32_t K, uint64_t
     if (p.vjoin || p.join_grouped == 1) MSP_GRID_CHECK(dim3(nb), p.gbig ? 1024 : 256);
 #define MSP_GROUPED(K32V, VJV)                                                                  \
     do {                                                                                        \
-        if constexpr (W <= 1) {                                                                 \
+        if constexpr (W <= 2) {                                                                 \
             if (p.gbig) {                                                                       \
                 hipLaunchKernelGGL((k_join_grouped<W, K32V, VJV, 1024, kGroupCapBig,            \
                                                    kGroupSlotsBig>),                            \
@@ -2571,7 +2692,7 @@ static hipError_t join_impl(const Plan &p, const DevBufs &b, int32_t K, uint64_t
     // Second pass over the buckets the 256-thread grouped join deferred:
     // 1024-thread groups for those of up to kGroupCapBig left records.
     bool second = false;
-    if constexpr (W <= 1) {
+    if constexpr (W <= 2) {
         if ((p.vjoin || p.join_grouped == 1) && !p.gbig) {
             second = true;
             const dim3 g2(std::min<uint32_t>(nb, 512));
@@ -2591,7 +2712,15 @@ static hipError_t join_impl(const Plan &p, const DevBufs &b, int32_t K, uint64_t
     // device).
     uint32_t *hl = second ? b.heavy2 : b.heavy;
     const int hs = second ? (int)S_NHEAVY2 : (int)S_NHEAVY;
-    if (p.vjoin && p.khb <= 32)
+    if (p.vjoin && p.khb <= 31)
+        hipLaunchKernelGGL((k_join_heavy_vj2<W, true>), dim3(std::min<uint32_t>(nb, 1024)),
+                           dim3(1024), 0, st, p, b.off[0], b.off[1], L, R, hl, b.scal, b.sol, cap,
+                           sorted_quarters<W>(b), hs);
+    else if (p.vjoin && p.khb <= 63)
+        hipLaunchKernelGGL((k_join_heavy_vj2<W, false>), dim3(std::min<uint32_t>(nb, 1024)),
+                           dim3(1024), 0, st, p, b.off[0], b.off[1], L, R, hl, b.scal, b.sol, cap,
+                           sorted_quarters<W>(b), hs);
+    else if (p.vjoin && p.khb <= 32)
         hipLaunchKernelGGL((k_join_heavy_vj<W, true>), dim3(std::min<uint32_t>(nb, 2048)), dim3(256),
                            0, st, p, b.off[0], b.off[1], L, R, hl, b.scal, b.sol, cap,
                            sorted_quarters<W>(b), hs);
