@@ -183,9 +183,9 @@ def run_stream(args):
 
 def stream_results(count, closed_loop=True):
     """Uneven stream (m in {5..8}, n = 10(m-1), r = m - 4, odd instances
-    planted): plain one-at-a-time solves, one batched solve, and a served run
-    with Poisson arrivals at twice the plain rate, plus a closed-loop served
-    run with every request at t = 0."""
+    planted): plain one-at-a-time solves, one batched solve, served runs
+    with Poisson arrivals at twice the plain rate and at the plain rate, plus
+    a closed-loop served run with every request at t = 0."""
     import threading
     import torch
     from paper_2507_05045_amd import autotune, msp
@@ -286,6 +286,10 @@ def stream_results(count, closed_loop=True):
     rate = 2.0 * plain["instances_per_s"]
     poisson = served(poisson_arrivals(len(insts), rate, seed=7))
     poisson["rate_per_s"] = rate
+    # The plain path's own offered load (its throughput): served latency
+    # against plain latency at the same arrival rate.
+    same = served(poisson_arrivals(len(insts), plain["instances_per_s"], seed=8))
+    same["rate_per_s"] = plain["instances_per_s"]
     closed = served([0.0] * len(insts)) if closed_loop else None
     ms = [int(i.m) for i in insts]
     out = {
@@ -298,7 +302,8 @@ def stream_results(count, closed_loop=True):
                                "n = 10(m-1), key rows m-4, odd instances planted",
                    "instances": len(insts)},
         "hits_total": hits,
-        "plain": plain, "batched": batched, "served_poisson": poisson, "served_closed": closed,
+        "plain": plain, "batched": batched, "served_poisson": poisson,
+        "served_poisson_plain_rate": same, "served_closed": closed,
         "speedup_vs_plain": {"batched": t_plain / t_batch,
                              "served_closed": t_plain / closed["makespan_s"] if closed else None},
     }
