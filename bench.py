@@ -237,6 +237,9 @@ def stream_results(count, closed_loop=True):
 
     # Batched: msp_batch_solve over the stream, in calls of at most 128
     # instances (each call reports when it ends).
+    # Batched and served arenas come from PyTorch's caching allocator as well
+    # (msp_set_allocator), so each batch call does not allocate its own.
+    arena = msp.TorchArena().__enter__()
     ctxs = [msp.Context(i.A, i.d) for i in insts]
     t0 = time.perf_counter()
     for k0 in range(0, len(ctxs), 128):
@@ -294,6 +297,7 @@ def stream_results(count, closed_loop=True):
     same = served(poisson_arrivals(len(insts), plain["instances_per_s"], seed=8))
     same["rate_per_s"] = plain["instances_per_s"]
     closed = served([0.0] * len(insts)) if closed_loop else None
+    arena.__exit__(None, None, None)
     ms = [int(i.m) for i in insts]
     out = {
         "metric": "1-D hits verified/s (served stream) + p50/p99 latency",
