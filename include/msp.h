@@ -52,7 +52,8 @@ extern "C" {
 #define MSP_E_RANGE        (-2)  /* some row sum exceeds 65534 (uint16 row packing)    */
 #define MSP_E_KEY_OVERFLOW (-3)  /* largest key >= 2^96, or >= 2^63 with key_words = 1 */
 #define MSP_E_UNSUPPORTED  (-4)  /* m > 16, n > 100, m - r > 10, or > 2^29 cells needed*/
-#define MSP_E_NOMEM        (-5)  /* device workspace does not fit the budget            */
+#define MSP_E_NOMEM        (-5)  /* workspace does not fit the budget, or a residue
+                                    bucket holds 2^32 or more records                  */
 #define MSP_E_DEVICE       (-6)  /* HIP runtime error; the context is poisoned          */
 #define MSP_E_CANCELLED    (-7)  /* solve cancelled                                     */
 #define MSP_E_TRUNCATED    (-8)  /* caller buffer smaller than the result               */

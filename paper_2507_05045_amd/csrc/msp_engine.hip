@@ -699,8 +699,8 @@ int enqueue_count(Job &j) {
     const uint64_t nbk = (uint64_t)j.K << p.log2F;
     for (int sd = 0; sd < 2; ++sd)
         JCHK(scan_counts(j.b.cnt[sd], j.b.pre[sd], j.b.tot[sd], j.b.off[sd], nbk, F, P,
-                         &j.b.scal[sd ? S_TOT_R : S_TOT_L], j.b.scan_tmp, j.b.scan_tmp_bytes,
-                         j.s));
+                         &j.b.scal[sd ? S_TOT_R : S_TOT_L], &j.b.scal[S_OVF], j.b.scan_tmp,
+                         j.b.scan_tmp_bytes, j.s));
     JCHK(ev_rec(j, E_C2));
     JCHK(hipMemcpyAsync(j.hs, j.b.scal, S_COUNT * 8, hipMemcpyDeviceToHost, j.s));
     return MSP_OK;
@@ -741,8 +741,8 @@ int job_step(Job &j) {
                     const uint64_t nbk = j.K << p.log2F;
                     for (int sd = 0; sd < 2; ++sd)
                         JCHK(scan_counts(j.b.cnt[sd], j.b.pre[sd], j.b.tot[sd], j.b.off[sd], nbk,
-                                         1u << p.log2F, (uint32_t)p.parts, nullptr, j.b.scan_tmp,
-                                         j.b.scan_tmp_bytes, j.s));
+                                         1u << p.log2F, (uint32_t)p.parts, nullptr,
+                                         &j.b.scal[S_OVF], j.b.scan_tmp, j.b.scan_tmp_bytes, j.s));
                     JCHK(launch_window_score(j.b, nbk, j.b.wscore + w, j.s));
                 }
                 j.scores.assign(nwin, 0);
@@ -789,9 +789,10 @@ int job_step(Job &j) {
                 j.next = A_FINAL1;
                 return MSP_OK;
             }
-            // A work-group whose 32-bit bucket counters could wrap: no window
-            // split helps (one cell, one part), so the solve does not fit.
-            if (j.hs[S_OVF]) return MSP_E_NOMEM;
+            // A work-group whose 32-bit bucket counters could wrap, or a
+            // bucket of 2^32 or more records: no window split helps (one
+            // bucket cannot be divided), so the solve does not fit.
+            if (j.hs[S_OVF] & 5) return MSP_E_NOMEM;
             // Window totals are exact 64-bit sums; the scatter runs only when
             // both fit the record buffers (offsets are 32-bit below cap_rec).
             const uint64_t totL = j.hs[S_TOT_L], totR = j.hs[S_TOT_R];

@@ -124,7 +124,9 @@ struct DevBufs {
 
 // Slots of DevBufs::scal.
 // S_OVF is set by the count pass when one work-group enumerates 2^32 or more
-// pairs (its 32-bit bucket counters would wrap).
+// pairs (its 32-bit bucket counters would wrap: bit 1), by the offset pass
+// when a bucket's parts add up to 2^32 or more records (bit 4), and when a
+// run pair needs 2^32 or more verify tiles (bit 2).
 // S_NHEAVY2 counts the buckets the second join pass (big-bucket groups)
 // defers to the heavy kernels.
 enum Scal {
@@ -160,9 +162,10 @@ size_t scan_tmp_bytes(size_t n);
 // Offsets of the count pass's part-major counts (nbk = cells x F buckets):
 // per-part prefixes within each bucket to `pre`, bucket totals to `tot`, and
 // bucket starts to `start` (start[nbk] = total, also to *total64 exactly).
+// A bucket total of 2^32 or more sets bit 4 of *ovf (S_OVF).
 hipError_t scan_counts(const uint32_t *cnt, uint32_t *pre, uint32_t *tot, uint32_t *start,
-                       uint64_t nbk, uint32_t F, uint32_t P, uint64_t *total64, void *tmp,
-                       size_t tmp_bytes, hipStream_t st);
+                       uint64_t nbk, uint32_t F, uint32_t P, uint64_t *total64, uint64_t *ovf,
+                       void *tmp, size_t tmp_bytes, hipStream_t st);
 
 size_t qrec_bytes(int W);
 size_t rec_bytes(int W);

@@ -2278,30 +2278,34 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *__restrict__
 // exclusive prefix within the bucket to pre[cell][part][fine] and the
 // bucket's total to tot[cell][fine] (lanes take consecutive buckets, so every
 // access is coalesced).  A scan of tot then gives each bucket's start.
+// A bucket of 2^32 or more records (its parts' counts summed) cannot be
+// addressed by the 32-bit offsets: bit 4 of *ovf, and the solve stops.
 __global__ __launch_bounds__(256) void k_part_prefix(const uint32_t *__restrict__ cnt,
                                                      uint32_t *pre, uint32_t *tot, uint64_t nbk,
-                                                     uint32_t F, uint32_t P) {
+                                                     uint32_t F, uint32_t P, uint64_t *ovf) {
     const uint64_t bk = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (bk >= nbk) return;
     const uint64_t c = bk / F, f = bk - c * F;
     const uint64_t base = c * P * F + f;
-    uint32_t run = 0, p = 0;
+    uint64_t run = 0;
+    uint32_t p = 0;
     for (; p + 4 <= P; p += 4) {              // four independent loads in flight
         uint32_t v[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) v[u] = cnt[base + (uint64_t)(p + u) * F];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            pre[base + (uint64_t)(p + u) * F] = run;
+            pre[base + (uint64_t)(p + u) * F] = (uint32_t)run;
             run += v[u];
         }
     }
     for (; p < P; ++p) {
         const uint32_t v = cnt[base + (uint64_t)p * F];
-        pre[base + (uint64_t)p * F] = run;
+        pre[base + (uint64_t)p * F] = (uint32_t)run;
         run += v;
     }
-    tot[bk] = run;
+    tot[bk] = (uint32_t)run;
+    if (run > 0xFFFFFFFFull) atomicOr((unsigned long long *)ovf, 4ull);
 }
 
 size_t scan_tmp_bytes(size_t n) {
@@ -2343,12 +2347,12 @@ hipError_t scan_u32(const uint32_t *in, uint32_t *out, size_t n, uint64_t *total
 }
 
 hipError_t scan_counts(const uint32_t *cnt, uint32_t *pre, uint32_t *tot, uint32_t *start,
-                       uint64_t nbk, uint32_t F, uint32_t P, uint64_t *total64, void *tmp,
-                       size_t tmp_bytes, hipStream_t st) {
+                       uint64_t nbk, uint32_t F, uint32_t P, uint64_t *total64, uint64_t *ovf,
+                       void *tmp, size_t tmp_bytes, hipStream_t st) {
     if (nbk == 0) return scan_u32(tot, start, 0, total64, tmp, tmp_bytes, st);
     const dim3 g((uint32_t)((nbk + 255) / 256));
     MSP_GRID_CHECK(g, 256);
-    hipLaunchKernelGGL(k_part_prefix, g, dim3(256), 0, st, cnt, pre, tot, nbk, F, P);
+    hipLaunchKernelGGL(k_part_prefix, g, dim3(256), 0, st, cnt, pre, tot, nbk, F, P, ovf);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return scan_u32(tot, start, nbk, total64, tmp, tmp_bytes, st);

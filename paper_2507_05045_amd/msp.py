@@ -21,6 +21,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libmsp.so")
 
 MSP_OK = 0
+MSP_E_NOMEM = -5
 MSP_E_DEVICE = -6
 MSP_E_CANCELLED = -7
 MSP_E_TRUNCATED = -8

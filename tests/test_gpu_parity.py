@@ -618,3 +618,33 @@ def test_keys_past_int64_vs_oracle():
             if inst.planted is not None:
                 assert any(np.array_equal(s_, inst.planted) for s_ in ctx.solutions())
         ctx.close()
+
+
+def test_bucket_of_2_32_records_is_refused():
+    """A residue bucket whose parts add up to 2^32 or more records (one key
+    value shared by C(43,11) = 5.75e9 left halves: 43 columns of weight 1,
+    42 of weight 64, d = 51) cannot be addressed by 32-bit offsets: the
+    solve returns MSP_E_NOMEM from the offset pass, before any scatter, and
+    the context stays usable.  Every right key is 51 mod 64, so the right
+    side of cell 11 enumerates nothing and each part's left count (C(43,11)
+    / 64 parts) stays below 2^32: only the bucket's sum over parts wraps."""
+    from paper_2507_05045_amd import msp
+    A = np.zeros((1, 85), np.int32)
+    A[0, :43] = 1
+    A[0, 43:] = 64
+    ctx = msp.Context(A, [51])
+    p = ctx.plan(key_rows=1, verify_join=2, slice_mod=64, slice_res=11)
+    assert p["parts"] > 1 and p["cells"] == 1          # each part's counts stay below 2^32
+    say("bucket of 5.75e9 records")
+    with pytest.raises(msp.MspError) as e:
+        ctx.solve(key_rows=1, verify_join=2, slice_mod=64, slice_res=11)
+    assert e.value.code == msp.MSP_E_NOMEM
+    # Not a device error: the context is not poisoned (the same answer
+    # again), and the GPU goes on solving.
+    with pytest.raises(msp.MspError) as e:
+        ctx.solve(key_rows=1, verify_join=2, slice_mod=64, slice_res=11)
+    assert e.value.code == msp.MSP_E_NOMEM
+    ctx.close()
+    inst = make_instance(4, 30, 0, planted=True)
+    g = gsolve(inst.A, inst.d, key_rows=1)
+    assert any(np.array_equal(s_, inst.planted) for s_ in g.solutions)
