@@ -481,7 +481,9 @@ def main():
     else:
         join_k = ("k_join_light", "k_join_grouped", "k_join_pairs")[flat[0]["join_grouped"]]
         # One-word records (fingerprint or one packed word) take k_scatter_rec.
-        scat_k = "k_scatter_rec" if flat[0]["record_bytes"] <= 12 else "k_scatter_staged"
+        # (and fingerprint records with a second key word, 16 bytes).
+        scat_k = ("k_scatter_rec" if flat[0]["record_bytes"] <= 12 or flat[0]["row_fingerprint"]
+                  else "k_scatter_staged")
         key = {"ms_scatter": scat_k, "ms_join": join_k,
                "ms_count": "k_count", "ms_quarters": "k_quarter_gen"}.get(dom, dom)
         bytes_per_launch = records * rec_bytes / max(windows, 1)
