@@ -482,8 +482,6 @@ def main():
         join_k = ("k_join_light", "k_join_grouped", "k_join_pairs")[flat[0]["join_grouped"]]
         # One-word records (fingerprint or one packed word) and fingerprint
         # records with a second key word (16 bytes) take k_scatter_rec.
-
-
         scat_k = ("k_scatter_rec" if flat[0]["record_bytes"] <= 12 or flat[0]["row_fingerprint"]
                   else "k_scatter_staged")
         key = {"ms_scatter": scat_k, "ms_join": join_k,
