@@ -1451,14 +1451,23 @@ __device__ __forceinline__ void grouped_bucket(const Plan &p, const uint32_t *__
             return;
         }
         // Eight first words in flight per step; the rest of a word vector is
-        // read only where the first word matches.
+        // read only where the first word matches.  A first word equal to v[0]
+        // is rare (the fingerprint of a probable solution), so each step
+        // tests the eight differences for a zero by their minimum and builds
+        // the match mask, bounded by the group end, only when one is zero;
+        // the words past the group end (a next group, or the padding) can
+        // only send a step to that slower test.
         for (uint32_t q0 = gs; q0 < ge; q0 += 8) {
+            const uint32_t *sv = &s_vec[0][q0];                   // padded past nl
             uint32_t x[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) x[u] = s_vec[0][q0 + u];   // padded past nl
+            for (int u = 0; u < 8; ++u) x[u] = sv[u] ^ v[0];
+            const uint32_t mn = min(min(min(x[0], x[1]), min(x[2], x[3])),
+                                    min(min(x[4], x[5]), min(x[6], x[7])));
+            if (mn != 0u) continue;
             uint32_t m = 0;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) m |= (uint32_t)(x[u] == v[0] && q0 + u < ge) << u;
+            for (int u = 0; u < 8; ++u) m |= (uint32_t)(x[u] == 0u && q0 + u < ge) << u;
             while (m) {
                 const uint32_t q = q0 + __builtin_ctz(m);
                 m &= m - 1;
