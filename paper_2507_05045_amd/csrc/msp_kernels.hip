@@ -696,79 +696,43 @@ __device__ __forceinline__ void scatter_rec_body(
             const uint32_t nb = min((uint32_t)BATCH - fill, total - P0);
             // Stage my pairs whose index falls in [P0, P0 + nb), records
             // whole, at slots fill + (index - P0).
-            uint32_t qlo[PER], qhi[PER], obase[PER], umax = 0;
-            {
-                uint32_t off = myoff;
+            uint32_t off = myoff;
 #pragma unroll
-                for (int e = 0; e < PER; ++e) {
-                    const uint32_t n = nn[e];
-                    qlo[e] = off >= P0 ? 0u : min(n, P0 - off);
-                    qhi[e] = (off + n <= P0 + nb) ? n : (P0 + nb > off ? P0 + nb - off : 0u);
-                    obase[e] = fill + off - P0;
-                    umax = max(umax, qhi[e] - qlo[e]);
-                    off += n;
-                }
-            }
-            // The record of pair (outer element e, inner element b0[e] + q).
-            auto stage = [&](const int e, const uint32_t q, const int64_t bk, const uint32_t bw,
-                             const int64_t bh) {
-                const uint64_t qi = b0[e] + q;
+            for (int e = 0; e < PER; ++e) {
+                const uint32_t n = nn[e];
+                const uint32_t qa0 = off >= P0 ? 0u : min(n, P0 - off);
+                const uint32_t qb0 = (off + n <= P0 + nb) ? n : (P0 + nb > off ? P0 + nb - off : 0u);
                 const uint64_t ai = c0 + (uint64_t)e * NT + t;
-                int64_t key;
-                bool keep;
-                uint64_t c;                       // key >> log2M
-                if (KW) {
-                    uint64_t l;
-                    int64_t h;
-                    keep = key128<SIDE>(p, (uint64_t)akey[e], akh[e], (uint64_t)bk, bh, l, h);
-                    key = (int64_t)l;
-                    c = (l >> lm) | ((uint64_t)h << (64 - lm));
-                } else {
-                    key = SIDE ? akey[e] - bk : akey[e] + bk;
-                    keep = SIDE ? key >= 0 : key <= Kd;
-                    c = (uint64_t)key >> lm;
-                }
-                if (SLICE) keep = keep && ((key & smod1) == sres);
-                const uint32_t o = obase[e] + q;
-                s_hdr[o] = ai | (qi << qa) | (c << hsh);
-                if constexpr (W == 2) s_kx[o] = (uint32_t)(c >> (64 - hsh));
-                uint32_t wd;
-                if (FP) wd = SIDE ? hd - aw[e] - bw : aw[e] + bw;
-                else wd = SIDE ? resid_word(dp0, aw[e], bw) : aw[e] + bw;
-                s_wd[o] = wd;
-                s_f[o] = keep ? (uint16_t)((uint32_t)((uint64_t)key >> lt) & (uint32_t)(F - 1))
-                              : (uint16_t)0xFFFF;
-            };
-            if constexpr (KW) {
-                // 128-bit keys: the high words leave no registers for loads
-                // of several elements at once.
-#pragma unroll
-                for (int e = 0; e < PER; ++e)
-                    for (uint32_t q = qlo[e]; q < qhi[e]; ++q) {
-                        const uint64_t qi = b0[e] + q;
-                        stage(e, q, inner[qi].key, inner[qi].vec[0], ikh[qi]);
+                for (uint32_t q = qa0; q < qb0; ++q) {
+                    const uint64_t qi = b0[e] + q;
+                    const int64_t bk = inner[qi].key;
+                    const uint32_t bw = inner[qi].vec[0];
+                    int64_t key;
+                    bool keep;
+                    uint64_t c;                   // key >> log2M
+                    if (KW) {
+                        uint64_t l;
+                        int64_t h;
+                        keep = key128<SIDE>(p, (uint64_t)akey[e], akh[e], (uint64_t)bk, ikh[qi], l, h);
+                        key = (int64_t)l;
+                        c = (l >> lm) | ((uint64_t)h << (64 - lm));
+                    } else {
+                        key = SIDE ? akey[e] - bk : akey[e] + bk;
+                        keep = SIDE ? key >= 0 : key <= Kd;
+                        c = (uint64_t)key >> lm;
                     }
-            } else {
-                // Step u takes the u-th pair of each of my outer elements, so
-                // the PER inner loads of a step are in flight together and a
-                // lane waits on about as many loads as its largest inner cell
-                // holds, not on all its pairs in turn.  A lane with no u-th
-                // pair of an element reads inner element 0 (a quarter list is
-                // never empty) and ignores it.
-                for (uint32_t u = 0; u < umax; ++u) {
-                    int64_t bk[PER];
-                    uint32_t bw[PER];
-#pragma unroll
-                    for (int e = 0; e < PER; ++e) {
-                        const uint32_t q = qlo[e] + u;
-                        const uint64_t qi = q < qhi[e] ? b0[e] + q : 0u;
-                        bk[e] = inner[qi].key;
-                        bw[e] = inner[qi].vec[0];
-                    }
-#pragma unroll
-                    for (int e = 0; e < PER; ++e)
-                        if (qlo[e] + u < qhi[e]) stage(e, qlo[e] + u, bk[e], bw[e], 0);
+                    if (SLICE) keep = keep && ((key & smod1) == sres);
+                    const uint32_t o = fill + off + q - P0;
+                    s_hdr[o] = ai | (qi << qa) | (c << hsh);
+                    if constexpr (W == 2) s_kx[o] = (uint32_t)(c >> (64 - hsh));
+                    uint32_t wd;
+                    if (FP) wd = SIDE ? hd - aw[e] - bw : aw[e] + bw;
+                    else wd = SIDE ? resid_word(dp0, aw[e], bw) : aw[e] + bw;
+                    s_wd[o] = wd;
+                    s_f[o] = keep ? (uint16_t)((uint32_t)((uint64_t)key >> lt) & (uint32_t)(F - 1))
+                                  : (uint16_t)0xFFFF;
                 }
+                off += n;
             }
             fill += nb;
             P0 += nb;
