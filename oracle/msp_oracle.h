@@ -44,9 +44,13 @@
  * keys past int64 (tests/test_oracle_wide.py) it equals brute force (r = 6, 7
  * at n = 22, two moduli, a split range), the mixed radix on the same rows
  * (where the key fits int64 and keys are compared directly), and its slices
- * partition the solve.  Its
- * results for the n = 70..90 classes are parity unpinned beyond that: they
- * rest on the same code being right at larger n.
+ * partition the solve.  At the sizes of its golden values
+ * (tests/test_oracle_mitm_large.py: n = 70, 80, 90, two key rows, a modulus
+ * above every left key so that a class is one pair of left row sums) its H
+ * equals the product of the two halves' subset counts by row sums (a
+ * dynamic programme in the test), up to 7e12 hits per class, and the
+ * planted vector is among the class's solutions.  Key rows 3 and 4, which
+ * most n >= 70 golden values add, are pinned at the smaller sizes above.
  *
  * Every entry point returns 0 on success or a negative code:
  *   -1 invalid argument, -2 row sum exceeds 65534, -3 key overflows int64,
