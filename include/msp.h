@@ -93,7 +93,7 @@ typedef struct {
                                  2 = every one of the |G_L||G_R| pairs compared on its
                                  own (1-D hits verified one by one); 0 = planner's
                                  choice: the hash join when the expected equal-key
-                                 group holds >= 16 records per side.  Same H, |S| and
+                                 group holds >= 32 records per side.  Same H, |S| and
                                  solutions; no effect when every row is a key row   */
     int32_t  key_base;        /* radix of the surrogate key (Section 1, eq. surrogate):
                                  0 = B = n*D for every key row (D = max(100, max a_ij

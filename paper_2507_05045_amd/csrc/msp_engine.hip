@@ -373,7 +373,11 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
     if (o.first_order < 0 || o.first_order > 1) return MSP_E_INVALID;
     if (o.verify_join == 1) p.vjoin = 1;
     else if (o.verify_join == 2) p.vjoin = 0;
-    else p.vjoin = expected_group_lg2(c, p) >= 4.0 ? 1 : 0;
+    // Planner's choice: the pairwise walk of a group costs about one compare
+    // per left record against the vector join's fixed probe, and is still
+    // the faster at groups of ~23 records ((9,80) with four key rows); from
+    // 32 records per group the vector join decides the runs.
+    else p.vjoin = expected_group_lg2(c, p) >= 5.0 ? 1 : 0;
     if (p.W == 0) p.vjoin = 0;
     const uint64_t T = (uint64_t)1 << log2T;
     if (o.slice_mod > 0) {

@@ -201,8 +201,16 @@ def test_plan_picks_the_vector_join_for_large_equal_key_groups():
     small = msp.Context(make_instance(8, 70, 0).A, make_instance(8, 70, 0).d)
     assert small.plan(key_rows=4)["vector_join"] == 0
     assert small.plan(key_rows=4, verify_join=1)["vector_join"] == 1
+    # (9,80): groups of ~23 records, still walked pair by pair; (10,90):
+    # hundreds, decided by the vector join.
+    mid = msp.Context(make_instance(9, 80, 0).A, make_instance(9, 80, 0).d)
+    assert mid.plan(key_rows=4)["vector_join"] == 0
+    wide = msp.Context(make_instance(10, 90, 0).A, make_instance(10, 90, 0).d)
+    assert wide.plan(key_rows=4)["vector_join"] == 1
     big.close()
     small.close()
+    mid.close()
+    wide.close()
 
 
 def test_set_allocator_rejects_half_a_pair():
