@@ -71,7 +71,9 @@ typedef struct {
     int64_t  slice_mod;       /* 0 = full solve; else a power of two (see above)        */
     int64_t  slice_res;       /* residue kept by the slice, 0 <= slice_res < slice_mod  */
     uint64_t max_solutions;   /* solution vectors kept on the device; 0 = 1<<20         */
-    uint64_t window_records;  /* half records per side per window; 0 = planner's choice */
+    uint64_t window_records;  /* half records per side per window, and the least the
+                                 record buffers hold (for a class far denser than
+                                 the average cell); 0 = planner's choice          */
     void    *workspace;       /* caller-owned device buffer, or NULL (library allocates)*/
     uint64_t workspace_bytes; /* size of `workspace`; with NULL workspace: budget, 0=auto*/
     void    *stream;          /* hipStream_t to run on, or NULL (library's own stream)  */

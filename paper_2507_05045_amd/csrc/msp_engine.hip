@@ -484,8 +484,12 @@ int prepare(const msp_ctx *c, const msp_opts &o, uint64_t budget, Prepared &P) {
         z.o_rows = take(P.rows.size() * 2);
         return off;
     };
+    // The caller's window_records is also a floor on the buffers: a window
+    // of one cell can still hold a class far denser than the average cell.
     auto cap_for = [&](uint64_t kw) {
-        return std::min<uint64_t>(hard_cap, std::min<uint64_t>(all_rec, kw * per_cell + 1024));
+        return std::min<uint64_t>(
+            hard_cap, std::min<uint64_t>(all_rec, std::max<uint64_t>(kw * per_cell + 1024,
+                                                                     o.window_records)));
     };
     uint64_t cap_rec = cap_for(kwin);
     uint64_t total = layout(cap_rec, kwin);

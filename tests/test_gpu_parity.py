@@ -648,3 +648,35 @@ def test_bucket_of_2_32_records_is_refused():
     inst = make_instance(4, 30, 0, planted=True)
     g = gsolve(inst.A, inst.d, key_rows=1)
     assert any(np.array_equal(s_, inst.planted) for s_ in g.solutions)
+
+
+def test_9_80_two_row_class_against_half_counts():
+    """x*'s residue class of the (9,80) planted twin with key rows 1-2 and a
+    slice modulus above every left key: the class is one pair of left row
+    sums (s1, s2), so its H is N_L(s1, s2) * N_R(d1 - s1, d2 - s2), the
+    halves' subset counts by row sums from a numpy DP (no oracle): about
+    7e12 1-D hits in one equal-key run pair of millions of records per
+    side, a class far denser than the average cell (the record buffers are
+    sized by window_records).  S is compared with the oracle's, with every
+    hit checked pair by pair and with the vector join."""
+    from half_counts import half_counts
+    inst = make_instance(9, 80, 0, planted=True)
+    A64, d = inst.A.astype(np.int64), inst.d.astype(np.int64)
+    hl = 40
+    NL = half_counts(A64[0, :hl], A64[1, :hl])
+    NR = half_counts(A64[0, hl:], A64[1, hl:])
+    base = O.key_setup(inst.A, inst.d, 2)[0]
+    lm = int(NL.shape[0] - 1 + (NL.shape[1] - 1) * base).bit_length()
+    x = inst.planted
+    s1, s2 = int(A64[0, :hl] @ x[:hl]), int(A64[1, :hl] @ x[:hl])
+    rho = s1 + s2 * base
+    nl, nr = int(NL[s1, s2]), int(NR[d[0] - s1, d[1] - s2])
+    ref = O.mitm(inst.A, inst.d, 2, lm, rho, rho + 1)
+    assert ref.H == nl * nr and ref.H > 10 ** 12
+    wr = 1 << max(nl, nr).bit_length()
+    for vj in (2, 1):
+        say("(9,80) key rows 1-2, class", rho, "mod 2^%d" % lm, "sides", nl, nr,
+            "verify_join", vj)
+        g = gsolve(inst.A, inst.d, key_rows=2, slice_mod=1 << lm, slice_res=rho,
+                   verify_join=vj, window_records=wr)
+        same(g, ref, f"(9,80) key rows 1-2, x*'s class, verify_join={vj}")

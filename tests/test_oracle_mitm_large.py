@@ -22,21 +22,11 @@ import itertools
 import numpy as np
 import pytest
 
+from half_counts import half_counts
 from oracle import oracle as O
 from paper_2507_05045_amd.inputs import make_instance
 
 pytestmark = pytest.mark.slow
-
-
-def half_counts(a1, a2):
-    """N[s1, s2] = #{subsets T of the columns : sum a1[T] = s1, sum a2[T] = s2}."""
-    a1, a2 = np.asarray(a1, dtype=np.int64), np.asarray(a2, dtype=np.int64)
-    S1, S2 = int(a1.sum()), int(a2.sum())
-    N = np.zeros((S1 + 1, S2 + 1), dtype=np.int64)
-    N[0, 0] = 1
-    for x, y in zip(a1.tolist(), a2.tolist()):
-        N[x:, y:] += N[:S1 + 1 - x, :S2 + 1 - y].copy()
-    return N
 
 
 def test_half_counts_is_the_subset_count():
