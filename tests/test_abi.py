@@ -267,3 +267,20 @@ def test_tiny_instances_plan(n):
     p = ctx.plan(key_rows=1)
     assert p["log2_outer"] + p["log2_inner"] == (n + 1) // 2 and p["workspace_bytes"] > 0
     ctx.close()
+
+
+def test_window_records_is_a_floor_on_the_record_buffers():
+    """A one-cell window (a slice finer than the cells) is sized for the
+    average cell; window_records raises its buffers for a denser class."""
+    from paper_2507_05045_amd import msp
+    from paper_2507_05045_amd.inputs import make_instance
+    inst = make_instance(9, 80, 0, planted=True)
+    ctx = msp.Context(inst.A, inst.d)
+    kw = dict(key_rows=2, slice_mod=1 << 24, slice_res=12345)
+    base = ctx.plan(**kw)
+    assert base["windows"] == 1 and base["cells_per_window"] == 1
+    assert base["window_records"] < 1 << 20
+    big = ctx.plan(**kw, window_records=1 << 22)
+    assert big["windows"] == 1 and big["window_records"] == 1 << 22
+    assert big["workspace_bytes"] > base["workspace_bytes"] + 2 * 12 * ((1 << 22) - (1 << 20))
+    ctx.close()
