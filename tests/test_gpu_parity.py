@@ -680,3 +680,37 @@ def test_9_80_two_row_class_against_half_counts():
         g = gsolve(inst.A, inst.d, key_rows=2, slice_mod=1 << lm, slice_res=rho,
                    verify_join=vj, window_records=wr)
         same(g, ref, f"(9,80) key rows 1-2, x*'s class, verify_join={vj}")
+
+
+def test_10_90_two_row_class_against_half_counts():
+    """The largest class of (10,90) seed 0 under key rows 1-2 with at most a
+    million vectors per side (a modulus above every left key): H against the
+    per-half counting DP, S against the oracle, both run checks."""
+    from half_counts import half_counts
+    inst = make_instance(10, 90, 0)
+    A64, d = inst.A.astype(np.int64), inst.d.astype(np.int64)
+    hl = 45
+    NL = half_counts(A64[0, :hl], A64[1, :hl])
+    NR = half_counts(A64[0, hl:], A64[1, hl:])
+    base = O.key_setup(inst.A, inst.d, 2)[0]
+    lm = int(NL.shape[0] - 1 + (NL.shape[1] - 1) * base).bit_length()
+    # NRd[s1, s2] = N_R(d1 - s1, d2 - s2) where defined
+    NRd = np.zeros_like(NL)
+    r1 = int(d[0]) - np.arange(NL.shape[0])
+    r2 = int(d[1]) - np.arange(NL.shape[1])
+    ok1, ok2 = (r1 >= 0) & (r1 < NR.shape[0]), (r2 >= 0) & (r2 < NR.shape[1])
+    NRd[np.ix_(ok1, ok2)] = NR[np.ix_(r1[ok1], r2[ok2])]
+    prod = np.where((NL <= 10 ** 6) & (NRd <= 10 ** 6), NL * NRd, 0)
+    s1, s2 = (int(v) for v in np.unravel_index(np.argmax(prod), prod.shape))
+    nl, nr = int(NL[s1, s2]), int(NRd[s1, s2])
+    assert nl * nr > 10 ** 11
+    rho = s1 + s2 * base
+    ref = O.mitm(inst.A, inst.d, 2, lm, rho, rho + 1)
+    assert ref.H == nl * nr
+    wr = 1 << max(nl, nr).bit_length()
+    for vj in (2, 1):
+        say("(10,90) key rows 1-2, class", rho, "mod 2^%d" % lm, "sides", nl, nr,
+            "verify_join", vj)
+        g = gsolve(inst.A, inst.d, key_rows=2, slice_mod=1 << lm, slice_res=rho,
+                   verify_join=vj, window_records=wr)
+        same(g, ref, f"(10,90) key rows 1-2, class {rho}, verify_join={vj}")
