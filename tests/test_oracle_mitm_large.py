@@ -41,6 +41,20 @@ def test_half_counts_is_the_subset_count():
     assert N.sum() == 2 ** 12
 
 
+def test_half_counts_equals_the_oracle_two_row_dp():
+    """The test's DP and the oracle's 2-row counting DP, written apart,
+    agree on the (6,50) matrix's first two rows over all 50 columns."""
+    inst = make_instance(6, 50, 0)
+    a1, a2 = inst.A[0].astype(np.int64), inst.A[1].astype(np.int64)
+    N = half_counts(a1, a2)
+    rng = np.random.default_rng(5)
+    targets = [(int(a1.sum()) // 2, int(a2.sum()) // 2), (0, 0), (int(a1.sum()), int(a2.sum()))]
+    targets += [(int(rng.integers(0, N.shape[0])), int(rng.integers(0, N.shape[1])))
+                for _ in range(6)]
+    for t1, t2 in targets:
+        assert int(N[t1, t2]) == O.dp_count2(a1, a2, t1, t2), (t1, t2)
+
+
 def _class_counts(inst):
     A, d = inst.A.astype(np.int64), inst.d.astype(np.int64)
     hl = (A.shape[1] + 1) // 2
